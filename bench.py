@@ -1,0 +1,170 @@
+#!/usr/bin/env python3
+"""Throughput of the LSKUM residual sweep on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 1m]
+
+A step is one pseudo-time iteration of the whole hot path over the cloud:
+the local time step, then four SSP Runge-Kutta stages, each of
+q-variables -> least-squares q-derivatives (first-order + inner sweeps)
+-> limited split-flux residual -> stage update, plus the device-side
+residual norm.  Inputs are synthetic (seeded airfoil point cloud) and
+resident in HBM before timing starts.  The value is point-stage updates per
+second (points x 4 stages x steps / seconds).
+
+Besides the throughput the JSON line carries:
+* roofline: the flux kernel (the dominant one) -- algorithmic FP64
+  operations per launch divided by its mean launch time, measured with HIP
+  events around every flux launch in the timed region, against the MI355X
+  FP64 vector peak;
+* cpu_baseline: the FP64 oracle timed on this host on a bounded sample
+  (one stage over the whole cloud, single thread).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "point-RK-stage updates/s FP64 at 1M/16M pts; adjoint/forward time ratio"
+FP64_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(cloud, wl, U_host):
+    """The oracle, as it stands, on one full RK stage of the workload."""
+    from oracle.ref import Oracle
+
+    o = Oracle(cloud, wl.mach, wl.aoa_deg, cfl=wl.cfl, venkat_k=wl.venkat_k,
+               n_inner=wl.n_inner, gamma=wl.gamma)
+    t0 = time.perf_counter()
+    q, _ = o.q_vars(U_host)
+    dq, qlim = o.q_derivs(q)
+    R, _ = o.flux_residual(q, dq, qlim)
+    dt = o.local_dt(U_host)
+    o.rk_stage(0, U_host, R, dt, U_host)
+    sec = time.perf_counter() - t0
+    return {"value": cloud.n / sec, "unit": "point-stage updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one RK stage (q-variables, first-order + {wl.n_inner} inner LS sweeps, "
+                      f"flux residual, local time step, stage update) over all {cloud.n} points "
+                      f"of the {wl.name} cloud, single thread, {sec:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed iterations (default: the workload's)")
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="1m")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the sweep is not "
+              "sharded across GPUs in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from cloudgen.workloads import WORKLOADS
+    from paper_2403_13287_amd import costs
+    from paper_2403_13287_amd import lskum as L
+
+    wl = WORKLOADS[args.workload]
+    steps = wl.iters if args.steps is None else args.steps
+    warm = args.warmup
+    torch.cuda.set_device(0)
+    log(f"[bench] generating the {wl.name} cloud ({wl.W} x {wl.L})")
+    cloud = wl.cloud()
+    n = cloud.n
+    edges = int(cloud.nbr_count.astype(np.int64).sum())
+    p = L.Params(wl.mach, wl.aoa_deg, wl.cfl, wl.venkat_k, wl.n_inner, wl.gamma)
+    plan = L.Plan(cloud, p)
+    U = plan.field(4)
+    L.lskum_init_state(plan, U)
+    U0_host = U.cpu().numpy()
+    Un, q, dq, qlim, work, R = (plan.field(c) for c in (4, 4, 8, 8, 8, 4))
+    dt = plan.field(1)
+    hist = torch.zeros(max(steps + warm, 1), dtype=torch.float64, device="cuda")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(4 * steps)]
+
+    def step(k, timed):
+        L.lskum_local_dt(plan, U, dt)
+        Un.copy_(U)
+        for s in range(4):
+            L.lskum_q_vars(plan, U, q)
+            L.lskum_q_derivs(plan, q, dq, qlim, work)
+            if timed:
+                ev[4 * (k - warm) + s][0].record()
+            L.lskum_flux_residual(plan, q, dq, qlim, R)
+            if timed:
+                ev[4 * (k - warm) + s][1].record()
+            if s == 0:
+                L.lskum_residual_norm(plan, R, hist[k:k + 1])
+            L.lskum_rk_stage(plan, s, Un, R, dt, U)
+
+    log(f"[bench] n={n} edges={edges} warmup={warm} steps={steps}")
+    for k in range(warm):
+        step(k, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(warm, warm + steps):
+        step(k, True)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    status = L.lskum_status(plan)
+    h = hist.cpu().numpy()
+    flux_ms = float(np.mean([a.elapsed_time(b) for a, b in ev])) if ev else float("nan")
+    log(f"[bench] {sec:.3f} s, flux mean {flux_ms:.4f} ms, status {status}, "
+        f"hist first {h[0]:.6e} last {h[warm + steps - 1]:.6e}")
+
+    value = n * 4.0 * steps / sec
+    flops = costs.flux_flops(n, edges)
+    achieved = flops / (flux_ms * 1e-3) / 1e12
+    stage_gb = costs.stage_bytes(n, cloud.k_pad, wl.n_inner) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "point-stage updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": sec * 1e3 / max(steps, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: NACA 0012 O-type airfoil cloud {wl.W} x {wl.L}, "
+                               f"k_max {wl.k_max}, M {wl.mach}, AoA {wl.aoa_deg} deg, "
+                               f"n_inner {wl.n_inner}, CFL {wl.cfl}, Venkatakrishnan K {wl.venkat_k}",
+                   "points": n, "edges": edges, "k_pad": cloud.k_pad, "iterations": steps,
+                   "stages_per_iteration": 4},
+        "roofline": {"bound": "alu", "kernel": "k_flux", "achieved": achieved,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": None, "flops_per_launch": flops, "avg_launch_ms": flux_ms},
+        "hbm_compulsory": {"GB_per_stage": stage_gb,
+                           "achieved_GBs": stage_gb * 4 * steps / sec,
+                           "frac": stage_gb * 4 * steps / sec / HBM_PEAK_GBS},
+        "status": L.strerror(status),
+        "residual_history": {"first": float(h[0]), "last": float(h[warm + steps - 1])},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on one stage")
+        out["cpu_baseline"] = cpu_baseline(cloud, wl, U0_host)
+    print(json.dumps(out), flush=True)
+    return 0 if status == L.OK and np.all(np.isfinite(h[:warm + steps])) else 1
+
+
+if __name__ == "__main__":
+    sys.exit(main())

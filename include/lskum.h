@@ -1,0 +1,159 @@
+/* lskum.h -- C ABI of the MI355X (gfx950) LSKUM residual sweep library.
+ *
+ * Least-squares kinetic upwind method (LSKUM) for the 2D Euler equations on
+ * a point cloud, arXiv 2403.13287 ("Theory of Meshfree LSKUM"): q-variables
+ * (eq. (13)), least-squares q-derivatives with inner iterations (eq. (14),
+ * (15)), limited reconstruction of the modified q-variables, kinetic split
+ * fluxes on half-plane stencils (eq. (10)-(12)), the flux residual, the
+ * local time step and a four-stage Runge-Kutta state update built from the
+ * forward-Euler update of eq. (16).
+ *
+ * Conventions
+ * -----------
+ * - Every field array passed to a sweep call is a DEVICE pointer (for
+ *   example torch.cuda tensor storage) in structure-of-arrays,
+ *   component-major layout: a field with c components over n points is
+ *   f[c*n + i].  FP64 throughout.
+ *     U    [4][n]  conserved (rho, rho u, rho v, E)
+ *     q    [4][n]  q-variables of eq. (13)
+ *     dq   [8][n]  rows 0..3 dq_m/dx, rows 4..7 dq_m/dy
+ *     qlim [8][n]  rows 0..3 max of q_m over {i} U N(i), rows 4..7 min
+ *     R    [4][n]  flux residual, dU/dt = -R (x/y momentum)
+ *     dt   [n]     local time step
+ * - The caller owns every field buffer; the library never frees caller
+ *   memory.  The plan owns the device copies of the geometry and the
+ *   connectivity, allocated in lskum_plan_create and freed in
+ *   lskum_plan_destroy.
+ * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   Sweep calls are asynchronous on that stream; they return LSKUM_OK once
+ *   the work is enqueued, or a negative status for invalid arguments or a
+ *   failed launch.  Non-physical states met inside kernels are recorded in a
+ *   device status word and reported by lskum_status().
+ * - Calls on one plan must not run concurrently on different streams: they
+ *   share the plan's status word and reduction scratch.
+ * - No C++ exception crosses this interface.
+ */
+#ifndef LSKUM_H
+#define LSKUM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LSKUM_OK = 0,
+  LSKUM_ERR_INVALID_ARG = -1, /* null pointer, bad size or stage index   */
+  LSKUM_ERR_BAD_CLOUD = -2,   /* connectivity fails validation           */
+  LSKUM_ERR_HIP = -3,         /* a HIP runtime call or launch failed     */
+  LSKUM_ERR_NONPHYSICAL = -4, /* rho, p or beta <= 0 or non-finite met   */
+  LSKUM_ERR_NO_MEMORY = -5,   /* device allocation failed                */
+  LSKUM_ERR_DEGENERATE = -6   /* a used half-plane stencil is singular   */
+} lskum_status_t;
+
+/* Point cloud, HOST pointers, read only inside lskum_plan_create. */
+typedef struct {
+  int32_t n;                 /* number of points, >= 1                          */
+  int32_t k_pad;             /* padded row width (columns stored per row)       */
+  const double *x, *y;       /* [n] coordinates                                 */
+  const double *nx, *ny;     /* [n] unit normal; tangent t = (ny, -nx).  Wall:  */
+                             /*     into the fluid; outer: outward; interior:   */
+                             /*     the frame of the split stencils             */
+  const int8_t *kind;        /* [n] 0 interior, 1 wall, 2 outer (Dirichlet)     */
+  const int64_t *row_ptr;    /* [n+1] row i = col[row_ptr[i] .. row_ptr[i+1])   */
+  const int32_t *col;        /* neighbour ids, ascending distance, padded       */
+  const int32_t *nbr_count;  /* [n] real neighbours in row i (first entries)    */
+  const int32_t *wall_loop;  /* [n_wall] wall ids, counter-clockwise            */
+  int32_t n_wall;
+} lskum_cloud;
+
+/* Flow and scheme settings. */
+typedef struct {
+  double gamma;     /* ratio of specific heats (1.4)                            */
+  double mach;      /* free-stream Mach number; free stream is rho = 1,         */
+                    /* p = 1/gamma, velocity = M (cos aoa, sin aoa)             */
+  double aoa_rad;   /* angle of attack                                          */
+  double cfl;       /* CFL number of the local time step                        */
+  double venkat_k;  /* limiter constant K, eps^2 = (K |d_i|)^3                  */
+  int32_t n_inner;  /* Jacobi inner sweeps after the first-order LS solve, >= 0 */
+  int32_t reserved; /* must be 0                                                */
+} lskum_params;
+
+typedef struct lskum_plan_s *lskum_plan;
+
+/* Build a plan on the current HIP device: validates the cloud (ids in
+ * range, no self links among the real neighbours, counts within the row,
+ * k_pad equal to every row's length) and uploads coordinates, normals,
+ * kinds and a column-major copy of the connectivity.  Returns
+ * LSKUM_ERR_BAD_CLOUD on a validation failure, LSKUM_ERR_NO_MEMORY or
+ * LSKUM_ERR_HIP on device failures; *out is NULL unless LSKUM_OK. */
+int lskum_plan_create(lskum_plan *out, const lskum_cloud *cloud, const lskum_params *params,
+                      void *stream);
+int lskum_plan_destroy(lskum_plan plan);
+/* Replace the flow/scheme settings of an existing plan (same cloud). */
+int lskum_plan_set_params(lskum_plan plan, const lskum_params *params);
+int32_t lskum_plan_n(lskum_plan plan);
+
+/* Free stream with the wall tangency projection applied at wall points. */
+int lskum_init_state(lskum_plan plan, double *U, void *stream);
+
+/* eq. (13): q-variables from the conserved state at every point. */
+int lskum_q_vars(lskum_plan plan, const double *U, double *q, void *stream);
+
+/* Least-squares q-derivatives (eq. (9) with dq_i = q_i - q_0, then
+ * params.n_inner Jacobi sweeps of eq. (14)-(15)) and the stencil bounds
+ * qlim.  `work` is an [8][n] scratch buffer; the final iterate is in dq. */
+int lskum_q_derivs(lskum_plan plan, const double *q, double *dq, double *qlim, double *work,
+                   void *stream);
+
+/* Flux residual: the sum of the split-flux derivatives of eq. (10), each
+ * from eq. (11) on its half-plane stencil of the point's (s, n) frame, with
+ * differences of split fluxes of the limited modified q-variables of
+ * eq. (14).  Interior points use G_s+-, G_n+-; wall points G_s+-, G_n-;
+ * outer points get R = 0. */
+int lskum_flux_residual(lskum_plan plan, const double *q, const double *dq, const double *qlim,
+                        double *R, void *stream);
+
+/* Local time step: dt_i = CFL * min_j |d_ij| / (|u_j| + 3 sqrt(p_j/rho_j)). */
+int lskum_local_dt(lskum_plan plan, const double *U, double *dt, void *stream);
+
+/* Stage `stage` (0..3) of the SSP Runge-Kutta (4,3) scheme with L = -R:
+ * U <- a Un + b (U - dt/2 R), (a, b) = (0, 1) except stage 2: (2/3, 1/3);
+ * then wall points drop normal momentum and outer points are reset to the
+ * free stream.  U holds the previous stage on entry. */
+int lskum_rk_stage(lskum_plan plan, int stage, const double *Un, const double *R,
+                   const double *dt, double *U, void *stream);
+
+/* Deterministic L2 norm of the density residual over interior and wall
+ * points, written to out[0] (device). */
+int lskum_residual_norm(lskum_plan plan, const double *R, double *out, void *stream);
+
+/* Lift and drag coefficients from the wall polygon (trapezoidal pressure
+ * per edge, chord 1), written to clcd[0..1] (device). */
+int lskum_force_coeffs(lskum_plan plan, const double *U, double *clcd, void *stream);
+
+/* Bytes of device workspace lskum_iterate needs for this plan. */
+size_t lskum_workspace_bytes(lskum_plan plan);
+
+/* Advance U by `iters` iterations (each: local time step from U^n, then four
+ * stages of q_vars -> q_derivs -> flux_residual -> rk_stage).  hist[k]
+ * (device, may be NULL) receives the residual norm of iteration k's first
+ * stage.  `ws` is a device buffer of lskum_workspace_bytes(plan) bytes,
+ * 256-byte aligned. */
+int lskum_iterate(lskum_plan plan, int32_t iters, double *U, double *hist, void *ws,
+                  void *stream);
+
+/* Synchronises `stream`, then returns LSKUM_ERR_NONPHYSICAL or
+ * LSKUM_ERR_DEGENERATE if a kernel has recorded one since the last clear,
+ * else LSKUM_OK (or LSKUM_ERR_HIP). */
+int lskum_status(lskum_plan plan, void *stream);
+int lskum_clear_status(lskum_plan plan, void *stream);
+
+const char *lskum_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSKUM_H */

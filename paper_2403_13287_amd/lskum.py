@@ -1,0 +1,268 @@
+"""Python binding of ``liblskum.so`` (argument marshalling only).
+
+Every sweep function has the name of its C entry point in ``include/lskum.h``
+and takes torch tensors: FP64, contiguous, on the plan's GPU, shaped (c, n)
+for a c-component field (component-major, exactly the C layout).  The work
+runs in the library's HIP kernels on the current torch stream (or the
+stream passed in); nothing is computed in Python.  A missing library is an
+error: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _build
+
+OK = 0
+ERR_INVALID_ARG = -1
+ERR_BAD_CLOUD = -2
+ERR_HIP = -3
+ERR_NONPHYSICAL = -4
+ERR_NO_MEMORY = -5
+ERR_DEGENERATE = -6
+
+
+class LskumError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+class _Cloud(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("k_pad", ctypes.c_int32),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("nx", ctypes.c_void_p), ("ny", ctypes.c_void_p),
+                ("kind", ctypes.c_void_p), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("nbr_count", ctypes.c_void_p),
+                ("wall_loop", ctypes.c_void_p), ("n_wall", ctypes.c_int32)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("mach", ctypes.c_double),
+                ("aoa_rad", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("venkat_k", ctypes.c_double), ("n_inner", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+# name -> (restype, argtypes); 'v' = void*, 'i' = int32, 'd' = double
+_SIGS = {
+    "lskum_plan_create": (ctypes.c_int, "vvvv"),
+    "lskum_plan_destroy": (ctypes.c_int, "v"),
+    "lskum_plan_set_params": (ctypes.c_int, "vv"),
+    "lskum_plan_n": (ctypes.c_int32, "v"),
+    "lskum_init_state": (ctypes.c_int, "vvv"),
+    "lskum_q_vars": (ctypes.c_int, "vvvv"),
+    "lskum_q_derivs": (ctypes.c_int, "vvvvvv"),
+    "lskum_flux_residual": (ctypes.c_int, "vvvvvv"),
+    "lskum_local_dt": (ctypes.c_int, "vvvv"),
+    "lskum_rk_stage": (ctypes.c_int, "vivvvvv"),
+    "lskum_residual_norm": (ctypes.c_int, "vvvv"),
+    "lskum_force_coeffs": (ctypes.c_int, "vvvv"),
+    "lskum_workspace_bytes": (ctypes.c_size_t, "v"),
+    "lskum_iterate": (ctypes.c_int, "vivvvv"),
+    "lskum_status": (ctypes.c_int, "vv"),
+    "lskum_clear_status": (ctypes.c_int, "vv"),
+    "lskum_strerror": (ctypes.c_char_p, "i"),
+}
+_CT = {"v": ctypes.c_void_p, "i": ctypes.c_int32, "d": ctypes.c_double}
+
+_lib = None
+
+
+def library_path() -> str:
+    return _build.LIB
+
+
+def load() -> ctypes.CDLL:
+    """Load the in-tree HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with python -m paper_2403_13287_amd._build")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = [_CT[a] for a in args]
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load().lskum_strerror(int(code)).decode()
+
+
+def _check(rc: int, where: str):
+    if rc != OK:
+        raise LskumError(rc, where)
+
+
+def _stream(stream):
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+@dataclass
+class Params:
+    mach: float
+    aoa_deg: float
+    cfl: float = 0.2
+    venkat_k: float = 5.0
+    n_inner: int = 2
+    gamma: float = 1.4
+
+    def c(self) -> _Params:
+        return _Params(self.gamma, self.mach, math.radians(self.aoa_deg), self.cfl,
+                       self.venkat_k, int(self.n_inner), 0)
+
+
+class Plan:
+    """Owner of an ``lskum_plan`` handle (device geometry + connectivity)."""
+
+    def __init__(self, cloud, params: Params, stream=None):
+        self.lib = load()
+        self.n = int(cloud.x.shape[0])
+        self.params = params
+        self.device = torch.cuda.current_device()
+        k_pad = int(getattr(cloud, "k_pad", 0)) or int(cloud.col.size // self.n)
+        keep = dict(
+            x=np.ascontiguousarray(cloud.x, np.float64), y=np.ascontiguousarray(cloud.y, np.float64),
+            nx=np.ascontiguousarray(cloud.nx, np.float64), ny=np.ascontiguousarray(cloud.ny, np.float64),
+            kind=np.ascontiguousarray(cloud.kind, np.int8),
+            row_ptr=np.ascontiguousarray(cloud.row_ptr, np.int64),
+            col=np.ascontiguousarray(cloud.col, np.int32),
+            nbr_count=np.ascontiguousarray(cloud.nbr_count, np.int32),
+            wall_loop=np.ascontiguousarray(cloud.wall_loop, np.int32))
+        c = _Cloud(self.n, k_pad, *(keep[k].ctypes.data for k in
+                                    ("x", "y", "nx", "ny", "kind", "row_ptr", "col", "nbr_count",
+                                     "wall_loop")), int(keep["wall_loop"].size))
+        h = ctypes.c_void_p()
+        p = params.c()
+        rc = self.lib.lskum_plan_create(ctypes.byref(h), ctypes.byref(c), ctypes.byref(p),
+                                        _stream(stream))
+        _check(rc, "lskum_plan_create")
+        self.handle = h
+
+    def set_params(self, params: Params):
+        p = params.c()
+        _check(self.lib.lskum_plan_set_params(self.handle, ctypes.byref(p)), "lskum_plan_set_params")
+        self.params = params
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            self.lib.lskum_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    # tensor helpers (allocation is torch's; the library never allocates fields)
+    def field(self, comps: int) -> torch.Tensor:
+        shape = (comps, self.n) if comps > 1 else (self.n,)
+        return torch.empty(shape, dtype=torch.float64, device=f"cuda:{self.device}")
+
+    def _arg(self, t: torch.Tensor, comps: int, name: str) -> int:
+        shape = (comps, self.n) if comps > 1 else (self.n,)
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda \
+                or t.device.index != self.device or not t.is_contiguous() or tuple(t.shape) != shape:
+            raise ValueError(f"{name}: need a contiguous float64 cuda:{self.device} tensor of shape {shape}")
+        return t.data_ptr()
+
+
+def plan_create(cloud, params: Params, stream=None) -> Plan:
+    return Plan(cloud, params, stream)
+
+
+def lskum_init_state(plan: Plan, U, stream=None):
+    _check(plan.lib.lskum_init_state(plan.handle, plan._arg(U, 4, "U"), _stream(stream)),
+           "lskum_init_state")
+
+
+def lskum_q_vars(plan: Plan, U, q, stream=None):
+    _check(plan.lib.lskum_q_vars(plan.handle, plan._arg(U, 4, "U"), plan._arg(q, 4, "q"),
+                                 _stream(stream)), "lskum_q_vars")
+
+
+def lskum_q_derivs(plan: Plan, q, dq, qlim, work, stream=None):
+    _check(plan.lib.lskum_q_derivs(plan.handle, plan._arg(q, 4, "q"), plan._arg(dq, 8, "dq"),
+                                   plan._arg(qlim, 8, "qlim"), plan._arg(work, 8, "work"),
+                                   _stream(stream)), "lskum_q_derivs")
+
+
+def lskum_flux_residual(plan: Plan, q, dq, qlim, R, stream=None):
+    _check(plan.lib.lskum_flux_residual(plan.handle, plan._arg(q, 4, "q"), plan._arg(dq, 8, "dq"),
+                                        plan._arg(qlim, 8, "qlim"), plan._arg(R, 4, "R"),
+                                        _stream(stream)), "lskum_flux_residual")
+
+
+def lskum_local_dt(plan: Plan, U, dt, stream=None):
+    _check(plan.lib.lskum_local_dt(plan.handle, plan._arg(U, 4, "U"), plan._arg(dt, 1, "dt"),
+                                   _stream(stream)), "lskum_local_dt")
+
+
+def lskum_rk_stage(plan: Plan, stage: int, Un, R, dt, U, stream=None):
+    _check(plan.lib.lskum_rk_stage(plan.handle, int(stage), plan._arg(Un, 4, "Un"),
+                                   plan._arg(R, 4, "R"), plan._arg(dt, 1, "dt"),
+                                   plan._arg(U, 4, "U"), _stream(stream)), "lskum_rk_stage")
+
+
+def _scalar_out(plan: Plan, t, count: int, name: str) -> int:
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda \
+            or t.device.index != plan.device or not t.is_contiguous() or t.numel() < count:
+        raise ValueError(f"{name}: need a float64 cuda tensor with >= {count} elements")
+    return t.data_ptr()
+
+
+def lskum_residual_norm(plan: Plan, R, out, stream=None):
+    _check(plan.lib.lskum_residual_norm(plan.handle, plan._arg(R, 4, "R"),
+                                        _scalar_out(plan, out, 1, "out"), _stream(stream)),
+           "lskum_residual_norm")
+
+
+def lskum_force_coeffs(plan: Plan, U, clcd, stream=None):
+    _check(plan.lib.lskum_force_coeffs(plan.handle, plan._arg(U, 4, "U"),
+                                       _scalar_out(plan, clcd, 2, "clcd"), _stream(stream)),
+           "lskum_force_coeffs")
+
+
+def lskum_workspace_bytes(plan: Plan) -> int:
+    return int(plan.lib.lskum_workspace_bytes(plan.handle))
+
+
+def workspace(plan: Plan) -> torch.Tensor:
+    ws = torch.empty(lskum_workspace_bytes(plan), dtype=torch.uint8, device=f"cuda:{plan.device}")
+    if ws.data_ptr() % 256:
+        raise RuntimeError("workspace not 256-byte aligned")
+    return ws
+
+
+def lskum_iterate(plan: Plan, iters: int, U, hist, ws, stream=None):
+    hp = 0 if hist is None else _scalar_out(plan, hist, int(iters), "hist")
+    if not isinstance(ws, torch.Tensor) or not ws.is_cuda or ws.numel() < lskum_workspace_bytes(plan):
+        raise ValueError("ws: need a cuda tensor of lskum_workspace_bytes(plan) bytes")
+    _check(plan.lib.lskum_iterate(plan.handle, int(iters), plan._arg(U, 4, "U"), hp, ws.data_ptr(),
+                                  _stream(stream)), "lskum_iterate")
+
+
+def lskum_status(plan: Plan, stream=None) -> int:
+    """Synchronising status query; returns the status code (0, or
+    ERR_NONPHYSICAL / ERR_DEGENERATE)."""
+    return int(plan.lib.lskum_status(plan.handle, _stream(stream)))
+
+
+def lskum_clear_status(plan: Plan, stream=None):
+    _check(plan.lib.lskum_clear_status(plan.handle, _stream(stream)), "lskum_clear_status")
