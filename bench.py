@@ -66,7 +66,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="1m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="instead of the sweep, run 5 plain device copies of this many bytes "
+                         "(calibrates the HBM traffic counters)")
     args = ap.parse_args()
+    if args.copy_bytes:
+        import torch
+        torch.cuda.set_device(0)
+        src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 8, "copies": 5}), flush=True)
+        return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the sweep is not "
               "sharded across GPUs in this build", file=sys.stderr)
