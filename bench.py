@@ -104,7 +104,7 @@ def main():
     plan = L.Plan(cloud, p)
     U = plan.field(4)
     L.lskum_init_state(plan, U)
-    U0_host = U.cpu().numpy()
+    U0_host = U.cpu().numpy().T.copy()  # oracle layout (4, n)
     Un, q, dq, qlim, work, R = (plan.field(c) for c in (4, 4, 8, 8, 8, 4))
     dt = plan.field(1)
     hist = torch.zeros(max(steps + warm, 1), dtype=torch.float64, device="cuda")

@@ -11,14 +11,16 @@
  * Conventions
  * -----------
  * - Every field array passed to a sweep call is a DEVICE pointer (for
- *   example torch.cuda tensor storage) in structure-of-arrays,
- *   component-major layout: a field with c components over n points is
- *   f[c*n + i].  FP64 throughout.
- *     U    [4][n]  conserved (rho, rho u, rho v, E)
- *     q    [4][n]  q-variables of eq. (13)
- *     dq   [8][n]  rows 0..3 dq_m/dx, rows 4..7 dq_m/dy
- *     qlim [8][n]  rows 0..3 max of q_m over {i} U N(i), rows 4..7 min
- *     R    [4][n]  flux residual, dU/dt = -R (x/y momentum)
+ *   example torch.cuda tensor storage) in point-major layout: a field with
+ *   c components over n points is f[i*c + m] (one contiguous record per
+ *   point, so a neighbour's values come in one cache line).  FP64
+ *   throughout.  4-component fields must be 32-byte aligned, 8-component
+ *   fields 64-byte aligned (LSKUM_ERR_INVALID_ARG otherwise).
+ *     U    [n][4]  conserved (rho, rho u, rho v, E)
+ *     q    [n][4]  q-variables of eq. (13)
+ *     dq   [n][8]  0..3 dq_m/dx, 4..7 dq_m/dy
+ *     qlim [n][8]  0..3 max of q_m over {i} U N(i), 4..7 min
+ *     R    [n][4]  flux residual, dU/dt = -R (x/y momentum)
  *     dt   [n]     local time step
  * - The caller owns every field buffer; the library never frees caller
  *   memory.  The plan owns the device copies of the geometry and the
@@ -104,7 +106,7 @@ int lskum_q_vars(lskum_plan plan, const double *U, double *q, void *stream);
 
 /* Least-squares q-derivatives (eq. (9) with dq_i = q_i - q_0, then
  * params.n_inner Jacobi sweeps of eq. (14)-(15)) and the stencil bounds
- * qlim.  `work` is an [8][n] scratch buffer; the final iterate is in dq. */
+ * qlim.  `work` is an [n][8] scratch buffer; the final iterate is in dq. */
 int lskum_q_derivs(lskum_plan plan, const double *q, double *dq, double *qlim, double *work,
                    void *stream);
 

@@ -1,8 +1,8 @@
 """Python binding of ``liblskum.so`` (argument marshalling only).
 
 Every sweep function has the name of its C entry point in ``include/lskum.h``
-and takes torch tensors: FP64, contiguous, on the plan's GPU, shaped (c, n)
-for a c-component field (component-major, exactly the C layout).  The work
+and takes torch tensors: FP64, contiguous, on the plan's GPU, shaped (n, c)
+for a c-component field (point-major, exactly the C layout).  The work
 runs in the library's HIP kernels on the current torch stream (or the
 stream passed in); nothing is computed in Python.  A missing library is an
 error: there is no fallback.
@@ -172,11 +172,11 @@ class Plan:
 
     # tensor helpers (allocation is torch's; the library never allocates fields)
     def field(self, comps: int) -> torch.Tensor:
-        shape = (comps, self.n) if comps > 1 else (self.n,)
+        shape = (self.n, comps) if comps > 1 else (self.n,)
         return torch.empty(shape, dtype=torch.float64, device=f"cuda:{self.device}")
 
     def _arg(self, t: torch.Tensor, comps: int, name: str) -> int:
-        shape = (comps, self.n) if comps > 1 else (self.n,)
+        shape = (self.n, comps) if comps > 1 else (self.n,)
         if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda \
                 or t.device.index != self.device or not t.is_contiguous() or tuple(t.shape) != shape:
             raise ValueError(f"{name}: need a contiguous float64 cuda:{self.device} tensor of shape {shape}")

@@ -44,6 +44,16 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
+def up(a):
+    """Oracle field (c, n) -> device field (n, c)."""
+    return to_gpu(np.asarray(a).T)
+
+
+def down(t):
+    """Device field (n, c) -> oracle layout (c, n)."""
+    return host(t).T
+
+
 def normwise(gpu, ref_):
     gpu = np.atleast_2d(gpu)
     ref_ = np.atleast_2d(ref_)
@@ -89,21 +99,21 @@ def test_per_kernel_parity_tiny(tiny):
         o = oracle_of(cloud, p)
         U, _, _ = o.iterate(o.init_state(), 3)
         plan = L.Plan(cloud, p)
-        Ug = to_gpu(U)
+        Ug = up(U)
         q, dq, qlim, work, R = plan.field(4), plan.field(8), plan.field(8), plan.field(8), plan.field(4)
         L.lskum_q_vars(plan, Ug, q)
         qo, _ = o.q_vars(U)
-        assert_field("q", host(q), qo)
+        assert_field("q", down(q), qo)
         # derivatives from the oracle's own q: isolates the derivative kernels
-        L.lskum_q_derivs(plan, to_gpu(qo), dq, qlim, work)
+        L.lskum_q_derivs(plan, up(qo), dq, qlim, work)
         dqo, qlimo = o.q_derivs(qo)
-        assert_field("dq", host(dq), dqo)
-        assert_field("qlim", host(qlim), qlimo, 1e-15)
+        assert_field("dq", down(dq), dqo)
+        assert_field("qlim", down(qlim), qlimo, 1e-15)
         # flux kernel from the oracle's inputs
-        L.lskum_flux_residual(plan, to_gpu(qo), to_gpu(dqo), to_gpu(qlimo), R)
+        L.lskum_flux_residual(plan, up(qo), up(dqo), up(qlimo), R)
         Ro, flags = o.flux_residual(qo, dqo, qlimo)
         assert flags == 0
-        assert_field("R", host(R), Ro)
+        assert_field("R", down(R), Ro)
         assert L.lskum_status(plan) == L.OK
         plan.destroy()
 
@@ -114,7 +124,7 @@ def test_small_kernels_parity_tiny(tiny):
     o = oracle_of(cloud, p)
     U, _, _ = o.iterate(o.init_state(), 3)
     plan = L.Plan(cloud, p)
-    Ug = to_gpu(U)
+    Ug = up(U)
     dt = plan.field(1)
     L.lskum_local_dt(plan, Ug, dt)
     dto = o.local_dt(U)
@@ -123,17 +133,17 @@ def test_small_kernels_parity_tiny(tiny):
     R = rng.normal(size=(4, cloud.n)) * 0.1
     Un = U * (1 + 1e-3 * rng.normal(size=U.shape))
     for s in range(4):
-        Ug = to_gpu(U)
-        L.lskum_rk_stage(plan, s, to_gpu(Un), to_gpu(R), to_gpu(dto), Ug)
-        np.testing.assert_allclose(host(Ug), o.rk_stage(s, Un, R, dto, U), rtol=1e-13, atol=1e-15)
+        Ug = up(U)
+        L.lskum_rk_stage(plan, s, up(Un), up(R), to_gpu(dto), Ug)
+        np.testing.assert_allclose(down(Ug), o.rk_stage(s, Un, R, dto, U), rtol=1e-13, atol=1e-15)
     out = torch.zeros(2, dtype=torch.float64, device="cuda")
-    L.lskum_residual_norm(plan, to_gpu(R), out)
+    L.lskum_residual_norm(plan, up(R), out)
     assert host(out)[0] == pytest.approx(o.residual_norm(R), rel=1e-12)
-    L.lskum_force_coeffs(plan, to_gpu(U), out)
+    L.lskum_force_coeffs(plan, up(U), out)
     np.testing.assert_allclose(host(out), o.force_coeffs(U), rtol=1e-11, atol=1e-14)
     Ui = plan.field(4)
     L.lskum_init_state(plan, Ui)
-    np.testing.assert_allclose(host(Ui), o.init_state(), rtol=4e-16, atol=1e-16)
+    np.testing.assert_allclose(down(Ui), o.init_state(), rtol=4e-16, atol=1e-16)
 
 
 def _gpu_stages(plan, Ug, iters):
@@ -154,8 +164,8 @@ def _gpu_stages(plan, Ug, iters):
                 L.lskum_residual_norm(plan, R, norm)
                 nv = float(host(norm)[0])
             L.lskum_rk_stage(plan, s, Un, R, dt, Ug)
-            yield dict(it=it, stage=s, q=host(q), dq=host(dq), qlim=host(qlim), R=host(R),
-                       dt=host(dt), U=host(Ug), norm=nv)
+            yield dict(it=it, stage=s, q=down(q), dq=down(dq), qlim=down(qlim), R=down(R),
+                       dt=host(dt), U=down(Ug), norm=nv)
 
 
 def _compare_stage(a, b, tag):
@@ -173,14 +183,14 @@ def test_stage_parity_first_two_and_last_iteration_tiny(tiny):
     plan = L.Plan(cloud, p)
     U0 = o.init_state()
     say("stage parity: first two iterations")
-    for a, b in zip(_gpu_stages(plan, to_gpu(U0), 2), o.stages(U0, 2)):
+    for a, b in zip(_gpu_stages(plan, up(U0), 2), o.stages(U0, 2)):
         _compare_stage(a, b, "first")
     # full run of wl.iters iterations: histories and the last iteration stage by stage
     say(f"full run: {wl.iters} iterations, oracle and lskum_iterate")
     last = wl.iters - 1
     Uo, hist_o, flags = o.iterate(U0, last)
     assert flags == 0
-    Ug = to_gpu(U0)
+    Ug = up(U0)
     hist_g = torch.zeros(last, dtype=torch.float64, device="cuda")
     ws = L.workspace(plan)
     L.lskum_iterate(plan, last, Ug, hist_g, ws)
@@ -188,7 +198,7 @@ def test_stage_parity_first_two_and_last_iteration_tiny(tiny):
     ok = hist_o / hist_o[0] >= 1e-6
     np.testing.assert_allclose(hg[ok], hist_o[ok], rtol=HIST_TOL)
     assert np.all(np.abs(hg[~ok] - hist_o[~ok]) <= 1e-14 * hist_o[0])
-    assert_field("U before last iteration", host(Ug), Uo)
+    assert_field("U before last iteration", down(Ug), Uo)
     say("stage parity: last iteration")
     for a, b in zip(_gpu_stages(plan, Ug, 1), o.stages(Uo, 1)):
         _compare_stage(a, b, "last")
@@ -215,7 +225,7 @@ def test_parity_1m_bench_configuration():
     s = Solver(cloud, p)
     say("5 GPU iterations at 1M")
     s.run(5)
-    U5 = host(s.U)
+    U5 = down(s.U)
     q, dq, qlim, R = s.residual()
     o = oracle_of(cloud, p)
     say("oracle residual at 1M")
@@ -223,14 +233,14 @@ def test_parity_1m_bench_configuration():
     dqo, qlimo = o.q_derivs(qo)
     Ro, flags = o.flux_residual(qo, dqo, qlimo)
     assert flags == 0
-    assert_field("q 1M", host(q), qo)
-    assert_field("dq 1M", host(dq), dqo)
-    assert_field("R 1M", host(R), Ro)
+    assert_field("q 1M", down(q), qo)
+    assert_field("dq 1M", down(dq), dqo)
+    assert_field("R 1M", down(R), Ro)
     # the next iteration's history entry is the norm of R(U5)
     h = s.run(1)
     assert float(host(h)[0]) == pytest.approx(o.residual_norm(Ro), rel=HIST_TOL)
     dt = s.plan.field(1)
-    L.lskum_local_dt(s.plan, to_gpu(U5), dt)
+    L.lskum_local_dt(s.plan, up(U5), dt)
     np.testing.assert_allclose(host(dt), o.local_dt(U5), rtol=1e-12)
     assert s.status() == L.OK
 
@@ -252,10 +262,10 @@ def test_small_and_ragged_clouds_with_garbage_padding(M, Lr):
     s = Solver(cg, p)
     hg = s.run(4)
     np.testing.assert_allclose(host(hg), ho, rtol=HIST_TOL)
-    assert_field("U cylinder", host(s.U), Uo)
+    assert_field("U cylinder", down(s.U), Uo)
     _, _, _, R = s.residual()
     Ro, _ = o.residual(Uo)
-    assert_field("R cylinder", host(R), Ro)
+    assert_field("R cylinder", down(R), Ro)
 
 
 def test_nonphysical_state_sets_status(tiny):
@@ -264,7 +274,7 @@ def test_nonphysical_state_sets_status(tiny):
     U = plan.field(4)
     L.lskum_init_state(plan, U)
     assert L.lskum_status(plan) == L.OK
-    U[3, 77] = 0.0  # E = 0 -> p < 0
+    U[77, 3] = 0.0  # E = 0 -> p < 0
     q = plan.field(4)
     L.lskum_q_vars(plan, U, q)
     assert L.lskum_status(plan) == L.ERR_NONPHYSICAL
@@ -283,9 +293,9 @@ def test_degenerate_stencil_sets_status():
     U = o.init_state()
     U[0, 3] *= 1.1
     q, dq, qlim, work, R = plan.field(4), plan.field(8), plan.field(8), plan.field(8), plan.field(4)
-    L.lskum_q_vars(plan, to_gpu(U), q)
+    L.lskum_q_vars(plan, up(U), q)
     L.lskum_q_derivs(plan, q, dq, qlim, work)
     L.lskum_flux_residual(plan, q, dq, qlim, R)
     assert L.lskum_status(plan) == L.ERR_DEGENERATE
     Ro, flags = o.residual(U)
-    assert_field("R degenerate", host(R), Ro)
+    assert_field("R degenerate", down(R), Ro)
