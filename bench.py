@@ -40,23 +40,86 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cloud, wl, U_host):
-    """The oracle, as it stands, on one full RK stage of the workload."""
+def cpu_baseline(cloud, wl, U_host, min_seconds: float = 10.0):
+    """The oracle, as it stands, on whole RK stages of the workload: repeated
+    until at least `min_seconds` of single-thread CPU work (one stage over
+    the 1M cloud takes about 4 s)."""
     from oracle.ref import Oracle
 
     o = Oracle(cloud, wl.mach, wl.aoa_deg, cfl=wl.cfl, venkat_k=wl.venkat_k,
                n_inner=wl.n_inner, gamma=wl.gamma)
+    U = U_host.copy()
+    Un = U_host.copy()
+    dt = None
+    stages = 0
     t0 = time.perf_counter()
-    q, _ = o.q_vars(U_host)
-    dq, qlim = o.q_derivs(q)
-    R, _ = o.flux_residual(q, dq, qlim)
-    dt = o.local_dt(U_host)
-    o.rk_stage(0, U_host, R, dt, U_host)
-    sec = time.perf_counter() - t0
-    return {"value": cloud.n / sec, "unit": "point-stage updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"one RK stage (q-variables, first-order + {wl.n_inner} inner LS sweeps, "
-                      f"flux residual, local time step, stage update) over all {cloud.n} points "
-                      f"of the {wl.name} cloud, single thread, {sec:.1f} s"}
+    while True:
+        if stages % 4 == 0:
+            dt = o.local_dt(U)
+            Un = U.copy()
+        q, _ = o.q_vars(U)
+        dq, qlim = o.q_derivs(q)
+        R, _ = o.flux_residual(q, dq, qlim)
+        U = o.rk_stage(stages % 4, Un, R, dt, U)
+        stages += 1
+        sec = time.perf_counter() - t0
+        if sec >= min_seconds:
+            break
+    return {"value": cloud.n * stages / sec, "unit": "point-stage updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{stages} RK stages (local time step per 4 stages, q-variables, first-order "
+                      f"+ {wl.n_inner} inner LS sweeps, flux residual, stage update) over all "
+                      f"{cloud.n} points of the {wl.name} cloud from the initial state, single "
+                      f"thread, {sec:.1f} s"}
+
+
+ELEMENTARY_RANGES = {
+    # fn id: (name, low, high) -- argument ranges met in the flux kernel
+    0: ("copy", 0.1, 3.0),
+    1: ("exp", -6.0, 1.0),     # exp(-S^2), exp(q1 + beta |u|^2)
+    2: ("erf", -2.5, 2.5),     # S = u_d sqrt(beta)
+    3: ("log", 0.3, 3.0),
+    4: ("sqrt", 1e-8, 1e-2),   # edge length squared
+    5: ("rsqrt", 0.3, 3.0),    # beta
+    6: ("divide", 0.1, 3.0),
+}
+
+
+def calibrate_elementary(n: int = 1 << 24) -> int:
+    """One launch per elementary function over n seeded inputs."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    from paper_2403_13287_amd import _build
+
+    torch.cuda.set_device(0)
+    lib = ctypes.CDLL(_build.CALIB_LIB)
+    lib.lskum_calib_elementary.restype = ctypes.c_int
+    lib.lskum_calib_elementary.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    rng = np.random.Generator(np.random.PCG64(17))
+    y = torch.from_numpy(rng.uniform(-2.0, 2.0, n)).cuda()
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    # first pass: inputs in random order; second pass: sorted, so every
+    # wavefront sees a narrow argument range (no divergence between the
+    # branches of piecewise implementations)
+    for order in ("random", "sorted"):
+        for fn, (name, lo, hi) in ELEMENTARY_RANGES.items():
+            xs = rng.uniform(lo, hi, n)
+            if order == "sorted":
+                xs = np.sort(xs)
+            x = torch.from_numpy(xs).cuda()
+            rc = lib.lskum_calib_elementary(fn, n, x.data_ptr(), y.data_ptr(), out.data_ptr(),
+                                            stream)
+            if rc != 0:
+                raise RuntimeError(f"calibration kernel {name} failed ({rc})")
+            torch.cuda.synchronize()
+    print(json.dumps({"calibrate_elementary": {str(k): v[0] for k, v in ELEMENTARY_RANGES.items()},
+                      "elements": n}), flush=True)
+    return 0
 
 
 def main():
@@ -69,7 +132,12 @@ def main():
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of the sweep, run 5 plain device copies of this many bytes "
                          "(calibrates the HBM traffic counters)")
+    ap.add_argument("--calibrate-elementary", action="store_true",
+                    help="instead of the sweep, run the FP64 elementary-function calibration "
+                         "kernels once each over 2^24 inputs (profile with rocprofv3 --pmc)")
     args = ap.parse_args()
+    if args.calibrate_elementary:
+        return calibrate_elementary()
     if args.copy_bytes:
         import torch
         torch.cuda.set_device(0)

@@ -14,6 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblskum.so")
+CALIB_LIB = os.path.join(HERE, "calib", "libelementary.so")
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -28,14 +29,21 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
-def build(verbose: bool = False, extra=()) -> str:
+def _hipcc(srcs, out, extra=(), verbose=False):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, *extra, "-I", os.path.join(ROOT, "include"), *sources(), "-o", tmp]
+    tmp = out + ".tmp"
+    cmd = [hipcc, *HIPCC_FLAGS, *extra, "-I", os.path.join(ROOT, "include"), *srcs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose: bool = False, extra=()) -> str:
+    """The sweep library, then the calibration kernels of the roofline report."""
+    _hipcc(sources(), LIB, extra, verbose)
+    _hipcc([os.path.join(HERE, "calib", "elementary.hip")], CALIB_LIB, extra, verbose)
     return LIB
 
 

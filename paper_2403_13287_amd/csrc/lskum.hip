@@ -31,8 +31,12 @@
 #include <vector>
 
 #include "lskum.h"
+#include "lskum_math.h"
 
 namespace {
+
+using lskum_math::lk_div;
+using lskum_math::lk_rsqrt;
 
 constexpr int kBlock = 256;
 constexpr int kXcds = 8;
@@ -156,6 +160,21 @@ __device__ __forceinline__ bool in_tile(int j, int lo, int &lj) {
   return (unsigned)lj < (unsigned)kBlock;
 }
 
+// Reader of point i's neighbour row (column-major connectivity).  Slots at
+// or past the row's count read the last real slot and return i itself, so
+// prefetching ahead never leaves the row: gather loops fetch the index two
+// neighbours ahead and the neighbour's records one ahead, which keeps two
+// dependent memory round trips off each iteration.
+struct Row {
+  const int32_t *col;  // &nbr[i], stride n
+  int n, c, i;
+  __device__ __forceinline__ int operator()(int k) const {
+    const int kk = k < c ? k : c - 1;
+    const int j = col[(size_t)kk * n];
+    return k < c ? j : i;
+  }
+};
+
 // ---------------------------------------------------------------------------
 // least-squares q-derivatives
 
@@ -186,11 +205,9 @@ __global__ void __launch_bounds__(kBlock) k_deriv_first(Geo G, const double *__r
   }
   double sxx = 0.0, sxy = 0.0, syy = 0.0;
   const int c = G.cnt[i];
-  for (int k = 0; k < c; ++k) {
-    const int j = G.nbr[(size_t)k * n + i];
+  const Row row{G.nbr + i, n, c, i};
+  auto fetch = [&](int j, double2 &xj, F4 &qj) {
     int lj;
-    double2 xj;
-    F4 qj;
     if (in_tile(j, lo, lj)) {
       xj = s_xy[lj];
       qj = s_q[lj];
@@ -198,6 +215,16 @@ __global__ void __launch_bounds__(kBlock) k_deriv_first(Geo G, const double *__r
       xj = G.xy[j];
       qj = ld4(q, j);
     }
+  };
+  int j_next = row(1);
+  double2 xj;
+  F4 qj;
+  fetch(row(0), xj, qj);
+  for (int k = 0; k < c; ++k) {
+    const int j_after = row(k + 2);
+    double2 xn;
+    F4 qn;
+    fetch(j_next, xn, qn);
     const double dx = xj.x - xi.x, dy = xj.y - xi.y;
     sxx += dx * dx;
     sxy += dx * dy;
@@ -209,6 +236,9 @@ __global__ void __launch_bounds__(kBlock) k_deriv_first(Geo G, const double *__r
       qmax[m] = fmax(qmax[m], qj.v[m]);
       qmin[m] = fmin(qmin[m], qj.v[m]);
     }
+    xj = xn;
+    qj = qn;
+    j_next = j_after;
   }
   const double det = sxx * syy - sxy * sxy;
   F8 g, lim;
@@ -250,12 +280,9 @@ __global__ void __launch_bounds__(kBlock) k_deriv_inner(Geo G, const double *__r
   double sxq[4] = {0, 0, 0, 0}, syq[4] = {0, 0, 0, 0};
   double sxx = 0.0, sxy = 0.0, syy = 0.0;
   const int c = G.cnt[i];
-  for (int k = 0; k < c; ++k) {
-    const int j = G.nbr[(size_t)k * n + i];
+  const Row row{G.nbr + i, n, c, i};
+  auto fetch = [&](int j, double2 &xj, F4 &qj, F8 &gj) {
     int lj;
-    double2 xj;
-    F4 qj;
-    F8 gj;
     if (in_tile(j, lo, lj)) {
       xj = s_xy[lj];
       qj = s_q[lj];
@@ -265,6 +292,18 @@ __global__ void __launch_bounds__(kBlock) k_deriv_inner(Geo G, const double *__r
       qj = ld4(q, j);
       gj = ld8(dqp, j);
     }
+  };
+  int j_next = row(1);
+  double2 xj;
+  F4 qj;
+  F8 gj;
+  fetch(row(0), xj, qj, gj);
+  for (int k = 0; k < c; ++k) {
+    const int j_after = row(k + 2);
+    double2 xn;
+    F4 qn;
+    F8 gn;
+    fetch(j_next, xn, qn, gn);
     const double dx = xj.x - xi.x, dy = xj.y - xi.y;
     sxx += dx * dx;
     sxy += dx * dy;
@@ -276,6 +315,10 @@ __global__ void __launch_bounds__(kBlock) k_deriv_inner(Geo G, const double *__r
       sxq[m] += dx * d;
       syq[m] += dy * d;
     }
+    xj = xn;
+    qj = qn;
+    gj = gn;
+    j_next = j_after;
   }
   const double det = sxx * syy - sxy * sxy;
   F8 g;
@@ -298,7 +341,7 @@ __device__ __forceinline__ double limited(double delta, double room_max, double 
   const double D = delta > 0.0 ? room_max : room_min;
   const double num = D * D + eps2 + 2.0 * delta * D;
   const double den = D * D + 2.0 * delta * delta + delta * D + eps2;
-  const double phi = delta == 0.0 ? 1.0 : fmin(1.0, num / den);
+  const double phi = delta == 0.0 ? 1.0 : fmin(1.0, lk_div(num, den));
   return phi * delta;
 }
 
@@ -317,7 +360,7 @@ __device__ __forceinline__ unsigned end_state(const double qt[4], const Flow &P,
                                               double ty, double nx, double ny, EndState &s) {
   constexpr double kHalfRsqrtPi = 0.28209479177387814347;  // 1 / (2 sqrt(pi))
   const double beta = -0.5 * qt[3];
-  const double rsb = rsqrt(beta);
+  const double rsb = lk_rsqrt(beta);
   const double ib = rsb * rsb;
   const double inv2b = 0.5 * ib;
   const double u = qt[1] * inv2b;
@@ -411,14 +454,21 @@ __global__ void __launch_bounds__(kBlock) k_flux(Geo G, Flow P, const double *__
   const double2 nv = G.nrm[i];
   const double nx = nv.x, ny = nv.y, tx = ny, ty = -nx;
   const int c = G.cnt[i];
+  const Row row{G.nbr + i, n, c, i};
+  auto fetch_xy = [&](int j) {
+    int lj;
+    return in_tile(j, lo, lj) ? s_xy[lj] : G.xy[j];
+  };
 
   // pass 1: geometry of the four half-plane stencils
   double sss[4] = {0, 0, 0, 0}, ssn[4] = {0, 0, 0, 0}, snn[4] = {0, 0, 0, 0};
   int cnt[4] = {0, 0, 0, 0};
+  {
+  int j_next = row(1);
+  double2 xj = fetch_xy(row(0));
   for (int k = 0; k < c; ++k) {
-    const int j = G.nbr[(size_t)k * n + i];
-    int lj;
-    const double2 xj = in_tile(j, lo, lj) ? s_xy[lj] : G.xy[j];
+    const int j_after = row(k + 2);
+    const double2 xn = fetch_xy(j_next);
     const double dx = xj.x - xi.x, dy = xj.y - xi.y;
     const double ds = dot_rn(dx, tx, dy, ty);
     const double dn = dot_rn(dx, nx, dy, ny);
@@ -430,6 +480,9 @@ __global__ void __launch_bounds__(kBlock) k_flux(Geo G, Flow P, const double *__
       snn[h] += w * (dn * dn);
       cnt[h] += in[h] ? 1 : 0;
     }
+    xj = xn;
+    j_next = j_after;
+  }
   }
   unsigned f = 0;
   SplitW W[4];
@@ -449,28 +502,33 @@ __global__ void __launch_bounds__(kBlock) k_flux(Geo G, Flow P, const double *__
   const double K = P.venkat_k;
   double acc[4] = {0, 0, 0, 0};  // (mass, s-momentum, n-momentum, energy)
 
-  // pass 2: limited modified q at both ends, split fluxes, weighted sums
+  // pass 2: limited modified q at both ends, split fluxes, weighted sums.
+  // The index and coordinates are prefetched ahead; the neighbour's larger
+  // records are loaded at the top of the iteration, while the own end's
+  // reconstruction (which needs only the coordinates) proceeds.
+  int j_next = row(1);
+  int j_cur = row(0);
+  double2 xj = fetch_xy(j_cur);
   for (int k = 0; k < c; ++k) {
-    const int j = G.nbr[(size_t)k * n + i];
+    const int j_after = row(k + 2);
+    const double2 xn = fetch_xy(j_next);
     int lj;
-    double2 xj;
     F4 qj;
     F8 gj, lj8;
-    if (in_tile(j, lo, lj)) {
-      xj = s_xy[lj];
+    if (in_tile(j_cur, lo, lj)) {
       qj = s_q[lj];
       gj = s_g[lj];
       lj8 = s_l[lj];
     } else {
-      xj = G.xy[j];
-      qj = ld4(q, j);
-      gj = ld8(dq, j);
-      lj8 = ld8(qlim, j);
+      qj = ld4(q, j_cur);
+      gj = ld8(dq, j_cur);
+      lj8 = ld8(qlim, j_cur);
     }
     const double dx = xj.x - xi.x, dy = xj.y - xi.y;
     const double ds = dot_rn(dx, tx, dy, ty);
     const double dn = dot_rn(dx, nx, dy, ny);
-    const double kd = K * sqrt(dx * dx + dy * dy);
+    const double d2 = dx * dx + dy * dy;
+    const double kd = K * (d2 > 0.0 ? d2 * lk_rsqrt(d2) : 0.0);
     const double eps2 = kd * kd * kd;
     double qtj[4], qt0[4];
     for (int m = 0; m < 4; ++m) {
@@ -512,6 +570,9 @@ __global__ void __launch_bounds__(kBlock) k_flux(Geo G, Flow P, const double *__
       acc[2] += wt * (Gj[1] - G0[1]);
       acc[3] += wt * (Gj[3] - G0[3]);
     }
+    xj = xn;
+    j_cur = j_next;
+    j_next = j_after;
   }
   F4 r;
   r.v[0] = acc[0];
@@ -533,14 +594,23 @@ __global__ void __launch_bounds__(kBlock) k_local_dt(Geo G, Flow P, const double
   const double2 xi = G.xy[i];
   double best = INFINITY;
   const int c = G.cnt[i];
+  const Row row{G.nbr + i, n, c, i};
+  int j_next = row(1);
+  int j = row(0);
+  double2 xj = G.xy[j];
+  F4 Uj = ld4(U, j);
   for (int k = 0; k < c; ++k) {
-    const int j = G.nbr[(size_t)k * n + i];
-    const double2 xj = G.xy[j];
+    const int j_after = row(k + 2);
+    const double2 xn = G.xy[j_next];
+    const F4 Un = ld4(U, j_next);
     const double dx = xj.x - xi.x, dy = xj.y - xi.y;
     double rho, u, v, p;
-    prim_from_cons(P.gamma, ld4(U, j), rho, u, v, p);
+    prim_from_cons(P.gamma, Uj, rho, u, v, p);
     const double speed = sqrt(u * u + v * v) + 3.0 * sqrt(p / rho);
     best = fmin(best, sqrt(dx * dx + dy * dy) / speed);
+    xj = xn;
+    Uj = Un;
+    j_next = j_after;
   }
   dt[i] = P.cfl * best;
 }

@@ -76,7 +76,8 @@ _lib = None
 
 
 def library_path() -> str:
-    return _build.LIB
+    """The in-tree library, or LSKUM_LIBRARY if set (an alternative build)."""
+    return os.environ.get("LSKUM_LIBRARY", _build.LIB)
 
 
 def load() -> ctypes.CDLL:
