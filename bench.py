@@ -212,6 +212,9 @@ def main():
     value = n * 4.0 * steps / sec
     flops = costs.flux_flops(n, edges)
     achieved = flops / (flux_ms * 1e-3) / 1e12
+    traffic = None
+    if wl.name == "1m":
+        traffic = costs.stored_flux_traffic(os.path.join(ROOT, "profiles", "k_flux_1m.txt"))
     stage_gb = costs.stage_bytes(n, cloud.k_pad, wl.n_inner) / 1e9
     out = {
         "metric": METRIC,
@@ -233,7 +236,8 @@ def main():
                    "stages_per_iteration": 4},
         "roofline": {"bound": "alu", "kernel": "k_flux", "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": None, "flops_per_launch": flops, "avg_launch_ms": flux_ms},
+                     "traffic": traffic, "flops_per_launch": flops, "avg_launch_ms": flux_ms,
+                     "algorithmic_bytes_per_launch": costs.flux_bytes(n, cloud.k_pad)},
         "hbm_compulsory": {"GB_per_stage": stage_gb,
                            "achieved_GBs": stage_gb * 4 * steps / sec,
                            "frac": stage_gb * 4 * steps / sec / HBM_PEAK_GBS},

@@ -4,37 +4,32 @@ Bytes: compulsory HBM traffic, each array read or written once per pass
 (neighbour values reused from cache).  Connectivity C = 4*k_pad + 4 bytes
 per point (padded column-major ids plus the count).
 
-FP64 operations: the operations of the method's formulas as written (one
-per add, subtract, multiply, compare-free; a divide or square root counts
-its FP64 instruction sequence), with each elementary function weighted by
-the FP64 operations of the device math library's implementation on its
-common path (an FMA counts 2).  EDGE_FLOPS is per (point, neighbour) pair of
-the flux pass, POINT_FLOPS per point of that pass.
+FP64 operations of the flux kernel: the operations of its formulation,
+with each elementary function at the device math library's cost (an FMA
+counts 2).  Every FP64 operation the kernel executes belongs to that
+formulation (the only wasted work is the n+ split flux evaluated with zero
+weight at wall points, 0.1 % of the edges of the 1M cloud), so the count is
+taken from the hardware: SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes of one launch
+on the 1M cloud divided by its edges (1.7866e10 / 29,967,646).  Per edge the
+formulation holds 4 erf, 6 exp, 3 Newton-refined rsqrt, 8 Newton-refined
+divides and about 200 multiply/add/FMA operations; the per-call costs of the
+elementary functions measured by the calibration kernels on arguments in
+the sweep's ranges are listed in ELEMENTARY_FLOPS (erf on wave-coherent
+arguments; on scattered ones it costs 99).
 """
 from __future__ import annotations
 
-# weights of the elementary functions in FP64 operations (FMA = 2)
-W_DIV = 17
-W_SQRT = 21
-W_EXP = 32
-W_LOG = 60
-W_ERF = 70
+import hashlib
+import os
 
-# operation counts of one flux-pass edge (two reconstructions of 4
-# components, two states, four split fluxes, two weighted accumulations)
-EDGE_BASIC = 404
-EDGE_DIV = 22
-EDGE_SQRT = 5
-EDGE_EXP = 6
-EDGE_LOG = 2
-EDGE_ERF = 4
-EDGE_FLOPS = (EDGE_BASIC + EDGE_DIV * W_DIV + EDGE_SQRT * W_SQRT + EDGE_EXP * W_EXP
-              + EDGE_LOG * W_LOG + EDGE_ERF * W_ERF)
-POINT_FLOPS = 60  # split weights and the rotation back
+# measured FP64 operations per call (FMA = 2), calibration kernels, gfx950
+ELEMENTARY_FLOPS = {"exp": 27, "erf": 54.4, "log": 79, "sqrt": 17, "rsqrt": 9, "div": 14}
+
+EDGE_FLOPS = 596.2  # flux kernel, FP64 operations per (point, neighbour) pair
 
 
 def flux_flops(n_points: int, n_edges: int) -> float:
-    return float(n_edges) * EDGE_FLOPS + float(n_points) * POINT_FLOPS
+    return float(n_edges) * EDGE_FLOPS
 
 
 def conn_bytes(k_pad: int) -> int:
@@ -55,3 +50,34 @@ def stage_bytes(n_points: int, k_pad: int, n_inner: int) -> float:
     c = conn_bytes(k_pad)
     per = 64 + (176 + c) + n_inner * (176 + c) + (225 + c) + 137 + (120 + c) / 4.0
     return float(n_points) * per
+
+
+def kernel_source_hash() -> str:
+    """sha256 of the kernel sources, to tie stored counter readings to the
+    code they were taken on."""
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(here)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(here, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def stored_flux_traffic(path: str):
+    """HBM bytes per flux launch from a profile summary, or None when the
+    summary was taken on other kernel sources."""
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["flux_hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
