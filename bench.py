@@ -122,6 +122,84 @@ def calibrate_elementary(n: int = 1 << 24) -> int:
     return 0
 
 
+def bench_batch(args) -> int:
+    """64 uneven airfoil clouds advanced together (one graph launch per
+    replay, autotuned tile size and XCD mapping) against the same 64 clouds
+    advanced one after the other (each with its own graph)."""
+    import numpy as np
+    import torch
+
+    from cloudgen import batch_sizes, make_airfoil_cloud
+    from paper_2403_13287_amd import lskum as L
+    from paper_2403_13287_amd.solver import Solver
+
+    torch.cuda.set_device(0)
+    iters = 500 if args.steps is None else args.steps
+    per_graph = 25 if iters % 25 == 0 else 1
+    replays = iters // per_graph
+    draws = batch_sizes()
+    log(f"[bench] generating {len(draws)} clouds")
+    clouds = [make_airfoil_cloud(d["W"], d["L"], 25, d["seed"]) for d in draws]
+    params = [L.Params(d["mach"], d["aoa_deg"], 0.2, 5.0, 2) for d in draws]
+    total = sum(c.n for c in clouds)
+    log(f"[bench] {total} points in {len(clouds)} clouds ({min(c.n for c in clouds)}-"
+        f"{max(c.n for c in clouds)}), {iters} iterations")
+
+    batch = Solver(clouds, params)
+    best, tune_ms = L.autotune(batch.plan, batch.U, batch.ws, iters=2, reps=2)
+    log(f"[bench] autotuned: {best} from {tune_ms}")
+    graph, hist = batch.capture(per_graph, replays)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(replays):
+        graph.launch()
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    status = batch.status()
+
+    t_loop = 0.0
+    loop_status = L.OK
+    for c, (cloud, p) in enumerate(zip(clouds, params)):
+        s = Solver(cloud, p)
+        g, h = s.capture(per_graph, replays)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(replays):
+            g.launch()
+        torch.cuda.synchronize()
+        t_loop += time.perf_counter() - t0
+        loop_status = loop_status or s.status()
+        if not torch.equal(s.U, batch.cloud_state(c)):
+            log(f"[bench] cloud {c}: batched and single states differ")
+            loop_status = L.ERR_INVALID_ARG
+        del g, s
+    value = total * 4.0 * iters / t_batch
+    out = {
+        "metric": "batched point-RK-stage updates/s FP64, 64 uneven airfoil clouds",
+        "value": value,
+        "unit": "point-stage updates/s",
+        "n_gpus": 1,
+        "steps": iters,
+        "higher_is_better": True,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "batch: 64 NACA 0012 clouds, 5k-250k points log-uniform, "
+                               "M U[0.3, 0.9], AoA U[-4, 6] deg, k_max 25, n_inner 2, CFL 0.2",
+                   "points": total, "clouds": len(clouds), "iterations_per_graph": per_graph},
+        "batch_seconds": t_batch,
+        "loop_seconds": t_loop,
+        "loop_value": total * 4.0 * iters / t_loop,
+        "speedup_vs_loop": t_loop / t_batch,
+        "tuning": {"block": best.block, "xcd_contiguous": best.xcd_contiguous},
+        "autotune_ms_per_2_iterations": {f"{k[0]}/{k[1]}": v for k, v in tune_ms.items()},
+        "status": L.strerror(status),
+        "loop_status": L.strerror(loop_status),
+        "residual_last": float(np.nanmax(hist[-1].cpu().numpy())),
+    }
+    print(json.dumps(out), flush=True)
+    return 0 if status == L.OK and loop_status == L.OK else 1
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +230,8 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the sweep is not "
               "sharded across GPUs in this build", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        return bench_batch(args)
 
     import numpy as np
     import torch

@@ -83,7 +83,17 @@ typedef struct {
   int32_t reserved; /* must be 0                                                */
 } lskum_params;
 
+/* Launch tuning of a plan: the block size (= points per LDS tile of the
+ * gather kernels) and whether blocks are relabelled so that each of the 8
+ * XCDs walks one contiguous range of points (its L2 then holds that range's
+ * neighbours).  Results do not depend on the tuning. */
+typedef struct {
+  int32_t block;          /* 128, 256 or 512 (0: 256)                         */
+  int32_t xcd_contiguous; /* 1 (default): XCD-contiguous ranges; 0: round-robin */
+} lskum_tuning;
+
 typedef struct lskum_plan_s *lskum_plan;
+typedef struct lskum_graph_s *lskum_graph;
 
 /* Build a plan on the current HIP device: validates the cloud (ids in
  * range, no self links among the real neighbours, counts within the row,
@@ -93,10 +103,28 @@ typedef struct lskum_plan_s *lskum_plan;
  * LSKUM_ERR_HIP on device failures; *out is NULL unless LSKUM_OK. */
 int lskum_plan_create(lskum_plan *out, const lskum_cloud *cloud, const lskum_params *params,
                       void *stream);
+
+/* Batched plan over n_clouds independent clouds (uneven sizes, each with its
+ * own Mach number and angle of attack in params[c]; gamma, cfl, venkat_k and
+ * n_inner must be equal across clouds, and all clouds share k_pad).  The
+ * clouds are concatenated in the given order: cloud c occupies points
+ * lskum_plan_offset(plan, c) .. lskum_plan_offset(plan, c+1)-1 of every field,
+ * so all sweep calls below advance every cloud at once; the reductions
+ * (residual norm, force coefficients) are per cloud.  tuning may be NULL.
+ * A plan from lskum_plan_create is a batch of one cloud.  Errors as for
+ * lskum_plan_create, plus LSKUM_ERR_INVALID_ARG for differing shared
+ * settings or k_pad. */
+int lskum_batch_plan_create(lskum_plan *out, int32_t n_clouds, const lskum_cloud *clouds,
+                            const lskum_params *params, const lskum_tuning *tuning,
+                            void *stream);
 int lskum_plan_destroy(lskum_plan plan);
-/* Replace the flow/scheme settings of an existing plan (same cloud). */
+/* Replace the flow/scheme settings of an existing plan (same clouds);
+ * params points to one struct per cloud. */
 int lskum_plan_set_params(lskum_plan plan, const lskum_params *params);
-int32_t lskum_plan_n(lskum_plan plan);
+int lskum_plan_set_tuning(lskum_plan plan, const lskum_tuning *tuning);
+int32_t lskum_plan_n(lskum_plan plan);                       /* total points     */
+int32_t lskum_plan_clouds(lskum_plan plan);                  /* number of clouds */
+int32_t lskum_plan_offset(lskum_plan plan, int32_t cloud);   /* first point; cloud = n_clouds gives n */
 
 /* Free stream with the wall tangency projection applied at wall points. */
 int lskum_init_state(lskum_plan plan, double *U, void *stream);
@@ -129,23 +157,34 @@ int lskum_rk_stage(lskum_plan plan, int stage, const double *Un, const double *R
                    const double *dt, double *U, void *stream);
 
 /* Deterministic L2 norm of the density residual over interior and wall
- * points, written to out[0] (device). */
+ * points, per cloud: out[c] (device, n_clouds doubles). */
 int lskum_residual_norm(lskum_plan plan, const double *R, double *out, void *stream);
 
-/* Lift and drag coefficients from the wall polygon (trapezoidal pressure
- * per edge, chord 1), written to clcd[0..1] (device). */
+/* Lift and drag coefficients from each cloud's wall polygon (trapezoidal
+ * pressure per edge, chord 1): clcd[2c], clcd[2c+1] (device). */
 int lskum_force_coeffs(lskum_plan plan, const double *U, double *clcd, void *stream);
 
 /* Bytes of device workspace lskum_iterate needs for this plan. */
 size_t lskum_workspace_bytes(lskum_plan plan);
 
 /* Advance U by `iters` iterations (each: local time step from U^n, then four
- * stages of q_vars -> q_derivs -> flux_residual -> rk_stage).  hist[k]
- * (device, may be NULL) receives the residual norm of iteration k's first
- * stage.  `ws` is a device buffer of lskum_workspace_bytes(plan) bytes,
- * 256-byte aligned. */
+ * stages of q_vars -> q_derivs -> flux_residual -> rk_stage).
+ * hist[k*n_clouds + c] (device, may be NULL) receives the residual norm of
+ * iteration k's first stage for cloud c.  `ws` is a device buffer of
+ * lskum_workspace_bytes(plan) bytes, 256-byte aligned. */
 int lskum_iterate(lskum_plan plan, int32_t iters, double *U, double *hist, void *ws,
                   void *stream);
+
+/* Capture `iters` iterations of lskum_iterate on U into a HIP graph (one
+ * launch replays them all).  Each replay appends the residual norms of its
+ * iterations to hist as rows [row][n_clouds], row counted on the device
+ * from 0 (reset here) up to hist_rows-1 (later rows are dropped); hist may
+ * be NULL.  U, hist and ws stay bound to the graph.  One graph per plan at
+ * a time: replays share the plan's row counter. */
+int lskum_graph_create(lskum_graph *out, lskum_plan plan, int32_t iters, double *U, double *hist,
+                       int32_t hist_rows, void *ws, void *stream);
+int lskum_graph_launch(lskum_graph graph, void *stream);
+int lskum_graph_destroy(lskum_graph graph);
 
 /* Synchronises `stream`, then returns LSKUM_ERR_NONPHYSICAL or
  * LSKUM_ERR_DEGENERATE if a kernel has recorded one since the last clear,

@@ -18,8 +18,9 @@
 //   nbr  int32   [k_pad][n]  column-major connectivity, pad entries = own id
 //   cnt  int32   [n]         real neighbours per point
 //   wall int32   [n_wall]    wall loop, counter-clockwise
+//   cloud int32  [n]         cloud of each point; uinf double [n_clouds][4]
 //   status uint32            OR of the kFlag* bits seen by the kernels
-//   partial double [kNormBlocks] reduction scratch
+//   chunks, partial          residual-norm chunk table and partial sums
 
 #include <hip/hip_runtime.h>
 
@@ -40,22 +41,24 @@ using lskum_math::lk_rsqrt;
 
 constexpr int kBlock = 256;
 constexpr int kXcds = 8;
-constexpr int kNormBlocks = 512;
+constexpr int kNormChunk = 2048;  // points per residual-norm chunk
 constexpr unsigned kFlagNonPhysical = 1u;
 constexpr unsigned kFlagDegenerate = 2u;
 
 struct Geo {
   int n;
+  int xcd;  // 1: blocks relabelled so that each XCD walks one contiguous range
   const double2 *xy;
   const double2 *nrm;
   const int8_t *kind;
-  const int32_t *nbr;  // [k_pad][n]
+  const int32_t *nbr;    // [k_pad][n]
   const int32_t *cnt;
+  const int32_t *cloud;  // [n] cloud of each point (batched plans)
+  const double *uinf;    // [n_clouds][4] free-stream state of each cloud
 };
 
 struct Flow {
   double gamma, inv_gm1, cfl, venkat_k;
-  double uinf[4];
   bool gamma_is_14;  // gamma == 1.4 exactly: rho from beta^(-5/2) without a log
 };
 
@@ -83,18 +86,22 @@ __device__ __forceinline__ void st8(double *f, int i, const F8 &v) {
 // ---------------------------------------------------------------------------
 // launch helpers
 
-// Blocks are dispatched to the 8 XCDs round-robin.  Re-label them so that XCD
-// x processes one contiguous range of logical blocks.  The grid is a
-// multiple of 8; threads past n exit at once.
-__device__ __forceinline__ int xcd_block() {
+// Blocks are dispatched to the 8 XCDs round-robin.  With xcd set, re-label
+// them so that XCD x processes one contiguous range of logical blocks.  The
+// grid is a multiple of 8; threads past n exit at once.
+__device__ __forceinline__ int block_id(int xcd) {
+  if (!xcd) return blockIdx.x;
   const int per = gridDim.x / kXcds;
   return (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
 }
 
-__device__ __forceinline__ int point_index() { return xcd_block() * kBlock + threadIdx.x; }
+template <int BLK>
+__device__ __forceinline__ int point_index(int xcd) {
+  return block_id(xcd) * BLK + threadIdx.x;
+}
 
-inline int grid_for(int n) {
-  int nb = (n + kBlock - 1) / kBlock;
+inline int grid_for(int n, int blk = kBlock) {
+  int nb = (n + blk - 1) / blk;
   return (nb + kXcds - 1) / kXcds * kXcds;
 }
 
@@ -124,10 +131,10 @@ __device__ __forceinline__ void prim_from_cons(double g, const F4 &U, double &rh
   p = (g - 1.0) * (U.v[3] - 0.5 * rho * (u * u + v * v));
 }
 
-__global__ void __launch_bounds__(kBlock) k_q_vars(int n, double g, double inv_gm1,
+__global__ void __launch_bounds__(kBlock) k_q_vars(int n, int xcd, double g, double inv_gm1,
                                                    const double *__restrict__ U,
                                                    double *__restrict__ q, unsigned *status) {
-  const int i = point_index();
+  const int i = point_index<kBlock>(xcd);
   if (i >= n) return;
   double rho, u, v, p;
   prim_from_cons(g, ld4(U, i), rho, u, v, p);
@@ -146,18 +153,23 @@ __global__ void __launch_bounds__(kBlock) k_q_vars(int n, double g, double inv_g
 // ---------------------------------------------------------------------------
 // block tiles
 //
-// A block owns kBlock consecutive points (one Hilbert tile).  Kernels that
-// gather neighbour records first stage the tile's own records in LDS; about
-// 80 % of the neighbours of a 1M-point airfoil cloud fall inside their own
-// 256-point tile, so most gathers become LDS reads and only the remote ones
-// go through the vector memory path.
+// A block owns BLK consecutive points (one Hilbert tile; BLK is the tuned
+// block size, 128, 256 or 512).  Kernels that gather neighbour records first
+// stage the tile's own records in LDS; about 80 % of the neighbours of a
+// 1M-point airfoil cloud fall inside their own 256-point tile, so most
+// gathers become LDS reads and only the remote ones go through the vector
+// memory path.
 
-__device__ __forceinline__ int tile_lo() { return xcd_block() * kBlock; }
+template <int BLK>
+__device__ __forceinline__ int tile_lo(int xcd) {
+  return block_id(xcd) * BLK;
+}
 
 // lj = j - lo; true when j belongs to the tile starting at lo
+template <int BLK>
 __device__ __forceinline__ bool in_tile(int j, int lo, int &lj) {
   lj = j - lo;
-  return (unsigned)lj < (unsigned)kBlock;
+  return (unsigned)lj < (unsigned)BLK;
 }
 
 // Reader of point i's neighbour row (column-major connectivity).  Slots at
@@ -179,13 +191,14 @@ struct Row {
 // least-squares q-derivatives
 
 // First-order solve (eq. (9) with dq_i = q_i - q_0) and stencil bounds.
-__global__ void __launch_bounds__(kBlock) k_deriv_first(Geo G, const double *__restrict__ q,
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_deriv_first(Geo G, const double *__restrict__ q,
                                                         double *__restrict__ dq,
                                                         double *__restrict__ qlim) {
-  __shared__ double2 s_xy[kBlock];
-  __shared__ F4 s_q[kBlock];
+  __shared__ double2 s_xy[BLK];
+  __shared__ F4 s_q[BLK];
   const int n = G.n;
-  const int lo = tile_lo();
+  const int lo = tile_lo<BLK>(G.xcd);
   const int i = lo + threadIdx.x;
   const bool active = i < n;
   double2 xi = make_double2(0.0, 0.0);
@@ -208,7 +221,7 @@ __global__ void __launch_bounds__(kBlock) k_deriv_first(Geo G, const double *__r
   const Row row{G.nbr + i, n, c, i};
   auto fetch = [&](int j, double2 &xj, F4 &qj) {
     int lj;
-    if (in_tile(j, lo, lj)) {
+    if (in_tile<BLK>(j, lo, lj)) {
       xj = s_xy[lj];
       qj = s_q[lj];
     } else {
@@ -254,14 +267,15 @@ __global__ void __launch_bounds__(kBlock) k_deriv_first(Geo G, const double *__r
 
 // One Jacobi inner sweep (eq. (14)-(15)): modified differences from the
 // previous iterate at both ends of each edge.
-__global__ void __launch_bounds__(kBlock) k_deriv_inner(Geo G, const double *__restrict__ q,
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_deriv_inner(Geo G, const double *__restrict__ q,
                                                         const double *__restrict__ dqp,
                                                         double *__restrict__ dqn) {
-  __shared__ double2 s_xy[kBlock];
-  __shared__ F4 s_q[kBlock];
-  __shared__ F8 s_g[kBlock];
+  __shared__ double2 s_xy[BLK];
+  __shared__ F4 s_q[BLK];
+  __shared__ F8 s_g[BLK];
   const int n = G.n;
-  const int lo = tile_lo();
+  const int lo = tile_lo<BLK>(G.xcd);
   const int i = lo + threadIdx.x;
   const bool active = i < n;
   double2 xi = make_double2(0.0, 0.0);
@@ -283,7 +297,7 @@ __global__ void __launch_bounds__(kBlock) k_deriv_inner(Geo G, const double *__r
   const Row row{G.nbr + i, n, c, i};
   auto fetch = [&](int j, double2 &xj, F4 &qj, F8 &gj) {
     int lj;
-    if (in_tile(j, lo, lj)) {
+    if (in_tile<BLK>(j, lo, lj)) {
       xj = s_xy[lj];
       qj = s_q[lj];
       gj = s_g[lj];
@@ -418,16 +432,17 @@ __device__ __forceinline__ SplitW split_weights(bool s_dir, int count, double ss
   return s_dir ? SplitW{snn * inv, -ssn * inv} : SplitW{-ssn * inv, sss * inv};
 }
 
-__global__ void __launch_bounds__(kBlock) k_flux(Geo G, Flow P, const double *__restrict__ q,
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__restrict__ q,
                                                  const double *__restrict__ dq,
                                                  const double *__restrict__ qlim,
                                                  double *__restrict__ R, unsigned *status) {
-  __shared__ double2 s_xy[kBlock];
-  __shared__ F4 s_q[kBlock];
-  __shared__ F8 s_g[kBlock];
-  __shared__ F8 s_l[kBlock];
+  __shared__ double2 s_xy[BLK];
+  __shared__ F4 s_q[BLK];
+  __shared__ F8 s_g[BLK];
+  __shared__ F8 s_l[BLK];
   const int n = G.n;
-  const int lo = tile_lo();
+  const int lo = tile_lo<BLK>(G.xcd);
   const int i = lo + threadIdx.x;
   const bool active = i < n;
   double2 xi = make_double2(0.0, 0.0);
@@ -457,7 +472,7 @@ __global__ void __launch_bounds__(kBlock) k_flux(Geo G, Flow P, const double *__
   const Row row{G.nbr + i, n, c, i};
   auto fetch_xy = [&](int j) {
     int lj;
-    return in_tile(j, lo, lj) ? s_xy[lj] : G.xy[j];
+    return in_tile<BLK>(j, lo, lj) ? s_xy[lj] : G.xy[j];
   };
 
   // pass 1: geometry of the four half-plane stencils
@@ -515,7 +530,7 @@ __global__ void __launch_bounds__(kBlock) k_flux(Geo G, Flow P, const double *__
     int lj;
     F4 qj;
     F8 gj, lj8;
-    if (in_tile(j_cur, lo, lj)) {
+    if (in_tile<BLK>(j_cur, lo, lj)) {
       qj = s_q[lj];
       gj = s_g[lj];
       lj8 = s_l[lj];
@@ -589,7 +604,7 @@ __global__ void __launch_bounds__(kBlock) k_flux(Geo G, Flow P, const double *__
 __global__ void __launch_bounds__(kBlock) k_local_dt(Geo G, Flow P, const double *__restrict__ U,
                                                      double *__restrict__ dt) {
   const int n = G.n;
-  const int i = point_index();
+  const int i = point_index<kBlock>(G.xcd);
   if (i >= n) return;
   const double2 xi = G.xy[i];
   double best = INFINITY;
@@ -621,12 +636,12 @@ __global__ void __launch_bounds__(kBlock) k_rk_stage(Geo G, Flow P, int stage,
                                                      const double *__restrict__ dt,
                                                      double *__restrict__ U) {
   const int n = G.n;
-  const int i = point_index();
+  const int i = point_index<kBlock>(G.xcd);
   if (i >= n) return;
   const int kind = G.kind[i];
   F4 Ui;
   if (kind == 2) {
-    for (int m = 0; m < 4; ++m) Ui.v[m] = P.uinf[m];
+    Ui = ld4(G.uinf, G.cloud[i]);
   } else {
     const double h = 0.5 * dt[i];
     const F4 Uc = ld4(U, i), Ri = ld4(R, i);
@@ -647,11 +662,11 @@ __global__ void __launch_bounds__(kBlock) k_rk_stage(Geo G, Flow P, int stage,
   st4(U, i, Ui);
 }
 
-__global__ void __launch_bounds__(kBlock) k_init_state(Geo G, Flow P, double *__restrict__ U) {
+__global__ void __launch_bounds__(kBlock) k_init_state(Geo G, double *__restrict__ U) {
   const int n = G.n;
-  const int i = point_index();
+  const int i = point_index<kBlock>(G.xcd);
   if (i >= n) return;
-  F4 Ui{{P.uinf[0], P.uinf[1], P.uinf[2], P.uinf[3]}};
+  F4 Ui = ld4(G.uinf, G.cloud[i]);
   if (G.kind[i] == 1) {
     const double2 nv = G.nrm[i];
     const double mn = Ui.v[1] * nv.x + Ui.v[2] * nv.y;
@@ -680,16 +695,17 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
   return lds[0];
 }
 
-// Block b sums R_rho^2 over the fixed range [b*chunk, (b+1)*chunk) of
-// non-outer points; every thread walks a fixed strided subset.
-__global__ void __launch_bounds__(kBlock) k_norm_partial(int n, int chunk, const int8_t *kind,
+// Residual norms per cloud.  Each cloud's points are cut into fixed chunks
+// (chunk table built with the plan); block b sums R_rho^2 over the non-outer
+// points of chunk b, every thread walking a fixed strided subset.
+__global__ void __launch_bounds__(kBlock) k_norm_partial(const int2 *__restrict__ chunks,
+                                                         const int8_t *kind,
                                                          const double *__restrict__ R,
                                                          double *__restrict__ partial) {
   __shared__ double lds[kBlock];
-  const int lo = blockIdx.x * chunk;
-  const int hi = min(n, lo + chunk);
+  const int2 ch = chunks[blockIdx.x];
   double s = 0.0;
-  for (int i = lo + (int)threadIdx.x; i < hi; i += kBlock) {
+  for (int i = ch.x + (int)threadIdx.x; i < ch.y; i += kBlock) {
     const double r = R[4 * (size_t)i];
     if (kind[i] != 2) s += r * r;
   }
@@ -697,24 +713,51 @@ __global__ void __launch_bounds__(kBlock) k_norm_partial(int n, int chunk, const
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-__global__ void __launch_bounds__(kNormBlocks) k_norm_final(const double *__restrict__ partial,
-                                                            double *__restrict__ out) {
-  __shared__ double lds[kNormBlocks];
-  const double t = block_sum(partial[threadIdx.x], lds);
-  if (threadIdx.x == 0) out[0] = sqrt(t);
+// Block c combines the partials of cloud c (chunks [first[c], first[c+1]))
+// in a fixed order and writes its norm to out[row * n_clouds + c], where row
+// is *counter when a counter is given (graph replays append rows; rows past
+// `capacity` are not written), else 0.
+__global__ void __launch_bounds__(kBlock) k_norm_final(const int32_t *__restrict__ first,
+                                                       const double *__restrict__ partial,
+                                                       int n_clouds, const int32_t *counter,
+                                                       int capacity, double *__restrict__ out) {
+  __shared__ double lds[kBlock];
+  const int c = blockIdx.x;
+  double s = 0.0;
+  for (int k = first[c] + (int)threadIdx.x; k < first[c + 1]; k += kBlock) s += partial[k];
+  const double t = block_sum(s, lds);
+  if (threadIdx.x == 0) {
+    const int row = counter ? *counter : 0;
+    if (row < capacity) out[(size_t)row * n_clouds + c] = sqrt(t);
+  }
 }
 
-// Wall-polygon pressure integral (single block, fixed order).
-__global__ void __launch_bounds__(kBlock) k_force(Geo G, Flow P, int n_wall,
+// Advance the iteration counter of graph replays (one thread).
+__global__ void k_tick(int32_t *counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] += 1;
+}
+
+// Zero the iteration counter (a kernel, so that it can sit inside graphs).
+__global__ void k_zero_counter(int32_t *counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0;
+}
+
+// Lift and drag of cloud c (block c): wall polygon wall[woff[c] .. woff[c+1]),
+// trapezoidal pressure per edge, fixed-order reduction.
+__global__ void __launch_bounds__(kBlock) k_force(Geo G, Flow P, const int32_t *__restrict__ woff,
                                                   const int32_t *__restrict__ wall,
-                                                  const double *__restrict__ U, double mach,
-                                                  double aoa, double *__restrict__ clcd) {
+                                                  const double *__restrict__ mach,
+                                                  const double *__restrict__ aoa,
+                                                  const double *__restrict__ U,
+                                                  double *__restrict__ clcd) {
   __shared__ double lds[kBlock];
+  const int c = blockIdx.x;
+  const int w0 = woff[c], nw = woff[c + 1] - woff[c];
   const double pinf = 1.0 / P.gamma;
-  const double qinf = 0.5 * mach * mach;
+  const double qinf = 0.5 * mach[c] * mach[c];
   double fx = 0.0, fy = 0.0;
-  for (int e = threadIdx.x; e < n_wall; e += kBlock) {
-    const int a = wall[e], b = wall[(e + 1) % n_wall];
+  for (int e = threadIdx.x; e < nw; e += kBlock) {
+    const int a = wall[w0 + e], b = wall[w0 + (e + 1) % nw];
     double ra, ua, va, pa, rb, ub, vb, pb;
     prim_from_cons(P.gamma, ld4(U, a), ra, ua, va, pa);
     prim_from_cons(P.gamma, ld4(U, b), rb, ub, vb, pb);
@@ -727,9 +770,9 @@ __global__ void __launch_bounds__(kBlock) k_force(Geo G, Flow P, int n_wall,
   __syncthreads();
   const double Cy = block_sum(fy, lds);
   if (threadIdx.x == 0) {
-    const double ca = cos(aoa), sa = sin(aoa);
-    clcd[0] = Cy * ca - Cx * sa;
-    clcd[1] = Cx * ca + Cy * sa;
+    const double ca = cos(aoa[c]), sa = sin(aoa[c]);
+    clcd[2 * c] = Cy * ca - Cx * sa;
+    clcd[2 * c + 1] = Cx * ca + Cy * sa;
   }
 }
 
@@ -740,35 +783,47 @@ __global__ void __launch_bounds__(kBlock) k_force(Geo G, Flow P, int n_wall,
 
 struct lskum_plan_s {
   int device = 0;
-  int32_t n = 0, k_pad = 0, n_wall = 0;
-  lskum_params params{};
+  int32_t n = 0, k_pad = 0, n_clouds = 0, n_wall = 0, n_chunks = 0;
+  int block = 256, xcd = 1;
+  std::vector<lskum_params> params;  // one per cloud
+  std::vector<int32_t> offset;       // first point of each cloud (+ total)
   double2 *xy = nullptr, *nrm = nullptr;
   int8_t *kind = nullptr;
-  int32_t *nbr = nullptr, *cnt = nullptr, *wall = nullptr;
+  int32_t *nbr = nullptr, *cnt = nullptr, *cloud = nullptr;
+  int32_t *wall = nullptr, *woff = nullptr;  // concatenated wall loops, offsets [n_clouds+1]
+  double *uinf = nullptr;                    // [n_clouds][4]
+  double *mach = nullptr, *aoa = nullptr;    // [n_clouds]
+  int2 *chunks = nullptr;                    // residual-norm chunks
+  int32_t *chunk_first = nullptr;            // first chunk of each cloud [n_clouds+1]
+  double *partial = nullptr;                 // [n_chunks]
+  double *norm_scratch = nullptr;            // [n_clouds]
+  int32_t *counter = nullptr;                // graph-replay iteration counter
   unsigned *status = nullptr;
-  double *partial = nullptr;
+};
+
+struct lskum_graph_s {
+  lskum_plan_s *plan = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t capture = nullptr;
 };
 
 namespace {
 
 inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
-Geo geo(const lskum_plan_s *p) { return Geo{p->n, p->xy, p->nrm, p->kind, p->nbr, p->cnt}; }
+Geo geo(const lskum_plan_s *p) {
+  return Geo{p->n, p->xcd, p->xy, p->nrm, p->kind, p->nbr, p->cnt, p->cloud, p->uinf};
+}
 
 Flow flow(const lskum_plan_s *p) {
   Flow f;
-  const lskum_params &q = p->params;
+  const lskum_params &q = p->params[0];  // shared settings (validated equal)
   f.gamma = q.gamma;
   f.inv_gm1 = 1.0 / (q.gamma - 1.0);
   f.cfl = q.cfl;
   f.venkat_k = q.venkat_k;
   f.gamma_is_14 = q.gamma == 1.4;
-  const double rho = 1.0, u = q.mach * std::cos(q.aoa_rad), v = q.mach * std::sin(q.aoa_rad);
-  const double pr = 1.0 / q.gamma;
-  f.uinf[0] = rho;
-  f.uinf[1] = rho * u;
-  f.uinf[2] = rho * v;
-  f.uinf[3] = pr / (q.gamma - 1.0) + 0.5 * rho * (u * u + v * v);
   return f;
 }
 
@@ -777,6 +832,31 @@ bool params_ok(const lskum_params *p) {
          p->mach >= 0.0 && std::isfinite(p->aoa_rad) && std::isfinite(p->cfl) && p->cfl > 0.0 &&
          std::isfinite(p->venkat_k) && p->venkat_k >= 0.0 && p->n_inner >= 0 &&
          p->n_inner <= 64 && p->reserved == 0;
+}
+
+// every cloud valid, and the settings the kernels share equal across clouds
+bool batch_params_ok(int32_t nc, const lskum_params *p) {
+  if (!p || nc < 1) return false;
+  for (int32_t c = 0; c < nc; ++c) {
+    if (!params_ok(p + c)) return false;
+    if (p[c].gamma != p[0].gamma || p[c].cfl != p[0].cfl || p[c].venkat_k != p[0].venkat_k ||
+        p[c].n_inner != p[0].n_inner)
+      return false;
+  }
+  return true;
+}
+
+bool tuning_ok(const lskum_tuning *t) {
+  return !t || ((t->block == 0 || t->block == 128 || t->block == 256 || t->block == 512) &&
+                (t->xcd_contiguous == 0 || t->xcd_contiguous == 1));
+}
+
+void free_stream_state(const lskum_params &q, double U[4]) {
+  const double rho = 1.0, u = q.mach * std::cos(q.aoa_rad), v = q.mach * std::sin(q.aoa_rad);
+  U[0] = rho;
+  U[1] = rho * u;
+  U[2] = rho * v;
+  U[3] = (1.0 / q.gamma) / (q.gamma - 1.0) + 0.5 * rho * (u * u + v * v);
 }
 
 int launched() { return hipGetLastError() == hipSuccess ? LSKUM_OK : LSKUM_ERR_HIP; }
@@ -790,14 +870,10 @@ void release(lskum_plan_s *p) {
   int cur = 0;
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(p->device);
-  (void)hipFree(p->xy);
-  (void)hipFree(p->nrm);
-  (void)hipFree(p->kind);
-  (void)hipFree(p->nbr);
-  (void)hipFree(p->cnt);
-  (void)hipFree(p->wall);
-  (void)hipFree(p->status);
-  (void)hipFree(p->partial);
+  void *bufs[] = {p->xy,     p->nrm,  p->kind,   p->nbr,         p->cnt,     p->cloud,
+                  p->wall,   p->woff, p->uinf,   p->mach,        p->aoa,     p->chunks,
+                  p->chunk_first, p->partial, p->norm_scratch, p->counter, p->status};
+  for (void *b : bufs) (void)hipFree(b);
   (void)hipSetDevice(cur);
   delete p;
 }
@@ -811,10 +887,147 @@ int upload(T **dst, const void *src, size_t count) {
   return LSKUM_OK;
 }
 
-// Size of one field of `comps` components, checked against overflow.
-constexpr size_t kNumWorkFields = 4 + 4 + 8 + 8 + 8 + 4 + 1 + 1;  // Un q dq qlim work R dt norm
+constexpr size_t kNumWorkFields = 4 + 4 + 8 + 8 + 8 + 4 + 1;  // Un q dq qlim work R dt
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Validate one cloud and append it (point ids shifted by base) to the
+// concatenated host arrays.
+int append_cloud(const lskum_cloud *c, int32_t kp, int32_t base, int32_t cloud_id,
+                 std::vector<int32_t> &rows, std::vector<double2> &xy, std::vector<double2> &nrm,
+                 std::vector<int8_t> &kind, std::vector<int32_t> &cnt, std::vector<int32_t> &cid,
+                 std::vector<int32_t> &wall) {
+  if (!c || c->n < 1 || c->k_pad != kp || !c->x || !c->y || !c->nx || !c->ny || !c->kind ||
+      !c->row_ptr || !c->col || !c->nbr_count || c->n_wall < 0 || (c->n_wall > 0 && !c->wall_loop))
+    return LSKUM_ERR_INVALID_ARG;
+  const int32_t n = c->n;
+  if (c->row_ptr[0] != 0) return LSKUM_ERR_BAD_CLOUD;
+  for (int32_t i = 0; i < n; ++i) {
+    const int64_t b = c->row_ptr[i], e = c->row_ptr[i + 1];
+    const int32_t k = c->nbr_count[i];
+    if (e - b != kp || k < 2 || k > kp) return LSKUM_ERR_BAD_CLOUD;
+    if (c->kind[i] < 0 || c->kind[i] > 2) return LSKUM_ERR_BAD_CLOUD;
+    if (!std::isfinite(c->x[i]) || !std::isfinite(c->y[i]) || !std::isfinite(c->nx[i]) ||
+        !std::isfinite(c->ny[i]))
+      return LSKUM_ERR_BAD_CLOUD;
+    for (int32_t s = 0; s < kp; ++s) {
+      int32_t j = c->col[b + s];
+      if (s < k) {
+        if (j < 0 || j >= n || j == i) return LSKUM_ERR_BAD_CLOUD;
+      } else {
+        j = i;  // padding is always the point itself
+      }
+      rows.push_back(base + j);
+    }
+    xy.push_back(make_double2(c->x[i], c->y[i]));
+    nrm.push_back(make_double2(c->nx[i], c->ny[i]));
+    kind.push_back(c->kind[i]);
+    cnt.push_back(k);
+    cid.push_back(cloud_id);
+  }
+  for (int32_t e = 0; e < c->n_wall; ++e) {
+    const int32_t w = c->wall_loop[e];
+    if (w < 0 || w >= n || c->kind[w] != 1) return LSKUM_ERR_BAD_CLOUD;
+    wall.push_back(base + w);
+  }
+  return LSKUM_OK;
+}
+
+int upload_uinf(lskum_plan_s *p) {
+  std::vector<double> u((size_t)4 * p->n_clouds), mach(p->n_clouds), aoa(p->n_clouds);
+  for (int32_t c = 0; c < p->n_clouds; ++c) {
+    free_stream_state(p->params[c], &u[4 * (size_t)c]);
+    mach[c] = p->params[c].mach;
+    aoa[c] = p->params[c].aoa_rad;
+  }
+  if (hipMemcpy(p->uinf, u.data(), u.size() * sizeof(double), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(p->mach, mach.data(), mach.size() * sizeof(double), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(p->aoa, aoa.data(), aoa.size() * sizeof(double), hipMemcpyHostToDevice) !=
+          hipSuccess)
+    return LSKUM_ERR_HIP;
+  return LSKUM_OK;
+}
+
+// kernel launches with the plan's tile size
+#define LSKUM_TILED(kern, p, stream, ...)                                                    \
+  do {                                                                                       \
+    const int g_ = grid_for((p)->n, (p)->block);                                             \
+    switch ((p)->block) {                                                                    \
+      case 128: kern<128><<<g_, 128, 0, S(stream)>>>(__VA_ARGS__); break;                    \
+      case 512: kern<512><<<g_, 512, 0, S(stream)>>>(__VA_ARGS__); break;                    \
+      default: kern<256><<<g_, 256, 0, S(stream)>>>(__VA_ARGS__); break;                     \
+    }                                                                                        \
+  } while (0)
+
+int norm_launch(lskum_plan_s *p, const double *R, double *out, const int32_t *counter,
+                int capacity, void *stream) {
+  k_norm_partial<<<p->n_chunks, kBlock, 0, S(stream)>>>(p->chunks, p->kind, R, p->partial);
+  k_norm_final<<<p->n_clouds, kBlock, 0, S(stream)>>>(p->chunk_first, p->partial, p->n_clouds,
+                                                      counter, capacity, out);
+  return launched();
+}
+
+int q_derivs_launch(lskum_plan_s *p, const double *q, double *dq, double *qlim, double *work,
+                    void *stream) {
+  const Geo g = geo(p);
+  const int ni = p->params[0].n_inner;
+  // ping-pong so that the last sweep writes dq
+  double *a = (ni % 2 == 0) ? dq : work;
+  double *b = (ni % 2 == 0) ? work : dq;
+  LSKUM_TILED(k_deriv_first, p, stream, g, q, a, qlim);
+  for (int it = 0; it < ni; ++it) {
+    LSKUM_TILED(k_deriv_inner, p, stream, g, q, a, b);
+    double *t = a;
+    a = b;
+    b = t;
+  }
+  return launched();
+}
+
+// The iteration body shared by lskum_iterate and graph capture.  With a
+// counter, norms go to hist[*counter] and the counter advances after each
+// iteration (graph replays); without one, iteration k writes hist[k].
+int run_iterations(lskum_plan_s *p, int32_t iters, double *U, double *hist, int32_t hist_rows,
+                   void *ws, int32_t *counter, void *stream) {
+  const size_t n = (size_t)p->n;
+  const size_t f1 = align256(n * sizeof(double));
+  char *base = static_cast<char *>(ws);
+  double *Un = reinterpret_cast<double *>(base);
+  double *q = reinterpret_cast<double *>(base + 4 * f1);
+  double *dq = reinterpret_cast<double *>(base + 8 * f1);
+  double *qlim = reinterpret_cast<double *>(base + 16 * f1);
+  double *work = reinterpret_cast<double *>(base + 24 * f1);
+  double *R = reinterpret_cast<double *>(base + 32 * f1);
+  double *dt = reinterpret_cast<double *>(base + 36 * f1);
+  const Geo g = geo(p);
+  const Flow f = flow(p);
+  const int grid = grid_for(p->n);
+  const int copy_grid = grid_for((int)std::min<size_t>(4 * n, (size_t)1 << 24));
+  int rc;
+  for (int32_t it = 0; it < iters; ++it) {
+    k_local_dt<<<grid, kBlock, 0, S(stream)>>>(g, f, U, dt);
+    k_copy<<<copy_grid, kBlock, 0, S(stream)>>>(4 * n, U, Un);
+    for (int s = 0; s < 4; ++s) {
+      k_q_vars<<<grid, kBlock, 0, S(stream)>>>(p->n, p->xcd, f.gamma, f.inv_gm1, U, q, p->status);
+      if ((rc = q_derivs_launch(p, q, dq, qlim, work, stream))) return rc;
+      LSKUM_TILED(k_flux, p, stream, g, f, q, dq, qlim, R, p->status);
+      if (s == 0) {
+        if (counter)
+          rc = norm_launch(p, R, hist ? hist : p->norm_scratch, counter, hist ? hist_rows : 1,
+                           stream);
+        else
+          rc = norm_launch(p, R, hist ? hist + (size_t)it * p->n_clouds : p->norm_scratch,
+                           nullptr, 1, stream);
+        if (rc) return rc;
+      }
+      k_rk_stage<<<grid, kBlock, 0, S(stream)>>>(g, f, s, Un, R, dt, U);
+    }
+    if (counter) k_tick<<<1, 64, 0, S(stream)>>>(counter);
+  }
+  return launched();
+}
 
 }  // namespace
 
@@ -833,50 +1046,53 @@ const char *lskum_strerror(int code) {
   }
 }
 
-int lskum_plan_create(lskum_plan *out, const lskum_cloud *c, const lskum_params *params,
-                      void *stream) {
+int lskum_batch_plan_create(lskum_plan *out, int32_t n_clouds, const lskum_cloud *clouds,
+                            const lskum_params *params, const lskum_tuning *tuning,
+                            void *stream) {
   if (!out) return LSKUM_ERR_INVALID_ARG;
   *out = nullptr;
-  if (!c || !params_ok(params) || c->n < 1 || c->k_pad < 1 || !c->x || !c->y || !c->nx ||
-      !c->ny || !c->kind || !c->row_ptr || !c->col || !c->nbr_count || c->n_wall < 0 ||
-      (c->n_wall > 0 && !c->wall_loop))
+  if (n_clouds < 1 || !clouds || !batch_params_ok(n_clouds, params) || !tuning_ok(tuning))
     return LSKUM_ERR_INVALID_ARG;
-  const int32_t n = c->n, kp = c->k_pad;
-  if ((size_t)n * (size_t)kp > (size_t)INT32_MAX * 4) return LSKUM_ERR_INVALID_ARG;
-  // host validation and the column-major connectivity
-  std::vector<int32_t> nbr;
+  const int32_t kp = clouds[0].k_pad;
+  int64_t total = 0;
+  for (int32_t c = 0; c < n_clouds; ++c) total += clouds[c].n;
+  if (kp < 1 || total < 1 || total > INT32_MAX / 2 || total * (int64_t)kp > (int64_t)INT32_MAX * 4)
+    return LSKUM_ERR_INVALID_ARG;
+  const int32_t n = (int32_t)total;
+  // host validation, concatenation (ids shifted per cloud)
+  std::vector<int32_t> rows, cnt, cid, wall, woff(1, 0), offset(1, 0);
+  std::vector<double2> xy, nrm;
+  std::vector<int8_t> kind;
   try {
-    nbr.resize((size_t)n * (size_t)kp);
+    rows.reserve((size_t)n * kp);
+    xy.reserve(n);
+    nrm.reserve(n);
+    kind.reserve(n);
+    cnt.reserve(n);
+    cid.reserve(n);
+    for (int32_t c = 0; c < n_clouds; ++c) {
+      const int rc = append_cloud(clouds + c, kp, offset.back(), c, rows, xy, nrm, kind, cnt, cid,
+                                  wall);
+      if (rc) return rc;
+      offset.push_back(offset.back() + clouds[c].n);
+      woff.push_back((int32_t)wall.size());
+    }
   } catch (const std::bad_alloc &) {
     return LSKUM_ERR_NO_MEMORY;
   }
-  if (c->row_ptr[0] != 0) return LSKUM_ERR_BAD_CLOUD;
-  for (int32_t i = 0; i < n; ++i) {
-    const int64_t b = c->row_ptr[i], e = c->row_ptr[i + 1];
-    const int32_t cnt = c->nbr_count[i];
-    if (e - b != kp || cnt < 2 || cnt > kp) return LSKUM_ERR_BAD_CLOUD;
-    if (c->kind[i] < 0 || c->kind[i] > 2) return LSKUM_ERR_BAD_CLOUD;
-    if (!std::isfinite(c->x[i]) || !std::isfinite(c->y[i]) || !std::isfinite(c->nx[i]) ||
-        !std::isfinite(c->ny[i]))
-      return LSKUM_ERR_BAD_CLOUD;
-    for (int32_t k = 0; k < kp; ++k) {
-      int32_t j = c->col[b + k];
-      if (k < cnt) {
-        if (j < 0 || j >= n || j == i) return LSKUM_ERR_BAD_CLOUD;
-      } else {
-        j = i;  // padding is always the point itself
-      }
-      nbr[(size_t)k * n + i] = j;
-    }
-  }
-  for (int32_t e = 0; e < c->n_wall; ++e) {
-    const int32_t w = c->wall_loop[e];
-    if (w < 0 || w >= n || c->kind[w] != 1) return LSKUM_ERR_BAD_CLOUD;
-  }
-  std::vector<double2> xy((size_t)n), nrm((size_t)n);
-  for (int32_t i = 0; i < n; ++i) {
-    xy[i] = make_double2(c->x[i], c->y[i]);
-    nrm[i] = make_double2(c->nx[i], c->ny[i]);
+  // column-major connectivity
+  std::vector<int32_t> nbr((size_t)n * kp);
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t s = 0; s < kp; ++s) nbr[(size_t)s * n + i] = rows[(size_t)i * kp + s];
+  rows.clear();
+  rows.shrink_to_fit();
+  // residual-norm chunks, per cloud
+  std::vector<int2> chunks;
+  std::vector<int32_t> chunk_first(1, 0);
+  for (int32_t c = 0; c < n_clouds; ++c) {
+    for (int32_t a = offset[c]; a < offset[c + 1]; a += kNormChunk)
+      chunks.push_back(make_int2(a, std::min(a + kNormChunk, offset[c + 1])));
+    chunk_first.push_back((int32_t)chunks.size());
   }
   lskum_plan_s *p = new (std::nothrow) lskum_plan_s();
   if (!p) return LSKUM_ERR_NO_MEMORY;
@@ -886,29 +1102,53 @@ int lskum_plan_create(lskum_plan *out, const lskum_cloud *c, const lskum_params 
   }
   p->n = n;
   p->k_pad = kp;
-  p->n_wall = c->n_wall;
-  p->params = *params;
+  p->n_clouds = n_clouds;
+  p->n_wall = (int32_t)wall.size();
+  p->n_chunks = (int32_t)chunks.size();
+  p->params.assign(params, params + n_clouds);
+  p->offset = offset;
+  if (tuning) {
+    p->block = tuning->block ? tuning->block : 256;
+    p->xcd = tuning->xcd_contiguous;
+  }
   int rc = LSKUM_OK;
-  if (rc == LSKUM_OK) rc = upload(&p->xy, xy.data(), (size_t)n);
-  if (rc == LSKUM_OK) rc = upload(&p->nrm, nrm.data(), (size_t)n);
-  if (rc == LSKUM_OK) rc = upload(&p->kind, c->kind, (size_t)n);
+  if (rc == LSKUM_OK) rc = upload(&p->xy, xy.data(), xy.size());
+  if (rc == LSKUM_OK) rc = upload(&p->nrm, nrm.data(), nrm.size());
+  if (rc == LSKUM_OK) rc = upload(&p->kind, kind.data(), kind.size());
   if (rc == LSKUM_OK) rc = upload(&p->nbr, nbr.data(), nbr.size());
-  if (rc == LSKUM_OK) rc = upload(&p->cnt, c->nbr_count, (size_t)n);
-  if (rc == LSKUM_OK) rc = upload(&p->wall, c->wall_loop, (size_t)c->n_wall);
-  if (rc == LSKUM_OK && hipMalloc((void **)&p->status, sizeof(unsigned)) != hipSuccess)
+  if (rc == LSKUM_OK) rc = upload(&p->cnt, cnt.data(), cnt.size());
+  if (rc == LSKUM_OK) rc = upload(&p->cloud, cid.data(), cid.size());
+  if (rc == LSKUM_OK) rc = upload(&p->wall, wall.data(), wall.size());
+  if (rc == LSKUM_OK) rc = upload(&p->woff, woff.data(), woff.size());
+  if (rc == LSKUM_OK) rc = upload(&p->chunks, chunks.data(), chunks.size());
+  if (rc == LSKUM_OK) rc = upload(&p->chunk_first, chunk_first.data(), chunk_first.size());
+  if (rc == LSKUM_OK && (hipMalloc((void **)&p->uinf, 4 * sizeof(double) * n_clouds) != hipSuccess ||
+                         hipMalloc((void **)&p->mach, sizeof(double) * n_clouds) != hipSuccess ||
+                         hipMalloc((void **)&p->aoa, sizeof(double) * n_clouds) != hipSuccess ||
+                         hipMalloc((void **)&p->partial, sizeof(double) * chunks.size()) != hipSuccess ||
+                         hipMalloc((void **)&p->norm_scratch, sizeof(double) * n_clouds) != hipSuccess ||
+                         hipMalloc((void **)&p->counter, sizeof(int32_t)) != hipSuccess ||
+                         hipMalloc((void **)&p->status, sizeof(unsigned)) != hipSuccess))
     rc = LSKUM_ERR_NO_MEMORY;
-  if (rc == LSKUM_OK &&
-      hipMalloc((void **)&p->partial, kNormBlocks * sizeof(double)) != hipSuccess)
-    rc = LSKUM_ERR_NO_MEMORY;
-  if (rc == LSKUM_OK && hipMemsetAsync(p->status, 0, sizeof(unsigned), S(stream)) != hipSuccess)
+  if (rc == LSKUM_OK) rc = upload_uinf(p);
+  if (rc == LSKUM_OK && (hipMemsetAsync(p->status, 0, sizeof(unsigned), S(stream)) != hipSuccess ||
+                         hipMemsetAsync(p->counter, 0, sizeof(int32_t), S(stream)) != hipSuccess ||
+                         hipStreamSynchronize(S(stream)) != hipSuccess))
     rc = LSKUM_ERR_HIP;
-  if (rc == LSKUM_OK && hipStreamSynchronize(S(stream)) != hipSuccess) rc = LSKUM_ERR_HIP;
   if (rc != LSKUM_OK) {
     release(p);
     return rc;
   }
   *out = p;
   return LSKUM_OK;
+}
+
+int lskum_plan_create(lskum_plan *out, const lskum_cloud *cloud, const lskum_params *params,
+                      void *stream) {
+  if (!out) return LSKUM_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!cloud || !params_ok(params)) return LSKUM_ERR_INVALID_ARG;
+  return lskum_batch_plan_create(out, 1, cloud, params, nullptr, stream);
 }
 
 int lskum_plan_destroy(lskum_plan p) {
@@ -918,50 +1158,52 @@ int lskum_plan_destroy(lskum_plan p) {
 }
 
 int lskum_plan_set_params(lskum_plan p, const lskum_params *params) {
-  if (!p || !params_ok(params)) return LSKUM_ERR_INVALID_ARG;
-  p->params = *params;
+  if (!p || !batch_params_ok(p->n_clouds, params)) return LSKUM_ERR_INVALID_ARG;
+  p->params.assign(params, params + p->n_clouds);
+  return upload_uinf(p);
+}
+
+int lskum_plan_set_tuning(lskum_plan p, const lskum_tuning *tuning) {
+  if (!p || !tuning || !tuning_ok(tuning)) return LSKUM_ERR_INVALID_ARG;
+  p->block = tuning->block ? tuning->block : 256;
+  p->xcd = tuning->xcd_contiguous;
   return LSKUM_OK;
 }
 
 int32_t lskum_plan_n(lskum_plan p) { return p ? p->n : -1; }
 
+int32_t lskum_plan_clouds(lskum_plan p) { return p ? p->n_clouds : -1; }
+
+int32_t lskum_plan_offset(lskum_plan p, int32_t cloud) {
+  if (!p || cloud < 0 || cloud > p->n_clouds) return -1;
+  return p->offset[cloud];
+}
+
 int lskum_init_state(lskum_plan p, double *U, void *stream) {
   if (!p || !a32(U)) return LSKUM_ERR_INVALID_ARG;
-  k_init_state<<<grid_for(p->n), kBlock, 0, S(stream)>>>(geo(p), flow(p), U);
+  k_init_state<<<grid_for(p->n), kBlock, 0, S(stream)>>>(geo(p), U);
   return launched();
 }
 
 int lskum_q_vars(lskum_plan p, const double *U, double *q, void *stream) {
   if (!p || !a32(U) || !a32(q)) return LSKUM_ERR_INVALID_ARG;
   const Flow f = flow(p);
-  k_q_vars<<<grid_for(p->n), kBlock, 0, S(stream)>>>(p->n, f.gamma, f.inv_gm1, U, q, p->status);
+  k_q_vars<<<grid_for(p->n), kBlock, 0, S(stream)>>>(p->n, p->xcd, f.gamma, f.inv_gm1, U, q,
+                                                     p->status);
   return launched();
 }
 
 int lskum_q_derivs(lskum_plan p, const double *q, double *dq, double *qlim, double *work,
                    void *stream) {
-  if (!p || !a32(q) || !a64(dq) || !a64(qlim) || (p->params.n_inner > 0 && !a64(work)))
+  if (!p || !a32(q) || !a64(dq) || !a64(qlim) || (p->params[0].n_inner > 0 && !a64(work)))
     return LSKUM_ERR_INVALID_ARG;
-  const Geo g = geo(p);
-  const int grid = grid_for(p->n);
-  const int ni = p->params.n_inner;
-  // ping-pong so that the last sweep writes dq
-  double *a = (ni % 2 == 0) ? dq : work;
-  double *b = (ni % 2 == 0) ? work : dq;
-  k_deriv_first<<<grid, kBlock, 0, S(stream)>>>(g, q, a, qlim);
-  for (int it = 0; it < ni; ++it) {
-    k_deriv_inner<<<grid, kBlock, 0, S(stream)>>>(g, q, a, b);
-    double *t = a;
-    a = b;
-    b = t;
-  }
-  return launched();
+  return q_derivs_launch(p, q, dq, qlim, work, stream);
 }
 
 int lskum_flux_residual(lskum_plan p, const double *q, const double *dq, const double *qlim,
                         double *R, void *stream) {
   if (!p || !a32(q) || !a64(dq) || !a64(qlim) || !a32(R)) return LSKUM_ERR_INVALID_ARG;
-  k_flux<<<grid_for(p->n), kBlock, 0, S(stream)>>>(geo(p), flow(p), q, dq, qlim, R, p->status);
+  LSKUM_TILED(k_flux, p, stream, geo(p), flow(p), q, dq, qlim, R, p->status);
   return launched();
 }
 
@@ -981,16 +1223,13 @@ int lskum_rk_stage(lskum_plan p, int stage, const double *Un, const double *R, c
 
 int lskum_residual_norm(lskum_plan p, const double *R, double *out, void *stream) {
   if (!p || !a32(R) || !out) return LSKUM_ERR_INVALID_ARG;
-  const int chunk = (p->n + kNormBlocks - 1) / kNormBlocks;
-  k_norm_partial<<<kNormBlocks, kBlock, 0, S(stream)>>>(p->n, chunk, p->kind, R, p->partial);
-  k_norm_final<<<1, kNormBlocks, 0, S(stream)>>>(p->partial, out);
-  return launched();
+  return norm_launch(p, R, out, nullptr, 1, stream);
 }
 
 int lskum_force_coeffs(lskum_plan p, const double *U, double *clcd, void *stream) {
-  if (!p || !a32(U) || !clcd || p->n_wall < 2) return LSKUM_ERR_INVALID_ARG;
-  k_force<<<1, kBlock, 0, S(stream)>>>(geo(p), flow(p), p->n_wall, p->wall, U, p->params.mach,
-                                       p->params.aoa_rad, clcd);
+  if (!p || !a32(U) || !clcd) return LSKUM_ERR_INVALID_ARG;
+  k_force<<<p->n_clouds, kBlock, 0, S(stream)>>>(geo(p), flow(p), p->woff, p->wall, p->mach,
+                                                 p->aoa, U, clcd);
   return launched();
 }
 
@@ -1001,33 +1240,60 @@ size_t lskum_workspace_bytes(lskum_plan p) {
 
 int lskum_iterate(lskum_plan p, int32_t iters, double *U, double *hist, void *ws, void *stream) {
   if (!p || !a32(U) || !ws || iters < 0 || ((uintptr_t)ws % 256) != 0) return LSKUM_ERR_INVALID_ARG;
-  const size_t n = (size_t)p->n;
-  const size_t f1 = align256(n * sizeof(double));
-  char *base = static_cast<char *>(ws);
-  double *Un = reinterpret_cast<double *>(base);
-  double *q = reinterpret_cast<double *>(base + 4 * f1);
-  double *dq = reinterpret_cast<double *>(base + 8 * f1);
-  double *qlim = reinterpret_cast<double *>(base + 16 * f1);
-  double *work = reinterpret_cast<double *>(base + 24 * f1);
-  double *R = reinterpret_cast<double *>(base + 32 * f1);
-  double *dt = reinterpret_cast<double *>(base + 36 * f1);
-  double *scratch = reinterpret_cast<double *>(base + 37 * f1);
-  const int copy_grid = grid_for((int)std::min<size_t>(4 * n, (size_t)1 << 24));
-  for (int32_t it = 0; it < iters; ++it) {
-    int rc = lskum_local_dt(p, U, dt, stream);
-    if (rc) return rc;
-    k_copy<<<copy_grid, kBlock, 0, S(stream)>>>(4 * n, U, Un);
-    for (int s = 0; s < 4; ++s) {
-      if ((rc = lskum_q_vars(p, U, q, stream))) return rc;
-      if ((rc = lskum_q_derivs(p, q, dq, qlim, work, stream))) return rc;
-      if ((rc = lskum_flux_residual(p, q, dq, qlim, R, stream))) return rc;
-      if (s == 0) {
-        if ((rc = lskum_residual_norm(p, R, hist ? hist + it : scratch, stream))) return rc;
-      }
-      if ((rc = lskum_rk_stage(p, s, Un, R, dt, U, stream))) return rc;
-    }
+  return run_iterations(p, iters, U, hist, iters, ws, nullptr, stream);
+}
+
+int lskum_graph_create(lskum_graph *out, lskum_plan p, int32_t iters, double *U, double *hist,
+                       int32_t hist_rows, void *ws, void *stream) {
+  if (!out) return LSKUM_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!p || iters < 1 || !a32(U) || !ws || ((uintptr_t)ws % 256) != 0 ||
+      (hist && hist_rows < 1))
+    return LSKUM_ERR_INVALID_ARG;
+  lskum_graph_s *g = new (std::nothrow) lskum_graph_s();
+  if (!g) return LSKUM_ERR_NO_MEMORY;
+  g->plan = p;
+  int rc = LSKUM_OK;
+  if (hipStreamCreateWithFlags(&g->capture, hipStreamNonBlocking) != hipSuccess) rc = LSKUM_ERR_HIP;
+  if (rc == LSKUM_OK &&
+      hipStreamBeginCapture(g->capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    rc = LSKUM_ERR_HIP;
+  if (rc == LSKUM_OK) {
+    const int r2 = run_iterations(p, iters, U, hist, hist_rows, ws, p->counter, g->capture);
+    const hipError_t e = hipStreamEndCapture(g->capture, &g->graph);
+    if (r2 != LSKUM_OK) rc = r2;
+    else if (e != hipSuccess) rc = LSKUM_ERR_HIP;
   }
-  return launched();
+  if (rc == LSKUM_OK && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
+    rc = LSKUM_ERR_HIP;
+  if (rc == LSKUM_OK) {
+    // start the history at row 0 (a kernel on the caller's stream)
+    k_zero_counter<<<1, 64, 0, S(stream)>>>(p->counter);
+    rc = launched();
+  }
+  if (rc != LSKUM_OK) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->capture) (void)hipStreamDestroy(g->capture);
+    delete g;
+    return rc;
+  }
+  *out = g;
+  return LSKUM_OK;
+}
+
+int lskum_graph_launch(lskum_graph g, void *stream) {
+  if (!g || !g->exec) return LSKUM_ERR_INVALID_ARG;
+  return hipGraphLaunch(g->exec, S(stream)) == hipSuccess ? LSKUM_OK : LSKUM_ERR_HIP;
+}
+
+int lskum_graph_destroy(lskum_graph g) {
+  if (!g) return LSKUM_ERR_INVALID_ARG;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->capture) (void)hipStreamDestroy(g->capture);
+  delete g;
+  return LSKUM_OK;
 }
 
 int lskum_status(lskum_plan p, void *stream) {

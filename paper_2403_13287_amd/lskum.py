@@ -50,12 +50,20 @@ class _Params(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("xcd_contiguous", ctypes.c_int32)]
+
+
 # name -> (restype, argtypes); 'v' = void*, 'i' = int32, 'd' = double
 _SIGS = {
     "lskum_plan_create": (ctypes.c_int, "vvvv"),
+    "lskum_batch_plan_create": (ctypes.c_int, "vivvvv"),
     "lskum_plan_destroy": (ctypes.c_int, "v"),
     "lskum_plan_set_params": (ctypes.c_int, "vv"),
+    "lskum_plan_set_tuning": (ctypes.c_int, "vv"),
     "lskum_plan_n": (ctypes.c_int32, "v"),
+    "lskum_plan_clouds": (ctypes.c_int32, "v"),
+    "lskum_plan_offset": (ctypes.c_int32, "vi"),
     "lskum_init_state": (ctypes.c_int, "vvv"),
     "lskum_q_vars": (ctypes.c_int, "vvvv"),
     "lskum_q_derivs": (ctypes.c_int, "vvvvvv"),
@@ -66,6 +74,9 @@ _SIGS = {
     "lskum_force_coeffs": (ctypes.c_int, "vvvv"),
     "lskum_workspace_bytes": (ctypes.c_size_t, "v"),
     "lskum_iterate": (ctypes.c_int, "vivvvv"),
+    "lskum_graph_create": (ctypes.c_int, "vvivvivv"),
+    "lskum_graph_launch": (ctypes.c_int, "vv"),
+    "lskum_graph_destroy": (ctypes.c_int, "v"),
     "lskum_status": (ctypes.c_int, "vv"),
     "lskum_clear_status": (ctypes.c_int, "vv"),
     "lskum_strerror": (ctypes.c_char_p, "i"),
@@ -128,37 +139,77 @@ class Params:
                        self.venkat_k, int(self.n_inner), 0)
 
 
+@dataclass
+class Tuning:
+    """Block size (points per LDS tile: 128, 256, 512) and XCD-contiguous
+    block mapping; results do not depend on it."""
+    block: int = 256
+    xcd_contiguous: int = 1
+
+    def c(self) -> _Tuning:
+        return _Tuning(int(self.block), int(self.xcd_contiguous))
+
+
+def _cloud_struct(cloud):
+    n = int(cloud.x.shape[0])
+    k_pad = int(getattr(cloud, "k_pad", 0)) or int(cloud.col.size // n)
+    keep = dict(
+        x=np.ascontiguousarray(cloud.x, np.float64), y=np.ascontiguousarray(cloud.y, np.float64),
+        nx=np.ascontiguousarray(cloud.nx, np.float64), ny=np.ascontiguousarray(cloud.ny, np.float64),
+        kind=np.ascontiguousarray(cloud.kind, np.int8),
+        row_ptr=np.ascontiguousarray(cloud.row_ptr, np.int64),
+        col=np.ascontiguousarray(cloud.col, np.int32),
+        nbr_count=np.ascontiguousarray(cloud.nbr_count, np.int32),
+        wall_loop=np.ascontiguousarray(cloud.wall_loop, np.int32))
+    c = _Cloud(n, k_pad, *(keep[k].ctypes.data for k in
+                           ("x", "y", "nx", "ny", "kind", "row_ptr", "col", "nbr_count",
+                            "wall_loop")), int(keep["wall_loop"].size))
+    return c, keep
+
+
 class Plan:
-    """Owner of an ``lskum_plan`` handle (device geometry + connectivity)."""
+    """Owner of an ``lskum_plan`` handle (device geometry + connectivity).
 
-    def __init__(self, cloud, params: Params, stream=None):
+    ``cloud`` is one cloud or a list of clouds (a batched plan: the clouds are
+    concatenated in order; ``params`` is then one Params per cloud or one
+    shared by all)."""
+
+    def __init__(self, cloud, params, stream=None, tuning: Tuning | None = None):
         self.lib = load()
-        self.n = int(cloud.x.shape[0])
-        self.params = params
+        clouds = list(cloud) if isinstance(cloud, (list, tuple)) else [cloud]
+        plist = list(params) if isinstance(params, (list, tuple)) else [params] * len(clouds)
+        if len(plist) != len(clouds):
+            raise ValueError("one Params per cloud")
         self.device = torch.cuda.current_device()
-        k_pad = int(getattr(cloud, "k_pad", 0)) or int(cloud.col.size // self.n)
-        keep = dict(
-            x=np.ascontiguousarray(cloud.x, np.float64), y=np.ascontiguousarray(cloud.y, np.float64),
-            nx=np.ascontiguousarray(cloud.nx, np.float64), ny=np.ascontiguousarray(cloud.ny, np.float64),
-            kind=np.ascontiguousarray(cloud.kind, np.int8),
-            row_ptr=np.ascontiguousarray(cloud.row_ptr, np.int64),
-            col=np.ascontiguousarray(cloud.col, np.int32),
-            nbr_count=np.ascontiguousarray(cloud.nbr_count, np.int32),
-            wall_loop=np.ascontiguousarray(cloud.wall_loop, np.int32))
-        c = _Cloud(self.n, k_pad, *(keep[k].ctypes.data for k in
-                                    ("x", "y", "nx", "ny", "kind", "row_ptr", "col", "nbr_count",
-                                     "wall_loop")), int(keep["wall_loop"].size))
+        structs, keeps = zip(*(_cloud_struct(c) for c in clouds))
+        carr = (_Cloud * len(structs))(*structs)
+        parr = (_Params * len(plist))(*(p.c() for p in plist))
+        self._keep = keeps
         h = ctypes.c_void_p()
-        p = params.c()
-        rc = self.lib.lskum_plan_create(ctypes.byref(h), ctypes.byref(c), ctypes.byref(p),
-                                        _stream(stream))
-        _check(rc, "lskum_plan_create")
+        tun = tuning.c() if tuning is not None else None
+        rc = self.lib.lskum_batch_plan_create(ctypes.byref(h), len(structs), carr, parr,
+                                              ctypes.byref(tun) if tun is not None else None,
+                                              _stream(stream))
+        _check(rc, "lskum_batch_plan_create")
         self.handle = h
+        self.params = plist
+        self.tuning = tuning or Tuning()
+        self.n = int(self.lib.lskum_plan_n(h))
+        self.n_clouds = int(self.lib.lskum_plan_clouds(h))
+        self.offsets = [int(self.lib.lskum_plan_offset(h, c)) for c in range(self.n_clouds + 1)]
 
-    def set_params(self, params: Params):
-        p = params.c()
-        _check(self.lib.lskum_plan_set_params(self.handle, ctypes.byref(p)), "lskum_plan_set_params")
-        self.params = params
+    def set_params(self, params):
+        plist = list(params) if isinstance(params, (list, tuple)) else [params] * self.n_clouds
+        arr = (_Params * len(plist))(*(p.c() for p in plist))
+        if len(plist) != self.n_clouds:
+            raise ValueError("one Params per cloud")
+        _check(self.lib.lskum_plan_set_params(self.handle, arr), "lskum_plan_set_params")
+        self.params = plist
+
+    def set_tuning(self, tuning: Tuning):
+        t = tuning.c()
+        _check(self.lib.lskum_plan_set_tuning(self.handle, ctypes.byref(t)), "lskum_plan_set_tuning")
+        self.tuning = tuning
 
     def destroy(self):
         if getattr(self, "handle", None):
@@ -170,6 +221,9 @@ class Plan:
             self.destroy()
         except Exception:
             pass
+
+    def cloud_slice(self, c: int) -> slice:
+        return slice(self.offsets[c], self.offsets[c + 1])
 
     # tensor helpers (allocation is torch's; the library never allocates fields)
     def field(self, comps: int) -> torch.Tensor:
@@ -229,15 +283,17 @@ def _scalar_out(plan: Plan, t, count: int, name: str) -> int:
 
 
 def lskum_residual_norm(plan: Plan, R, out, stream=None):
+    """Per-cloud norms into out[0:n_clouds]."""
     _check(plan.lib.lskum_residual_norm(plan.handle, plan._arg(R, 4, "R"),
-                                        _scalar_out(plan, out, 1, "out"), _stream(stream)),
-           "lskum_residual_norm")
+                                        _scalar_out(plan, out, plan.n_clouds, "out"),
+                                        _stream(stream)), "lskum_residual_norm")
 
 
 def lskum_force_coeffs(plan: Plan, U, clcd, stream=None):
+    """Per-cloud (Cl, Cd) into clcd[2c], clcd[2c+1]."""
     _check(plan.lib.lskum_force_coeffs(plan.handle, plan._arg(U, 4, "U"),
-                                       _scalar_out(plan, clcd, 2, "clcd"), _stream(stream)),
-           "lskum_force_coeffs")
+                                       _scalar_out(plan, clcd, 2 * plan.n_clouds, "clcd"),
+                                       _stream(stream)), "lskum_force_coeffs")
 
 
 def lskum_workspace_bytes(plan: Plan) -> int:
@@ -252,7 +308,8 @@ def workspace(plan: Plan) -> torch.Tensor:
 
 
 def lskum_iterate(plan: Plan, iters: int, U, hist, ws, stream=None):
-    hp = 0 if hist is None else _scalar_out(plan, hist, int(iters), "hist")
+    """hist: iters x n_clouds residual norms (or None)."""
+    hp = 0 if hist is None else _scalar_out(plan, hist, int(iters) * plan.n_clouds, "hist")
     if not isinstance(ws, torch.Tensor) or not ws.is_cuda or ws.numel() < lskum_workspace_bytes(plan):
         raise ValueError("ws: need a cuda tensor of lskum_workspace_bytes(plan) bytes")
     _check(plan.lib.lskum_iterate(plan.handle, int(iters), plan._arg(U, 4, "U"), hp, ws.data_ptr(),
@@ -267,3 +324,65 @@ def lskum_status(plan: Plan, stream=None) -> int:
 
 def lskum_clear_status(plan: Plan, stream=None):
     _check(plan.lib.lskum_clear_status(plan.handle, _stream(stream)), "lskum_clear_status")
+
+
+class Graph:
+    """A captured run of `iters` iterations (lskum_graph_create); each
+    launch() replays them and appends residual-norm rows to hist."""
+
+    def __init__(self, plan: Plan, iters: int, U, hist, ws, stream=None):
+        self.plan = plan
+        rows = 0 if hist is None else hist.numel() // plan.n_clouds
+        hp = 0 if hist is None else _scalar_out(plan, hist, plan.n_clouds, "hist")
+        if not isinstance(ws, torch.Tensor) or not ws.is_cuda or ws.numel() < lskum_workspace_bytes(plan):
+            raise ValueError("ws: need a cuda tensor of lskum_workspace_bytes(plan) bytes")
+        g = ctypes.c_void_p()
+        _check(plan.lib.lskum_graph_create(ctypes.byref(g), plan.handle, int(iters),
+                                           plan._arg(U, 4, "U"), hp, int(rows), ws.data_ptr(),
+                                           _stream(stream)), "lskum_graph_create")
+        self.handle = g
+        self._keep = (U, hist, ws)
+
+    def launch(self, stream=None):
+        _check(self.plan.lib.lskum_graph_launch(self.handle, _stream(stream)), "lskum_graph_launch")
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            self.plan.lib.lskum_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+TUNING_SPACE = [Tuning(b, x) for b in (128, 256, 512) for x in (1, 0)]
+
+
+def autotune(plan: Plan, U, ws, iters: int = 2, reps: int = 3, space=None, stream=None):
+    """Time `iters` iterations for every tuning in `space` (default: block
+    128/256/512 x XCD mapping on/off) on a scratch copy of U, keep the
+    fastest on the plan and return (best, {tuning: ms})."""
+    space = space or TUNING_SPACE
+    scratch = U.clone()
+    times = {}
+    for t in space:
+        plan.set_tuning(t)
+        ms = []
+        for _ in range(reps):
+            scratch.copy_(U)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            lskum_iterate(plan, iters, scratch, None, ws, stream)
+            b.record()
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        times[(t.block, t.xcd_contiguous)] = min(ms)
+    best_key = min(times, key=times.get)
+    best = Tuning(*best_key)
+    plan.set_tuning(best)
+    lskum_clear_status(plan, stream)
+    return best, times
