@@ -28,6 +28,7 @@
 
 #include "lskum_ref.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstddef>
 #include <limits>
@@ -38,15 +39,109 @@ namespace {
 const double kPi = 3.14159265358979323846;
 
 // ---------------------------------------------------------------------------
+// Reverse-mode scalar for the adjoint routines.
+//
+// Every operation on a tape variable appends a node holding the indices of
+// its (at most two) operands and the partial derivatives with respect to
+// them; constants (index -1) are not recorded.  Values are computed with the
+// same double operations as the plain routines, so a taped evaluation
+// reproduces their results exactly.  Branches (limiter, max/min, split
+// stencil membership) follow the values, so the derivative is that of the
+// active branch.
+
+namespace ad {
+
+struct Tape {
+  std::vector<int32_t> a, b;
+  std::vector<double> ga, gb, adj;
+  void clear() {
+    a.clear();
+    b.clear();
+    ga.clear();
+    gb.clear();
+    adj.clear();
+  }
+  int32_t push(int32_t ia, double da, int32_t ib, double db) {
+    a.push_back(ia);
+    ga.push_back(da);
+    b.push_back(ib);
+    gb.push_back(db);
+    return (int32_t)a.size() - 1;
+  }
+  // adjoints of every node given seeds already placed in adj
+  void reverse() {
+    for (int32_t k = (int32_t)a.size() - 1; k >= 0; --k) {
+      const double g = adj[(size_t)k];
+      if (g == 0.0) continue;
+      if (a[(size_t)k] >= 0) adj[(size_t)a[(size_t)k]] += ga[(size_t)k] * g;
+      if (b[(size_t)k] >= 0) adj[(size_t)b[(size_t)k]] += gb[(size_t)k] * g;
+    }
+  }
+};
+
+Tape *tape = nullptr;  // the oracle is single-threaded
+
+struct Var {
+  double v;
+  int32_t i;
+  Var() : v(0.0), i(-1) {}
+  Var(double x) : v(x), i(-1) {}  // NOLINT: constants convert implicitly
+  Var(double x, int32_t idx) : v(x), i(idx) {}
+};
+
+inline Var input(double x) { return Var(x, tape->push(-1, 0.0, -1, 0.0)); }
+inline Var make(double v, int32_t ia, double da, int32_t ib, double db) {
+  if (ia < 0 && ib < 0) return Var(v);
+  return Var(v, tape->push(ia, da, ib, db));
+}
+inline Var operator+(Var x, Var y) { return make(x.v + y.v, x.i, 1.0, y.i, 1.0); }
+inline Var operator-(Var x, Var y) { return make(x.v - y.v, x.i, 1.0, y.i, -1.0); }
+inline Var operator*(Var x, Var y) { return make(x.v * y.v, x.i, y.v, y.i, x.v); }
+inline Var operator/(Var x, Var y) {
+  const double v = x.v / y.v;
+  return make(v, x.i, 1.0 / y.v, y.i, -v / y.v);
+}
+inline Var operator-(Var x) { return make(-x.v, x.i, -1.0, -1, 0.0); }
+inline Var &operator+=(Var &x, Var y) { return x = x + y; }
+inline bool operator<(Var x, Var y) { return x.v < y.v; }
+inline bool operator>(Var x, Var y) { return x.v > y.v; }
+inline Var exp(Var x) {
+  const double e = std::exp(x.v);
+  return make(e, x.i, e, -1, 0.0);
+}
+inline Var log(Var x) { return make(std::log(x.v), x.i, 1.0 / x.v, -1, 0.0); }
+inline Var sqrt(Var x) {
+  const double r = std::sqrt(x.v);
+  return make(r, x.i, 0.5 / r, -1, 0.0);
+}
+inline Var erf(Var x) {
+  return make(std::erf(x.v), x.i, 2.0 / std::sqrt(kPi) * std::exp(-x.v * x.v), -1, 0.0);
+}
+inline Var cos(Var x) { return make(std::cos(x.v), x.i, -std::sin(x.v), -1, 0.0); }
+inline Var sin(Var x) { return make(std::sin(x.v), x.i, std::cos(x.v), -1, 0.0); }
+inline double val(Var x) { return x.v; }
+
+}  // namespace ad
+
+inline double val(double x) { return x; }
+
+// ---------------------------------------------------------------------------
 // Point-level formulas
 
 // Free stream, non-dimensionalised by the free-stream density and sound
 // speed: rho = 1, p = 1/gamma (so a = 1), velocity = M (cos a, sin a).
+template <class T>
+void free_stream_prim_t(double gamma, T mach, T aoa, T w[4]) {
+  using std::cos;
+  using std::sin;
+  w[0] = T(1.0);
+  w[1] = mach * cos(aoa);
+  w[2] = mach * sin(aoa);
+  w[3] = T(1.0 / gamma);
+}
+
 void free_stream_prim(const lskum_ref_params &P, double w[4]) {
-  w[0] = 1.0;
-  w[1] = P.mach * std::cos(P.aoa_rad);
-  w[2] = P.mach * std::sin(P.aoa_rad);
-  w[3] = 1.0 / P.gamma;
+  free_stream_prim_t<double>(P.gamma, P.mach, P.aoa_rad, w);
 }
 
 // U = (rho, rho u, rho v, E), E = p/(gamma-1) + rho (u^2 + v^2)/2  (eq. (1))
@@ -174,15 +269,290 @@ inline double &fld(double *f, int32_t comp, int32_t n, int32_t i) {
 }
 
 // Pairwise (recursive halving) summation, fixed order.
-double pairwise_sum(const double *v, size_t n) {
-  if (n == 0) return 0.0;
+template <class T>
+T pairwise_sum(const T *v, size_t n) {
+  if (n == 0) return T(0.0);
   if (n <= 8) {
-    double s = 0.0;
+    T s = T(0.0);
     for (size_t k = 0; k < n; ++k) s += v[k];
     return s;
   }
   size_t h = n / 2;
   return pairwise_sum(v, h) + pairwise_sum(v + h, n - h);
+}
+
+// ---------------------------------------------------------------------------
+// Per-point formulas of the sweeps.  A point function reads the data of its
+// stencil through an accessor: st.own(f, m) for the point itself and
+// st.nbr(k, f, m) for its k-th real neighbour, field f = 0 (q, m < 4),
+// 1 (dq, m < 8) or 2 (qlim, m < 8).  The plain sweeps pass array accessors;
+// the adjoint routines pass accessors that return tape variables.
+
+enum Field { kQ = 0, kG = 1, kL = 2 };
+
+struct ArraySt {
+  const double *f[3];
+  int32_t n, i;
+  const int32_t *ids;
+  double own(int fld_, int m) const { return f[fld_][(size_t)m * n + i]; }
+  double nbr(int k, int fld_, int m) const { return f[fld_][(size_t)m * n + ids[k]]; }
+};
+
+const int kWidth[3] = {4, 8, 8};
+
+// eq. (13) at one point; flags a non-physical state.
+template <class T>
+unsigned q_point(double g, const T U[4], T q[4]) {
+  T w[4];
+  prim_from_cons(g, U, w);
+  const unsigned flags =
+      (!finite_positive(val(w[0])) || !finite_positive(val(w[3]))) ? LSKUM_REF_NONPHYSICAL : 0u;
+  q_from_prim(g, w, q);
+  return flags;
+}
+
+// First-order least squares (eq. (9) with the plain differences
+// dq_i = q_i - q_0) over the full stencil, and the stencil bounds
+// max/min of q over {P0} U N(P0) (the first point reaching the bound wins).
+template <class T, class St>
+void deriv_first_point(const lskum_ref_cloud &c, int32_t i, const St &st, T dq[8], T qlim[8]) {
+  Row r = row(c, i);
+  double sxx = 0.0, sxy = 0.0, syy = 0.0;
+  T sxq[4] = {T(0.0), T(0.0), T(0.0), T(0.0)}, syq[4] = {T(0.0), T(0.0), T(0.0), T(0.0)};
+  T qmax[4], qmin[4];
+  for (int m = 0; m < 4; ++m) qmax[m] = qmin[m] = st.own(kQ, m);
+  for (int32_t k = 0; k < r.count; ++k) {
+    int32_t j = r.ids[k];
+    double dx = c.x[j] - c.x[i];
+    double dy = c.y[j] - c.y[i];
+    sxx += dx * dx;
+    sxy += dx * dy;
+    syy += dy * dy;
+    for (int m = 0; m < 4; ++m) {
+      T qj = st.nbr(k, kQ, m);
+      T d = qj - st.own(kQ, m);
+      sxq[m] += dx * d;
+      syq[m] += dy * d;
+      if (qj > qmax[m]) qmax[m] = qj;
+      if (qj < qmin[m]) qmin[m] = qj;
+    }
+  }
+  double det = sxx * syy - sxy * sxy;
+  for (int m = 0; m < 4; ++m) {
+    dq[m] = (syy * sxq[m] - sxy * syq[m]) / det;
+    dq[4 + m] = (sxx * syq[m] - sxy * sxq[m]) / det;
+    qlim[m] = qmax[m];
+    qlim[4 + m] = qmin[m];
+  }
+}
+
+// One inner iteration (eq. (14)-(15)) at one point: the modified
+// differences use the previous iterate of the derivatives (field kG) at
+// both ends of each edge,
+//   dq~_i = [q_i - (dx q_x,i + dy q_y,i)/2] - [q_0 - (dx q_x,0 + dy q_y,0)/2].
+template <class T, class St>
+void deriv_inner_point(const lskum_ref_cloud &c, int32_t i, const St &st, T dq[8]) {
+  Row r = row(c, i);
+  double sxx = 0.0, sxy = 0.0, syy = 0.0;
+  T sxq[4] = {T(0.0), T(0.0), T(0.0), T(0.0)}, syq[4] = {T(0.0), T(0.0), T(0.0), T(0.0)};
+  for (int32_t k = 0; k < r.count; ++k) {
+    int32_t j = r.ids[k];
+    double dx = c.x[j] - c.x[i];
+    double dy = c.y[j] - c.y[i];
+    sxx += dx * dx;
+    sxy += dx * dy;
+    syy += dy * dy;
+    for (int m = 0; m < 4; ++m) {
+      T qt_j = st.nbr(k, kQ, m) - 0.5 * (dx * st.nbr(k, kG, m) + dy * st.nbr(k, kG, 4 + m));
+      T qt_0 = st.own(kQ, m) - 0.5 * (dx * st.own(kG, m) + dy * st.own(kG, 4 + m));
+      T d = qt_j - qt_0;
+      sxq[m] += dx * d;
+      syq[m] += dy * d;
+    }
+  }
+  double det = sxx * syy - sxy * sxy;
+  for (int m = 0; m < 4; ++m) {
+    dq[m] = (syy * sxq[m] - sxy * syq[m]) / det;
+    dq[4 + m] = (sxx * syq[m] - sxy * sxq[m]) / det;
+  }
+}
+
+// Flux residual at one point (see lskum_ref_flux_residual).
+template <class T, class St>
+unsigned flux_point(const lskum_ref_cloud &c, const lskum_ref_params &P, int32_t i, const St &st,
+                    T R[4]) {
+  const double g = P.gamma;
+  unsigned flags = 0;
+  const int kind = c.kind[i];
+  if (kind == 2) {
+    for (int m = 0; m < 4; ++m) R[m] = T(0.0);
+    return 0;
+  }
+  const double nx = c.nx[i], ny = c.ny[i];
+  const double tx = ny, ty = -nx;
+  // split order: 0 = s+, 1 = s-, 2 = n+, 3 = n-
+  double sss[4] = {0, 0, 0, 0}, ssn[4] = {0, 0, 0, 0}, snn[4] = {0, 0, 0, 0};
+  T as[4][4], an[4][4];
+  for (int sp = 0; sp < 4; ++sp)
+    for (int m = 0; m < 4; ++m) as[sp][m] = an[sp][m] = T(0.0);
+  int cnt[4] = {0, 0, 0, 0};
+  Row r = row(c, i);
+  for (int32_t k = 0; k < r.count; ++k) {
+    int32_t j = r.ids[k];
+    double dx = c.x[j] - c.x[i];
+    double dy = c.y[j] - c.y[i];
+    double ds = dx * tx + dy * ty;
+    double dn = dx * nx + dy * ny;
+    double dist = std::sqrt(dx * dx + dy * dy);
+    double kd = P.venkat_k * dist;
+    double eps2 = kd * kd * kd;
+    T qt_j[4], qt_0[4];
+    for (int m = 0; m < 4; ++m) {
+      T qj = st.nbr(k, kQ, m), q0 = st.own(kQ, m);
+      T del_j = -0.5 * (dx * st.nbr(k, kG, m) + dy * st.nbr(k, kG, 4 + m));
+      T del_0 = -0.5 * (dx * st.own(kG, m) + dy * st.own(kG, 4 + m));
+      T phi_j = venkat_phi(del_j, st.nbr(k, kL, m) - qj, st.nbr(k, kL, 4 + m) - qj, T(eps2));
+      T phi_0 = venkat_phi(del_0, st.own(kL, m) - q0, st.own(kL, 4 + m) - q0, T(eps2));
+      qt_j[m] = qj + phi_j * del_j;
+      qt_0[m] = q0 + phi_0 * del_0;
+    }
+    T wj[4], w0[4];
+    prim_from_q(g, qt_j, wj);
+    prim_from_q(g, qt_0, w0);
+    if (!(qt_j[3] < 0.0) || !(qt_0[3] < 0.0) || !finite_positive(val(wj[0])) ||
+        !finite_positive(val(w0[0])) || !finite_positive(val(wj[3])) ||
+        !finite_positive(val(w0[3])))
+      flags |= LSKUM_REF_NONPHYSICAL;
+    // velocities in P0's frame
+    T lj[4] = {wj[0], wj[1] * tx + wj[2] * ty, wj[1] * nx + wj[2] * ny, wj[3]};
+    T l0[4] = {w0[0], w0[1] * tx + w0[2] * ty, w0[1] * nx + w0[2] * ny, w0[3]};
+    int sel[2] = {-1, -1};
+    if (ds < 0.0) sel[0] = 0;
+    if (ds > 0.0) sel[0] = 1;
+    if (dn < 0.0 && kind == 0) sel[1] = 2;
+    if (dn > 0.0) sel[1] = 3;
+    for (int h = 0; h < 2; ++h) {
+      int sp = sel[h];
+      if (sp < 0) continue;
+      int dir = sp < 2 ? 0 : 1;
+      int sign = (sp == 0 || sp == 2) ? 1 : -1;
+      T Gj[4], G0[4];
+      split_flux(g, dir, sign, lj, Gj);
+      split_flux(g, dir, sign, l0, G0);
+      sss[sp] += ds * ds;
+      ssn[sp] += ds * dn;
+      snn[sp] += dn * dn;
+      cnt[sp] += 1;
+      for (int m = 0; m < 4; ++m) {
+        T dG = Gj[m] - G0[m];
+        as[sp][m] += ds * dG;
+        an[sp][m] += dn * dG;
+      }
+    }
+  }
+  T Rf[4] = {T(0.0), T(0.0), T(0.0), T(0.0)};
+  for (int sp = 0; sp < 4; ++sp) {
+    if (sp == 2 && kind != 0) continue;
+    double det = sss[sp] * snn[sp] - ssn[sp] * ssn[sp];
+    if (cnt[sp] < 2 || !(det > 1e-12 * sss[sp] * snn[sp])) {
+      flags |= LSKUM_REF_DEGENERATE;
+      continue;
+    }
+    for (int m = 0; m < 4; ++m) {
+      T d;
+      if (sp < 2)
+        d = (snn[sp] * as[sp][m] - ssn[sp] * an[sp][m]) / det;
+      else
+        d = (sss[sp] * an[sp][m] - ssn[sp] * as[sp][m]) / det;
+      Rf[m] += d;
+    }
+  }
+  R[0] = Rf[0];
+  R[1] = Rf[1] * tx + Rf[2] * nx;
+  R[2] = Rf[1] * ty + Rf[2] * ny;
+  R[3] = Rf[3];
+  return flags;
+}
+
+
+// ---------------------------------------------------------------------------
+// Adjoint helpers: a stencil accessor whose values are tape inputs.  One
+// point function is evaluated on a fresh tape, its outputs are seeded with
+// their cotangents, the tape is swept backwards, and the adjoints of the
+// inputs are added to the cotangent arrays of the points they came from.
+
+struct TapeSt {
+  static int off(int f, int m) { return f == kQ ? m : (f == kG ? 4 + m : 12 + m); }
+  int32_t n, i;
+  Row r;
+  unsigned mask;  // bit f: field f is read by the point function
+  std::vector<ad::Var> v;  // (count + 1) slots x 20 values: own, then neighbours
+  TapeSt(const double *const f[3], int32_t n_, int32_t i_, Row r_, unsigned mask_)
+      : n(n_), i(i_), r(r_), mask(mask_), v((size_t)(r_.count + 1) * 20) {
+    for (int32_t s = 0; s <= r.count; ++s) {
+      const int32_t pnt = s == 0 ? i : r.ids[s - 1];
+      for (int fl = 0; fl < 3; ++fl) {
+        if (!(mask & (1u << fl))) continue;
+        for (int m = 0; m < kWidth[fl]; ++m)
+          v[(size_t)s * 20 + off(fl, m)] = ad::input(f[fl][(size_t)m * n + pnt]);
+      }
+    }
+  }
+  ad::Var own(int fl, int m) const { return v[(size_t)off(fl, m)]; }
+  ad::Var nbr(int k, int fl, int m) const { return v[(size_t)(k + 1) * 20 + off(fl, m)]; }
+  void scatter(double *const bar[3]) const {
+    for (int32_t s = 0; s <= r.count; ++s) {
+      const int32_t pnt = s == 0 ? i : r.ids[s - 1];
+      for (int fl = 0; fl < 3; ++fl) {
+        if (!(mask & (1u << fl)) || !bar[fl]) continue;
+        for (int m = 0; m < kWidth[fl]; ++m)
+          bar[fl][(size_t)m * n + pnt] += ad::tape->adj[(size_t)v[(size_t)s * 20 + off(fl, m)].i];
+      }
+    }
+  }
+};
+
+// Start a tape sweep: zero adjoints, then seed.
+void seed_begin() { ad::tape->adj.assign(ad::tape->a.size(), 0.0); }
+void seed(const ad::Var &x, double s) {
+  if (x.i >= 0) ad::tape->adj[(size_t)x.i] += s;
+}
+double adjoint(const ad::Var &x) { return x.i >= 0 ? ad::tape->adj[(size_t)x.i] : 0.0; }
+
+// Lift and drag from the wall polygon W_0..W_{m-1} (counter-clockwise):
+// edge e = (W_j, W_j+1) has outward normal-length vector (dy_e, -dx_e) and
+// pressure p_e = (p_j + p_j+1)/2; Cp_e = (p_e - p_inf)/(rho_inf M^2 / 2);
+// (Cx, Cy) = -sum_e Cp_e nu_e (chord 1); Cl = Cy cos a - Cx sin a,
+// Cd = Cx cos a + Cy sin a.  Uw(j, k) returns component k of U at point j.
+template <class T, class UW>
+void force_t(const lskum_ref_cloud &c, double gamma, T mach, T aoa, const UW &Uw, T clcd[2]) {
+  using std::cos;
+  using std::sin;
+  const int32_t m = c.n_wall;
+  const double pinf = 1.0 / gamma;
+  T qinf = 0.5 * 1.0 * mach * mach;
+  std::vector<T> fx((size_t)m), fy((size_t)m);
+  for (int32_t e = 0; e < m; ++e) {
+    int32_t a = c.wall_loop[e], b = c.wall_loop[(e + 1) % m];
+    T Ua[4], Ub[4], wa[4], wb[4];
+    for (int k = 0; k < 4; ++k) {
+      Ua[k] = Uw(a, k);
+      Ub[k] = Uw(b, k);
+    }
+    prim_from_cons(gamma, Ua, wa);
+    prim_from_cons(gamma, Ub, wb);
+    T pe = 0.5 * (wa[3] + wb[3]);
+    T cp = (pe - pinf) / qinf;
+    double ex = c.x[b] - c.x[a];
+    double ey = c.y[b] - c.y[a];
+    fx[(size_t)e] = -cp * ey;
+    fy[(size_t)e] = cp * ex;
+  }
+  T Cx = pairwise_sum(fx.data(), fx.size());
+  T Cy = pairwise_sum(fy.data(), fy.size());
+  T ca = cos(aoa), sa = sin(aoa);
+  clcd[0] = Cy * ca - Cx * sa;
+  clcd[1] = Cx * ca + Cy * sa;
 }
 
 }  // namespace
@@ -247,88 +617,36 @@ unsigned lskum_ref_q_vars(const lskum_ref_cloud *c, const lskum_ref_params *p, c
   unsigned flags = 0;
   const int32_t n = c->n;
   for (int32_t i = 0; i < n; ++i) {
-    double Ui[4], w[4], qi[4];
+    double Ui[4], qi[4];
     for (int m = 0; m < 4; ++m) Ui[m] = fld(U, m, n, i);
-    prim_from_cons(p->gamma, Ui, w);
-    if (!finite_positive(w[0]) || !finite_positive(w[3])) flags |= LSKUM_REF_NONPHYSICAL;
-    q_from_prim(p->gamma, w, qi);
+    flags |= q_point(p->gamma, Ui, qi);
     for (int m = 0; m < 4; ++m) fld(q, m, n, i) = qi[m];
   }
   return flags;
 }
 
-// First-order least squares (eq. (9) with the plain differences
-// dq_i = q_i - q_0) over the full stencil, and the stencil bounds
-// max/min of q over {P0} U N(P0).
 void lskum_ref_q_derivs_first(const lskum_ref_cloud *c, const double *q, double *dq,
                               double *qlim) {
   const int32_t n = c->n;
   for (int32_t i = 0; i < n; ++i) {
-    Row r = row(*c, i);
-    double sxx = 0.0, sxy = 0.0, syy = 0.0;
-    double sxq[4] = {0, 0, 0, 0}, syq[4] = {0, 0, 0, 0};
-    double qmax[4], qmin[4];
-    for (int m = 0; m < 4; ++m) qmax[m] = qmin[m] = fld(q, m, n, i);
-    for (int32_t k = 0; k < r.count; ++k) {
-      int32_t j = r.ids[k];
-      double dx = c->x[j] - c->x[i];
-      double dy = c->y[j] - c->y[i];
-      sxx += dx * dx;
-      sxy += dx * dy;
-      syy += dy * dy;
-      for (int m = 0; m < 4; ++m) {
-        double qj = fld(q, m, n, j);
-        double d = qj - fld(q, m, n, i);
-        sxq[m] += dx * d;
-        syq[m] += dy * d;
-        if (qj > qmax[m]) qmax[m] = qj;
-        if (qj < qmin[m]) qmin[m] = qj;
-      }
-    }
-    double det = sxx * syy - sxy * sxy;
-    for (int m = 0; m < 4; ++m) {
-      fld(dq, m, n, i) = (syy * sxq[m] - sxy * syq[m]) / det;
-      fld(dq, 4 + m, n, i) = (sxx * syq[m] - sxy * sxq[m]) / det;
-      fld(qlim, m, n, i) = qmax[m];
-      fld(qlim, 4 + m, n, i) = qmin[m];
+    ArraySt st{{q, nullptr, nullptr}, n, i, c->col + c->row_ptr[i]};
+    double d[8], l[8];
+    deriv_first_point(*c, i, st, d, l);
+    for (int m = 0; m < 8; ++m) {
+      fld(dq, m, n, i) = d[m];
+      fld(qlim, m, n, i) = l[m];
     }
   }
 }
 
-// One inner iteration (eq. (14)-(15)): the modified differences use the
-// previous iterate of the derivatives at both ends of each edge,
-//   dq~_i = [q_i - (dx q_x,i + dy q_y,i)/2] - [q_0 - (dx q_x,0 + dy q_y,0)/2],
-// and the same least-squares solve gives the next iterate (Jacobi: every
-// point reads only the previous iterate).
 void lskum_ref_q_derivs_inner(const lskum_ref_cloud *c, const double *q, const double *dq_prev,
                               double *dq_next) {
   const int32_t n = c->n;
   for (int32_t i = 0; i < n; ++i) {
-    Row r = row(*c, i);
-    double sxx = 0.0, sxy = 0.0, syy = 0.0;
-    double sxq[4] = {0, 0, 0, 0}, syq[4] = {0, 0, 0, 0};
-    for (int32_t k = 0; k < r.count; ++k) {
-      int32_t j = r.ids[k];
-      double dx = c->x[j] - c->x[i];
-      double dy = c->y[j] - c->y[i];
-      sxx += dx * dx;
-      sxy += dx * dy;
-      syy += dy * dy;
-      for (int m = 0; m < 4; ++m) {
-        double qt_j = fld(q, m, n, j) -
-                      0.5 * (dx * fld(dq_prev, m, n, j) + dy * fld(dq_prev, 4 + m, n, j));
-        double qt_0 = fld(q, m, n, i) -
-                      0.5 * (dx * fld(dq_prev, m, n, i) + dy * fld(dq_prev, 4 + m, n, i));
-        double d = qt_j - qt_0;
-        sxq[m] += dx * d;
-        syq[m] += dy * d;
-      }
-    }
-    double det = sxx * syy - sxy * sxy;
-    for (int m = 0; m < 4; ++m) {
-      fld(dq_next, m, n, i) = (syy * sxq[m] - sxy * syq[m]) / det;
-      fld(dq_next, 4 + m, n, i) = (sxx * syq[m] - sxy * sxq[m]) / det;
-    }
+    ArraySt st{{q, dq_prev, nullptr}, n, i, c->col + c->row_ptr[i]};
+    double d[8];
+    deriv_inner_point(*c, i, st, d);
+    for (int m = 0; m < 8; ++m) fld(dq_next, m, n, i) = d[m];
   }
 }
 
@@ -359,96 +677,12 @@ unsigned lskum_ref_flux_residual(const lskum_ref_cloud *c, const lskum_ref_param
                                  const double *q, const double *dq, const double *qlim,
                                  double *R) {
   const int32_t n = c->n;
-  const double g = p->gamma;
   unsigned flags = 0;
   for (int32_t i = 0; i < n; ++i) {
-    const int kind = c->kind[i];
-    if (kind == 2) {
-      for (int m = 0; m < 4; ++m) fld(R, m, n, i) = 0.0;
-      continue;
-    }
-    const double nx = c->nx[i], ny = c->ny[i];
-    const double tx = ny, ty = -nx;
-    // split order: 0 = s+, 1 = s-, 2 = n+, 3 = n-
-    double sss[4] = {0, 0, 0, 0}, ssn[4] = {0, 0, 0, 0}, snn[4] = {0, 0, 0, 0};
-    double as[4][4] = {{0}}, an[4][4] = {{0}};
-    int cnt[4] = {0, 0, 0, 0};
-    Row r = row(*c, i);
-    for (int32_t k = 0; k < r.count; ++k) {
-      int32_t j = r.ids[k];
-      double dx = c->x[j] - c->x[i];
-      double dy = c->y[j] - c->y[i];
-      double ds = dx * tx + dy * ty;
-      double dn = dx * nx + dy * ny;
-      double dist = std::sqrt(dx * dx + dy * dy);
-      double kd = p->venkat_k * dist;
-      double eps2 = kd * kd * kd;
-      double qt_j[4], qt_0[4];
-      for (int m = 0; m < 4; ++m) {
-        double qj = fld(q, m, n, j), q0 = fld(q, m, n, i);
-        double del_j = -0.5 * (dx * fld(dq, m, n, j) + dy * fld(dq, 4 + m, n, j));
-        double del_0 = -0.5 * (dx * fld(dq, m, n, i) + dy * fld(dq, 4 + m, n, i));
-        double phi_j = venkat_phi(del_j, fld(qlim, m, n, j) - qj, fld(qlim, 4 + m, n, j) - qj,
-                                  eps2);
-        double phi_0 = venkat_phi(del_0, fld(qlim, m, n, i) - q0, fld(qlim, 4 + m, n, i) - q0,
-                                  eps2);
-        qt_j[m] = qj + phi_j * del_j;
-        qt_0[m] = q0 + phi_0 * del_0;
-      }
-      double wj[4], w0[4];
-      prim_from_q(g, qt_j, wj);
-      prim_from_q(g, qt_0, w0);
-      if (!(qt_j[3] < 0.0) || !(qt_0[3] < 0.0) || !finite_positive(wj[0]) ||
-          !finite_positive(w0[0]) || !finite_positive(wj[3]) || !finite_positive(w0[3]))
-        flags |= LSKUM_REF_NONPHYSICAL;
-      // velocities in P0's frame
-      double lj[4] = {wj[0], wj[1] * tx + wj[2] * ty, wj[1] * nx + wj[2] * ny, wj[3]};
-      double l0[4] = {w0[0], w0[1] * tx + w0[2] * ty, w0[1] * nx + w0[2] * ny, w0[3]};
-      int sel[2] = {-1, -1};
-      if (ds < 0.0) sel[0] = 0;
-      if (ds > 0.0) sel[0] = 1;
-      if (dn < 0.0 && kind == 0) sel[1] = 2;
-      if (dn > 0.0) sel[1] = 3;
-      for (int h = 0; h < 2; ++h) {
-        int sp = sel[h];
-        if (sp < 0) continue;
-        int dir = sp < 2 ? 0 : 1;
-        int sign = (sp == 0 || sp == 2) ? 1 : -1;
-        double Gj[4], G0[4];
-        split_flux(g, dir, sign, lj, Gj);
-        split_flux(g, dir, sign, l0, G0);
-        sss[sp] += ds * ds;
-        ssn[sp] += ds * dn;
-        snn[sp] += dn * dn;
-        cnt[sp] += 1;
-        for (int m = 0; m < 4; ++m) {
-          double dG = Gj[m] - G0[m];
-          as[sp][m] += ds * dG;
-          an[sp][m] += dn * dG;
-        }
-      }
-    }
-    double Rf[4] = {0, 0, 0, 0};
-    for (int sp = 0; sp < 4; ++sp) {
-      if (sp == 2 && kind != 0) continue;
-      double det = sss[sp] * snn[sp] - ssn[sp] * ssn[sp];
-      if (cnt[sp] < 2 || !(det > 1e-12 * sss[sp] * snn[sp])) {
-        flags |= LSKUM_REF_DEGENERATE;
-        continue;
-      }
-      for (int m = 0; m < 4; ++m) {
-        double d;
-        if (sp < 2)
-          d = (snn[sp] * as[sp][m] - ssn[sp] * an[sp][m]) / det;
-        else
-          d = (sss[sp] * an[sp][m] - ssn[sp] * as[sp][m]) / det;
-        Rf[m] += d;
-      }
-    }
-    fld(R, 0, n, i) = Rf[0];
-    fld(R, 1, n, i) = Rf[1] * tx + Rf[2] * nx;
-    fld(R, 2, n, i) = Rf[1] * ty + Rf[2] * ny;
-    fld(R, 3, n, i) = Rf[3];
+    ArraySt st{{q, dq, qlim}, n, i, c->col + c->row_ptr[i]};
+    double Ri[4];
+    flags |= flux_point(*c, *p, i, st, Ri);
+    for (int m = 0; m < 4; ++m) fld(R, m, n, i) = Ri[m];
   }
   return flags;
 }
@@ -517,38 +751,12 @@ double lskum_ref_residual_norm(const lskum_ref_cloud *c, const double *R) {
   return std::sqrt(pairwise_sum(v.data(), v.size()));
 }
 
-// Lift and drag from the wall polygon W_0..W_{m-1} (counter-clockwise):
-// edge e = (W_j, W_j+1) has outward normal-length vector (dy_e, -dx_e) and
-// pressure p_e = (p_j + p_j+1)/2; Cp_e = (p_e - p_inf)/(rho_inf M^2 / 2);
-// (Cx, Cy) = -sum_e Cp_e nu_e (chord 1); Cl = Cy cos a - Cx sin a,
-// Cd = Cx cos a + Cy sin a.
+// Lift and drag coefficients of the wall polygon (see force_t).
 void lskum_ref_force_coeffs(const lskum_ref_cloud *c, const lskum_ref_params *p,
                             const double *U, double clcd[2]) {
-  const int32_t n = c->n, m = c->n_wall;
-  const double pinf = 1.0 / p->gamma;
-  const double qinf = 0.5 * 1.0 * p->mach * p->mach;
-  std::vector<double> fx((size_t)m), fy((size_t)m);
-  for (int32_t e = 0; e < m; ++e) {
-    int32_t a = c->wall_loop[e], b = c->wall_loop[(e + 1) % m];
-    double Ua[4], Ub[4], wa[4], wb[4];
-    for (int k = 0; k < 4; ++k) {
-      Ua[k] = fld(U, k, n, a);
-      Ub[k] = fld(U, k, n, b);
-    }
-    prim_from_cons(p->gamma, Ua, wa);
-    prim_from_cons(p->gamma, Ub, wb);
-    double pe = 0.5 * (wa[3] + wb[3]);
-    double cp = (pe - pinf) / qinf;
-    double ex = c->x[b] - c->x[a];
-    double ey = c->y[b] - c->y[a];
-    fx[(size_t)e] = -cp * ey;
-    fy[(size_t)e] = cp * ex;
-  }
-  double Cx = pairwise_sum(fx.data(), fx.size());
-  double Cy = pairwise_sum(fy.data(), fy.size());
-  double ca = std::cos(p->aoa_rad), sa = std::sin(p->aoa_rad);
-  clcd[0] = Cy * ca - Cx * sa;
-  clcd[1] = Cx * ca + Cy * sa;
+  const int32_t n = c->n;
+  auto Uw = [&](int32_t j, int k) { return fld(U, k, n, j); };
+  force_t<double>(*c, p->gamma, p->mach, p->aoa_rad, Uw, clcd);
 }
 
 unsigned lskum_ref_iterate(const lskum_ref_cloud *c, const lskum_ref_params *p, int32_t iters,
@@ -568,6 +776,142 @@ unsigned lskum_ref_iterate(const lskum_ref_cloud *c, const lskum_ref_params *p, 
     }
   }
   return flags;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoints (reverse mode through the same point formulas, differentiating
+// the branch each limiter, max/min and stencil test takes).
+
+// Cotangent of the residual map (U_int, theta) -> R, where the rows of the
+// outer points are the free stream U_inf(theta), theta = (M, alpha):
+//   Ubar     = (dR/dU)^T Rbar at interior and wall rows, 0 at outer rows;
+//   thetabar = sum over outer rows j of (dR/dU_j)^T Rbar . dU_inf/dtheta.
+// The derivative recomputes q and every derivative iterate, then runs the
+// passes backwards: flux, inner sweeps n_inner..1, first-order pass
+// (derivatives and stencil bounds), q-variables.
+unsigned lskum_ref_residual_vjp(const lskum_ref_cloud *c, const lskum_ref_params *p,
+                                const double *U, const double *Rbar, double *Ubar,
+                                double thetabar[2]) {
+  const int32_t n = c->n;
+  const size_t N = (size_t)n;
+  const int K = p->n_inner > 0 ? p->n_inner : 0;
+  unsigned flags = 0;
+  std::vector<double> q(4 * N), qlim(8 * N);
+  std::vector<std::vector<double>> dq((size_t)K + 1, std::vector<double>(8 * N));
+  flags |= lskum_ref_q_vars(c, p, U, q.data());
+  lskum_ref_q_derivs_first(c, q.data(), dq[0].data(), qlim.data());
+  for (int k = 1; k <= K; ++k)
+    lskum_ref_q_derivs_inner(c, q.data(), dq[(size_t)k - 1].data(), dq[(size_t)k].data());
+
+  ad::Tape tp;
+  ad::tape = &tp;
+  std::vector<double> qbar(4 * N, 0.0), gbar(8 * N, 0.0), lbar(8 * N, 0.0), gprev(8 * N);
+
+  // flux residual
+  for (int32_t i = 0; i < n; ++i) {
+    if (c->kind[i] == 2) continue;
+    tp.clear();
+    const double *f[3] = {q.data(), dq[(size_t)K].data(), qlim.data()};
+    TapeSt st(f, n, i, row(*c, i), 7u);
+    ad::Var R[4];
+    flags |= flux_point(*c, *p, i, st, R);
+    seed_begin();
+    for (int m = 0; m < 4; ++m) seed(R[m], fld(Rbar, m, n, i));
+    tp.reverse();
+    double *bar[3] = {qbar.data(), gbar.data(), lbar.data()};
+    st.scatter(bar);
+  }
+  // inner sweeps, last first
+  for (int k = K; k >= 1; --k) {
+    std::fill(gprev.begin(), gprev.end(), 0.0);
+    for (int32_t i = 0; i < n; ++i) {
+      tp.clear();
+      const double *f[3] = {q.data(), dq[(size_t)k - 1].data(), nullptr};
+      TapeSt st(f, n, i, row(*c, i), 3u);
+      ad::Var d[8];
+      deriv_inner_point(*c, i, st, d);
+      seed_begin();
+      for (int m = 0; m < 8; ++m) seed(d[m], fld(gbar.data(), m, n, i));
+      tp.reverse();
+      double *bar[3] = {qbar.data(), gprev.data(), nullptr};
+      st.scatter(bar);
+    }
+    gbar.swap(gprev);
+  }
+  // first-order derivatives and stencil bounds
+  for (int32_t i = 0; i < n; ++i) {
+    tp.clear();
+    const double *f[3] = {q.data(), nullptr, nullptr};
+    TapeSt st(f, n, i, row(*c, i), 1u);
+    ad::Var d[8], l[8];
+    deriv_first_point(*c, i, st, d, l);
+    seed_begin();
+    for (int m = 0; m < 8; ++m) {
+      seed(d[m], fld(gbar.data(), m, n, i));
+      seed(l[m], fld(lbar.data(), m, n, i));
+    }
+    tp.reverse();
+    double *bar[3] = {qbar.data(), nullptr, nullptr};
+    st.scatter(bar);
+  }
+  // q-variables; outer rows go to theta
+  double ubar_outer[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int32_t i = 0; i < n; ++i) {
+    tp.clear();
+    ad::Var Ui[4], qi[4];
+    for (int m = 0; m < 4; ++m) Ui[m] = ad::input(fld(U, m, n, i));
+    q_point(p->gamma, Ui, qi);
+    seed_begin();
+    for (int m = 0; m < 4; ++m) seed(qi[m], fld(qbar.data(), m, n, i));
+    tp.reverse();
+    for (int m = 0; m < 4; ++m) {
+      const double g = adjoint(Ui[m]);
+      if (c->kind[i] == 2) {
+        ubar_outer[m] += g;
+        fld(Ubar, m, n, i) = 0.0;
+      } else {
+        fld(Ubar, m, n, i) = g;
+      }
+    }
+  }
+  tp.clear();
+  ad::Var mach = ad::input(p->mach), aoa = ad::input(p->aoa_rad), w[4], Uinf[4];
+  free_stream_prim_t(p->gamma, mach, aoa, w);
+  cons_from_prim(p->gamma, w, Uinf);
+  seed_begin();
+  for (int m = 0; m < 4; ++m) seed(Uinf[m], ubar_outer[m]);
+  tp.reverse();
+  thetabar[0] = adjoint(mach);
+  thetabar[1] = adjoint(aoa);
+  ad::tape = nullptr;
+  return flags;
+}
+
+// Cotangent of (Cl, Cd) with weights Jbar = (Jbar_l, Jbar_d):
+//   Ubar = (d(Jbar.C)/dU)^T (non-zero at wall points only),
+//   thetabar = d(Jbar.C)/d(M, alpha) at fixed U.
+void lskum_ref_force_coeffs_vjp(const lskum_ref_cloud *c, const lskum_ref_params *p,
+                                const double *U, const double Jbar[2], double *Ubar,
+                                double thetabar[2]) {
+  const int32_t n = c->n;
+  ad::Tape tp;
+  ad::tape = &tp;
+  std::vector<ad::Var> Uv(4 * (size_t)n);
+  for (int32_t e = 0; e < c->n_wall; ++e) {
+    const int32_t j = c->wall_loop[e];
+    for (int k = 0; k < 4; ++k) Uv[(size_t)k * n + j] = ad::input(fld(U, k, n, j));
+  }
+  ad::Var mach = ad::input(p->mach), aoa = ad::input(p->aoa_rad), C[2];
+  auto Uw = [&](int32_t j, int k) { return Uv[(size_t)k * n + j]; };
+  force_t<ad::Var>(*c, p->gamma, mach, aoa, Uw, C);
+  seed_begin();
+  seed(C[0], Jbar[0]);
+  seed(C[1], Jbar[1]);
+  tp.reverse();
+  for (size_t k = 0; k < 4 * (size_t)n; ++k) Ubar[k] = adjoint(Uv[k]);
+  thetabar[0] = adjoint(mach);
+  thetabar[1] = adjoint(aoa);
+  ad::tape = nullptr;
 }
 
 }  // extern "C"

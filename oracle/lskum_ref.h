@@ -91,6 +91,20 @@ void lskum_ref_force_coeffs(const lskum_ref_cloud *c, const lskum_ref_params *p,
 unsigned lskum_ref_iterate(const lskum_ref_cloud *c, const lskum_ref_params *p,
                            int32_t iters, double *U, double *hist);
 
+/* adjoints (reverse mode through the same formulas, active branches).
+ * residual_vjp: the residual as a function of the interior and wall rows of
+ * U and of theta = (M, alpha [rad]), the outer rows being U_inf(theta):
+ *   Ubar [4][n] = (dR/dU)^T Rbar, zero at outer rows;
+ *   thetabar[2] = sum_outer (dR/dU_j)^T Rbar . dU_inf/dtheta.
+ * force_coeffs_vjp: Jbar = weights of (Cl, Cd); Ubar [4][n] (wall rows
+ * only non-zero) and thetabar[2] = partial derivatives at fixed U. */
+unsigned lskum_ref_residual_vjp(const lskum_ref_cloud *c, const lskum_ref_params *p,
+                                const double *U, const double *Rbar, double *Ubar,
+                                double thetabar[2]);
+void lskum_ref_force_coeffs_vjp(const lskum_ref_cloud *c, const lskum_ref_params *p,
+                                const double *U, const double Jbar[2], double *Ubar,
+                                double thetabar[2]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,6 +67,8 @@ def load(rebuild: bool = False) -> ctypes.CDLL:
         "lskum_ref_residual_norm": (ctypes.c_double, [cp, vp]),
         "lskum_ref_force_coeffs": (None, [cp, pp, vp, vp]),
         "lskum_ref_iterate": (ctypes.c_uint, [cp, pp, ctypes.c_int32, vp, vp]),
+        "lskum_ref_residual_vjp": (ctypes.c_uint, [cp, pp, vp, vp, vp, vp]),
+        "lskum_ref_force_coeffs_vjp": (None, [cp, pp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -246,6 +248,35 @@ class Oracle:
         self.lib.lskum_ref_force_coeffs(ctypes.byref(self._c), ctypes.byref(self._p), _ptr(U),
                                         _ptr(out))
         return out
+
+    def residual_vjp(self, U, Rbar):
+        """Cotangent of (interior and wall rows of U, theta) -> R(U), the
+        outer rows being the free stream of theta = (M, alpha [rad]).
+        Returns (Ubar (4, n) with zero outer rows, thetabar (2,), flags)."""
+        U = self._field(U, 4)
+        Rbar = self._field(Rbar, 4)
+        Ubar = np.zeros((4, self.n))
+        tb = np.zeros(2)
+        flags = self.lib.lskum_ref_residual_vjp(ctypes.byref(self._c), ctypes.byref(self._p),
+                                                _ptr(U), _ptr(Rbar), _ptr(Ubar), _ptr(tb))
+        return Ubar, tb, int(flags)
+
+    def force_coeffs_vjp(self, U, Jbar):
+        """Cotangent of (U, theta) -> (Cl, Cd) with weights Jbar: (Ubar, thetabar)."""
+        U = self._field(U, 4)
+        Jbar = _f64(Jbar, (2,))
+        Ubar = np.zeros((4, self.n))
+        tb = np.zeros(2)
+        self.lib.lskum_ref_force_coeffs_vjp(ctypes.byref(self._c), ctypes.byref(self._p), _ptr(U),
+                                            _ptr(Jbar), _ptr(Ubar), _ptr(tb))
+        return Ubar, tb
+
+    def with_flow(self, mach: float, aoa_rad: float) -> "Oracle":
+        """The same cloud and settings at another free stream (AoA in radians)."""
+        o = Oracle(self.cloud, mach, math.degrees(aoa_rad), cfl=self.cfl,
+                   venkat_k=self.venkat_k, n_inner=self.n_inner, gamma=self.gamma)
+        o._p.aoa_rad = aoa_rad  # exactly, not through degrees
+        return o
 
     def iterate(self, U, iters: int):
         U = self._field(U, 4).copy()
