@@ -186,6 +186,47 @@ int lskum_graph_create(lskum_graph *out, lskum_plan plan, int32_t iters, double 
 int lskum_graph_launch(lskum_graph graph, void *stream);
 int lskum_graph_destroy(lskum_graph graph);
 
+/* Dirichlet rows: writes each cloud's free stream (from its current params)
+ * at the outer points of U; other rows are left as they are. */
+int lskum_set_far_field(lskum_plan plan, double *U, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Adjoints (vector-Jacobian products), reverse mode through the formulas
+ * of lskum_q_vars, lskum_q_derivs and lskum_flux_residual (eq. (9)-(15) and
+ * the split fluxes of eq. (2)-(3)), differentiating the branch the forward
+ * takes at each limiter, stencil max/min (the first slot attaining it, the
+ * point itself first) and half-plane membership test.
+ *
+ * theta = (M, alpha [rad]) per cloud.  The residual is taken as a function
+ * of the interior and wall rows of U and of theta, the outer rows being the
+ * free stream U_inf(theta) of eq. (1) with rho = 1, p = 1/gamma.
+ * ------------------------------------------------------------------- */
+
+/* Bytes of device workspace lskum_flux_residual_vjp needs:
+ * (49 + 8 n_inner) doubles per point for q, every derivative iterate, the
+ * bounds and the cotangents, plus 32 bytes per (point, row slot) for the
+ * edge cotangents. */
+size_t lskum_vjp_workspace_bytes(lskum_plan plan);
+
+/* Ubar = (dR/dU)^T Rbar at interior and wall rows, 0 at outer rows;
+ * thetabar[2c], thetabar[2c+1] = the Mach and alpha cotangents of cloud c,
+ * i.e. sum over its outer rows j of (dR/dU_j)^T Rbar . dU_inf/dtheta.
+ * U, Rbar, Ubar: device [n][4] (Rbar is ignored at outer rows); thetabar:
+ * device [n_clouds][2]; ws: device, lskum_vjp_workspace_bytes(plan) bytes,
+ * 256-byte aligned.  q and the derivatives are recomputed from U.  The
+ * first call on a plan also builds the plan's transposed connectivity
+ * (synchronous; LSKUM_ERR_INVALID_ARG beyond 2^25 - 1 points or 64 slots per
+ * row). */
+int lskum_flux_residual_vjp(lskum_plan plan, const double *U, const double *Rbar, double *Ubar,
+                            double *thetabar, void *ws, void *stream);
+
+/* Cotangent of the force coefficients: with Jbar[2c], Jbar[2c+1] the
+ * weights of (Cl, Cd) of cloud c (device), writes Ubar = d(Jbar . C)/dU
+ * (device [n][4], non-zero at wall points only) and thetabar[2c..2c+1] =
+ * d(Jbar . C)/d(M, alpha) at fixed U (device). */
+int lskum_force_coeffs_vjp(lskum_plan plan, const double *U, const double *Jbar, double *Ubar,
+                           double *thetabar, void *stream);
+
 /* Synchronises `stream`, then returns LSKUM_ERR_NONPHYSICAL or
  * LSKUM_ERR_DEGENERATE if a kernel has recorded one since the last clear,
  * else LSKUM_OK (or LSKUM_ERR_HIP). */

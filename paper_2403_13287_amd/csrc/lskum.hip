@@ -32,104 +32,9 @@
 #include <vector>
 
 #include "lskum.h"
-#include "lskum_math.h"
+#include "lskum_impl.h"
 
-namespace {
-
-using lskum_math::lk_div;
-using lskum_math::lk_rsqrt;
-
-constexpr int kBlock = 256;
-constexpr int kXcds = 8;
-constexpr int kNormChunk = 2048;  // points per residual-norm chunk
-constexpr unsigned kFlagNonPhysical = 1u;
-constexpr unsigned kFlagDegenerate = 2u;
-
-struct Geo {
-  int n;
-  int xcd;  // 1: blocks relabelled so that each XCD walks one contiguous range
-  const double2 *xy;
-  const double2 *nrm;
-  const int8_t *kind;
-  const int32_t *nbr;    // [k_pad][n]
-  const int32_t *cnt;
-  const int32_t *cloud;  // [n] cloud of each point (batched plans)
-  const double *uinf;    // [n_clouds][4] free-stream state of each cloud
-};
-
-struct Flow {
-  double gamma, inv_gm1, cfl, venkat_k;
-  bool gamma_is_14;  // gamma == 1.4 exactly: rho from beta^(-5/2) without a log
-};
-
-// point records
-struct __attribute__((aligned(32))) F4 {
-  double v[4];
-};
-struct __attribute__((aligned(64))) F8 {
-  double v[8];
-};
-
-__device__ __forceinline__ F4 ld4(const double *f, int i) {
-  return reinterpret_cast<const F4 *>(f)[i];
-}
-__device__ __forceinline__ F8 ld8(const double *f, int i) {
-  return reinterpret_cast<const F8 *>(f)[i];
-}
-__device__ __forceinline__ void st4(double *f, int i, const F4 &v) {
-  reinterpret_cast<F4 *>(f)[i] = v;
-}
-__device__ __forceinline__ void st8(double *f, int i, const F8 &v) {
-  reinterpret_cast<F8 *>(f)[i] = v;
-}
-
-// ---------------------------------------------------------------------------
-// launch helpers
-
-// Blocks are dispatched to the 8 XCDs round-robin.  With xcd set, re-label
-// them so that XCD x processes one contiguous range of logical blocks.  The
-// grid is a multiple of 8; threads past n exit at once.
-__device__ __forceinline__ int block_id(int xcd) {
-  if (!xcd) return blockIdx.x;
-  const int per = gridDim.x / kXcds;
-  return (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
-}
-
-template <int BLK>
-__device__ __forceinline__ int point_index(int xcd) {
-  return block_id(xcd) * BLK + threadIdx.x;
-}
-
-inline int grid_for(int n, int blk = kBlock) {
-  int nb = (n + blk - 1) / blk;
-  return (nb + kXcds - 1) / kXcds * kXcds;
-}
-
-// ds = dx*tx + dy*ty and dn = dx*nx + dy*ny with every product and sum
-// rounded separately (no FMA contraction): the sign of ds/dn decides
-// split-stencil membership, and this matches the oracle's uncontracted
-// evaluation bit for bit.
-__device__ __forceinline__ double dot_rn(double a, double b, double c, double d) {
-#pragma clang fp contract(off)
-  const double ab = a * b;
-  const double cd = c * d;
-  return ab + cd;
-}
-
-__device__ __forceinline__ void flag(unsigned *status, unsigned f) {
-  if (f) __hip_atomic_fetch_or(status, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// ---------------------------------------------------------------------------
-// eq. (13) and its inverse
-
-__device__ __forceinline__ void prim_from_cons(double g, const F4 &U, double &rho, double &u,
-                                               double &v, double &p) {
-  rho = U.v[0];
-  u = U.v[1] / rho;
-  v = U.v[2] / rho;
-  p = (g - 1.0) * (U.v[3] - 0.5 * rho * (u * u + v * v));
-}
+namespace lskum_impl {
 
 __global__ void __launch_bounds__(kBlock) k_q_vars(int n, int xcd, double g, double inv_gm1,
                                                    const double *__restrict__ U,
@@ -151,50 +56,16 @@ __global__ void __launch_bounds__(kBlock) k_q_vars(int n, int xcd, double g, dou
 }
 
 // ---------------------------------------------------------------------------
-// block tiles
-//
-// A block owns BLK consecutive points (one Hilbert tile; BLK is the tuned
-// block size, 128, 256 or 512).  Kernels that gather neighbour records first
-// stage the tile's own records in LDS; about 80 % of the neighbours of a
-// 1M-point airfoil cloud fall inside their own 256-point tile, so most
-// gathers become LDS reads and only the remote ones go through the vector
-// memory path.
-
-template <int BLK>
-__device__ __forceinline__ int tile_lo(int xcd) {
-  return block_id(xcd) * BLK;
-}
-
-// lj = j - lo; true when j belongs to the tile starting at lo
-template <int BLK>
-__device__ __forceinline__ bool in_tile(int j, int lo, int &lj) {
-  lj = j - lo;
-  return (unsigned)lj < (unsigned)BLK;
-}
-
-// Reader of point i's neighbour row (column-major connectivity).  Slots at
-// or past the row's count read the last real slot and return i itself, so
-// prefetching ahead never leaves the row: gather loops fetch the index two
-// neighbours ahead and the neighbour's records one ahead, which keeps two
-// dependent memory round trips off each iteration.
-struct Row {
-  const int32_t *col;  // &nbr[i], stride n
-  int n, c, i;
-  __device__ __forceinline__ int operator()(int k) const {
-    const int kk = k < c ? k : c - 1;
-    const int j = col[(size_t)kk * n];
-    return k < c ? j : i;
-  }
-};
-
-// ---------------------------------------------------------------------------
 // least-squares q-derivatives
 
 // First-order solve (eq. (9) with dq_i = q_i - q_0) and stencil bounds.
-template <int BLK>
+// With ARG, also the slot attaining each bound (first in stencil order, the
+// point itself first; -1 = the point itself), for the adjoint.
+template <int BLK, bool ARG>
 __global__ void __launch_bounds__(BLK) k_deriv_first(Geo G, const double *__restrict__ q,
                                                         double *__restrict__ dq,
-                                                        double *__restrict__ qlim) {
+                                                        double *__restrict__ qlim,
+                                                        int8_t *__restrict__ argext) {
   __shared__ double2 s_xy[BLK];
   __shared__ F4 s_q[BLK];
   const int n = G.n;
@@ -212,9 +83,11 @@ __global__ void __launch_bounds__(BLK) k_deriv_first(Geo G, const double *__rest
   __syncthreads();
   if (!active) return;
   double qmax[4], qmin[4], sxq[4], syq[4];
+  int amax[4], amin[4];
   for (int m = 0; m < 4; ++m) {
     qmax[m] = qmin[m] = q0.v[m];
     sxq[m] = syq[m] = 0.0;
+    amax[m] = amin[m] = -1;
   }
   double sxx = 0.0, sxy = 0.0, syy = 0.0;
   const int c = G.cnt[i];
@@ -246,8 +119,19 @@ __global__ void __launch_bounds__(BLK) k_deriv_first(Geo G, const double *__rest
       const double d = qj.v[m] - q0.v[m];
       sxq[m] += dx * d;
       syq[m] += dy * d;
-      qmax[m] = fmax(qmax[m], qj.v[m]);
-      qmin[m] = fmin(qmin[m], qj.v[m]);
+      if (ARG) {
+        if (qj.v[m] > qmax[m]) {
+          qmax[m] = qj.v[m];
+          amax[m] = k;
+        }
+        if (qj.v[m] < qmin[m]) {
+          qmin[m] = qj.v[m];
+          amin[m] = k;
+        }
+      } else {
+        qmax[m] = fmax(qmax[m], qj.v[m]);
+        qmin[m] = fmin(qmin[m], qj.v[m]);
+      }
     }
     xj = xn;
     qj = qn;
@@ -263,6 +147,14 @@ __global__ void __launch_bounds__(BLK) k_deriv_first(Geo G, const double *__rest
   }
   st8(dq, i, g);
   st8(qlim, i, lim);
+  if (ARG) {
+    uint64_t packed = 0;
+    for (int m = 0; m < 4; ++m) {
+      packed |= (uint64_t)(uint8_t)(int8_t)amax[m] << (8 * m);
+      packed |= (uint64_t)(uint8_t)(int8_t)amin[m] << (8 * (4 + m));
+    }
+    reinterpret_cast<uint64_t *>(argext)[i] = packed;
+  }
 }
 
 // One Jacobi inner sweep (eq. (14)-(15)): modified differences from the
@@ -345,92 +237,6 @@ __global__ void __launch_bounds__(BLK) k_deriv_inner(Geo G, const double *__rest
 
 // ---------------------------------------------------------------------------
 // flux residual
-
-// Venkatakrishnan-limited increment phi*delta of one q component at one end
-// of an edge: D is the room to the stencil max (delta > 0) or min (delta < 0),
-// phi = min(1, (D^2 + eps2 + 2 delta D)/(D^2 + 2 delta^2 + delta D + eps2)),
-// phi = 1 for delta = 0.
-__device__ __forceinline__ double limited(double delta, double room_max, double room_min,
-                                          double eps2) {
-  const double D = delta > 0.0 ? room_max : room_min;
-  const double num = D * D + eps2 + 2.0 * delta * D;
-  const double den = D * D + 2.0 * delta * delta + delta * D + eps2;
-  const double phi = delta == 0.0 ? 1.0 : fmin(1.0, lk_div(num, den));
-  return phi * delta;
-}
-
-// State at one end of an edge, recovered from the limited modified q.
-struct EndState {
-  double rho, us, un, p, E;
-  double sqb;    // sqrt(beta)
-  double bcoef;  // 1 / (2 sqrt(pi beta))
-};
-
-// Inverse of eq. (13): beta = -q4/2, (u, v) = (q2, q3)/(2 beta),
-// rho = exp(q1 + beta (u^2+v^2)) beta^(-1/(gamma-1)), p = rho/(2 beta).
-// For gamma = 1.4 the power is beta^(-5/2) = rsqrt(beta) / beta^2, so one
-// rsqrt gives sqrt(beta), 1/beta and the power without a log or a divide.
-__device__ __forceinline__ unsigned end_state(const double qt[4], const Flow &P, double tx,
-                                              double ty, double nx, double ny, EndState &s) {
-  constexpr double kHalfRsqrtPi = 0.28209479177387814347;  // 1 / (2 sqrt(pi))
-  const double beta = -0.5 * qt[3];
-  const double rsb = lk_rsqrt(beta);
-  const double ib = rsb * rsb;
-  const double inv2b = 0.5 * ib;
-  const double u = qt[1] * inv2b;
-  const double v = qt[2] * inv2b;
-  const double uu = u * u + v * v;
-  double rho;
-  if (P.gamma_is_14)
-    rho = exp(qt[0] + beta * uu) * (rsb * ib * ib);
-  else
-    rho = exp(qt[0] + beta * uu - log(beta) * P.inv_gm1);
-  const double p = rho * inv2b;
-  s.rho = rho;
-  s.p = p;
-  s.us = u * tx + v * ty;
-  s.un = u * nx + v * ny;
-  s.E = p * P.inv_gm1 + 0.5 * rho * uu;
-  s.sqb = beta * rsb;
-  s.bcoef = kHalfRsqrtPi * rsb;
-  return (!(beta > 0.0) || !(rho > 0.0) || !(p > 0.0) || !isfinite(rho) || !isfinite(p))
-             ? kFlagNonPhysical
-             : 0u;
-}
-
-// Kinetic split flux along direction d with sign sg (+1 or -1): half-range
-// moments of the Maxwellian of eq. (2) under the CIR split of eq. (3).
-// ud: velocity along d, uo: the other component.  Output (mass, d-momentum,
-// o-momentum, energy).
-__device__ __forceinline__ void split_flux(double sg, const EndState &s, double ud, double uo,
-                                           double G[4]) {
-  const double S = ud * s.sqb;
-  const double A = 0.5 * (1.0 + sg * erf(S));
-  const double B = exp(-(S * S)) * s.bcoef;
-  const double F = ud * A + sg * B;
-  G[0] = s.rho * F;
-  G[1] = (s.p + s.rho * ud * ud) * A + sg * s.rho * ud * B;
-  G[2] = s.rho * uo * F;
-  G[3] = (s.E + s.p) * ud * A + sg * (s.E + 0.5 * s.p) * B;
-}
-
-// Least-squares weights of one half-plane stencil: for an s-split the
-// derivative is sum_i (Snn ds_i - Ssn dn_i)/det * dG_i, for an n-split
-// sum_i (Sss dn_i - Ssn ds_i)/det * dG_i (eq. (11) in the (s, n) frame).
-struct SplitW {
-  double a, b;  // weight of edge i = a*ds_i + b*dn_i
-};
-
-__device__ __forceinline__ SplitW split_weights(bool s_dir, int count, double sss, double ssn,
-                                                double snn, unsigned &f) {
-  const double det = sss * snn - ssn * ssn;
-  if (count < 2 || !(det > 1e-12 * sss * snn)) {
-    f |= kFlagDegenerate;
-    return SplitW{0.0, 0.0};
-  }
-  const double inv = 1.0 / det;
-  return s_dir ? SplitW{snn * inv, -ssn * inv} : SplitW{-ssn * inv, sss * inv};
-}
 
 template <int BLK>
 __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__restrict__ q,
@@ -542,14 +348,12 @@ __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__res
     const double dx = xj.x - xi.x, dy = xj.y - xi.y;
     const double ds = dot_rn(dx, tx, dy, ty);
     const double dn = dot_rn(dx, nx, dy, ny);
-    const double d2 = dx * dx + dy * dy;
-    const double kd = K * (d2 > 0.0 ? d2 * lk_rsqrt(d2) : 0.0);
-    const double eps2 = kd * kd * kd;
+    const double eps2 = edge_eps2(K, dx, dy);
     double qtj[4], qt0[4];
     for (int m = 0; m < 4; ++m) {
-      const double dj = -0.5 * (dx * gj.v[m] + dy * gj.v[4 + m]);
+      const double dj = half_step(dx, dy, gj.v[m], gj.v[4 + m]);
       qtj[m] = qj.v[m] + limited(dj, lj8.v[m] - qj.v[m], lj8.v[4 + m] - qj.v[m], eps2);
-      const double d0 = -0.5 * (dx * g0.v[m] + dy * g0.v[4 + m]);
+      const double d0 = half_step(dx, dy, g0.v[m], g0.v[4 + m]);
       qt0[m] = q0.v[m] + limited(d0, mx0[m], mn0[m], eps2);
     }
     EndState sj, s0;
@@ -676,23 +480,17 @@ __global__ void __launch_bounds__(kBlock) k_init_state(Geo G, double *__restrict
   st4(U, i, Ui);
 }
 
+// Dirichlet rows: the free stream of its cloud at every outer point.
+__global__ void __launch_bounds__(kBlock) k_far_field(Geo G, double *__restrict__ U) {
+  const int i = point_index<kBlock>(G.xcd);
+  if (i >= G.n || G.kind[i] != 2) return;
+  st4(U, i, ld4(G.uinf, G.cloud[i]));
+}
+
 __global__ void k_copy(size_t count, const double *__restrict__ src, double *__restrict__ dst) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += stride)
     dst[k] = src[k];
-}
-
-// ---------------------------------------------------------------------------
-// deterministic reductions
-
-__device__ __forceinline__ double block_sum(double v, double *lds) {
-  lds[threadIdx.x] = v;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
-    __syncthreads();
-  }
-  return lds[0];
 }
 
 // Residual norms per cloud.  Each cloud's points are cut into fixed chunks
@@ -776,30 +574,9 @@ __global__ void __launch_bounds__(kBlock) k_force(Geo G, Flow P, const int32_t *
   }
 }
 
-}  // namespace
+}  // namespace lskum_impl
 
-// ---------------------------------------------------------------------------
-// plan
-
-struct lskum_plan_s {
-  int device = 0;
-  int32_t n = 0, k_pad = 0, n_clouds = 0, n_wall = 0, n_chunks = 0;
-  int block = 256, xcd = 1;
-  std::vector<lskum_params> params;  // one per cloud
-  std::vector<int32_t> offset;       // first point of each cloud (+ total)
-  double2 *xy = nullptr, *nrm = nullptr;
-  int8_t *kind = nullptr;
-  int32_t *nbr = nullptr, *cnt = nullptr, *cloud = nullptr;
-  int32_t *wall = nullptr, *woff = nullptr;  // concatenated wall loops, offsets [n_clouds+1]
-  double *uinf = nullptr;                    // [n_clouds][4]
-  double *mach = nullptr, *aoa = nullptr;    // [n_clouds]
-  int2 *chunks = nullptr;                    // residual-norm chunks
-  int32_t *chunk_first = nullptr;            // first chunk of each cloud [n_clouds+1]
-  double *partial = nullptr;                 // [n_chunks]
-  double *norm_scratch = nullptr;            // [n_clouds]
-  int32_t *counter = nullptr;                // graph-replay iteration counter
-  unsigned *status = nullptr;
-};
+using namespace lskum_impl;
 
 struct lskum_graph_s {
   lskum_plan_s *plan = nullptr;
@@ -808,24 +585,46 @@ struct lskum_graph_s {
   hipStream_t capture = nullptr;
 };
 
+namespace lskum_impl {
+
+int q_vars_launch(lskum_plan_s *p, const double *U, double *q, void *stream) {
+  const Flow f = flow(p);
+  k_q_vars<<<grid_for(p->n), kBlock, 0, S(stream)>>>(p->n, p->xcd, f.gamma, f.inv_gm1, U, q,
+                                                     p->status);
+  return launched();
+}
+
+int deriv_first_launch(lskum_plan_s *p, const double *q, double *dq, double *qlim,
+                       int8_t *argext, void *stream) {
+  const Geo g = geo(p);
+  const int gr = grid_for(p->n, p->block);
+  hipStream_t st = S(stream);
+  switch (p->block) {
+    case 128:
+      if (argext) k_deriv_first<128, true><<<gr, 128, 0, st>>>(g, q, dq, qlim, argext);
+      else k_deriv_first<128, false><<<gr, 128, 0, st>>>(g, q, dq, qlim, nullptr);
+      break;
+    case 512:
+      if (argext) k_deriv_first<512, true><<<gr, 512, 0, st>>>(g, q, dq, qlim, argext);
+      else k_deriv_first<512, false><<<gr, 512, 0, st>>>(g, q, dq, qlim, nullptr);
+      break;
+    default:
+      if (argext) k_deriv_first<256, true><<<gr, 256, 0, st>>>(g, q, dq, qlim, argext);
+      else k_deriv_first<256, false><<<gr, 256, 0, st>>>(g, q, dq, qlim, nullptr);
+      break;
+  }
+  return launched();
+}
+
+int deriv_inner_launch(lskum_plan_s *p, const double *q, const double *dqp, double *dqn,
+                       void *stream) {
+  LSKUM_TILED(k_deriv_inner, p, stream, geo(p), q, dqp, dqn);
+  return launched();
+}
+
+}  // namespace lskum_impl
+
 namespace {
-
-inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
-
-Geo geo(const lskum_plan_s *p) {
-  return Geo{p->n, p->xcd, p->xy, p->nrm, p->kind, p->nbr, p->cnt, p->cloud, p->uinf};
-}
-
-Flow flow(const lskum_plan_s *p) {
-  Flow f;
-  const lskum_params &q = p->params[0];  // shared settings (validated equal)
-  f.gamma = q.gamma;
-  f.inv_gm1 = 1.0 / (q.gamma - 1.0);
-  f.cfl = q.cfl;
-  f.venkat_k = q.venkat_k;
-  f.gamma_is_14 = q.gamma == 1.4;
-  return f;
-}
 
 bool params_ok(const lskum_params *p) {
   return p && std::isfinite(p->gamma) && p->gamma > 1.0 && std::isfinite(p->mach) &&
@@ -859,12 +658,6 @@ void free_stream_state(const lskum_params &q, double U[4]) {
   U[3] = (1.0 / q.gamma) / (q.gamma - 1.0) + 0.5 * rho * (u * u + v * v);
 }
 
-int launched() { return hipGetLastError() == hipSuccess ? LSKUM_OK : LSKUM_ERR_HIP; }
-
-// 4-double records need 32-byte, 8-double records 64-byte alignment.
-bool a32(const void *p) { return p && ((uintptr_t)p % 32) == 0; }
-bool a64(const void *p) { return p && ((uintptr_t)p % 64) == 0; }
-
 void release(lskum_plan_s *p) {
   if (!p) return;
   int cur = 0;
@@ -872,24 +665,14 @@ void release(lskum_plan_s *p) {
   (void)hipSetDevice(p->device);
   void *bufs[] = {p->xy,     p->nrm,  p->kind,   p->nbr,         p->cnt,     p->cloud,
                   p->wall,   p->woff, p->uinf,   p->mach,        p->aoa,     p->chunks,
-                  p->chunk_first, p->partial, p->norm_scratch, p->counter, p->status};
+                  p->chunk_first, p->partial, p->norm_scratch, p->counter, p->status,
+                  p->in_ptr, p->in_ent, p->lsg, p->outer, p->ooff};
   for (void *b : bufs) (void)hipFree(b);
   (void)hipSetDevice(cur);
   delete p;
 }
 
-template <class T>
-int upload(T **dst, const void *src, size_t count) {
-  if (hipMalloc((void **)dst, count * sizeof(T) + (count == 0 ? sizeof(T) : 0)) != hipSuccess)
-    return LSKUM_ERR_NO_MEMORY;
-  if (count && hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
-    return LSKUM_ERR_HIP;
-  return LSKUM_OK;
-}
-
 constexpr size_t kNumWorkFields = 4 + 4 + 8 + 8 + 8 + 4 + 1;  // Un q dq qlim work R dt
-
-size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 // Validate one cloud and append it (point ids shifted by base) to the
 // concatenated host arrays.
@@ -925,9 +708,11 @@ int append_cloud(const lskum_cloud *c, int32_t kp, int32_t base, int32_t cloud_i
     cnt.push_back(k);
     cid.push_back(cloud_id);
   }
+  std::vector<char> on_loop((size_t)n, 0);
   for (int32_t e = 0; e < c->n_wall; ++e) {
     const int32_t w = c->wall_loop[e];
-    if (w < 0 || w >= n || c->kind[w] != 1) return LSKUM_ERR_BAD_CLOUD;
+    if (w < 0 || w >= n || c->kind[w] != 1 || on_loop[(size_t)w]) return LSKUM_ERR_BAD_CLOUD;
+    on_loop[(size_t)w] = 1;
     wall.push_back(base + w);
   }
   return LSKUM_OK;
@@ -950,17 +735,6 @@ int upload_uinf(lskum_plan_s *p) {
   return LSKUM_OK;
 }
 
-// kernel launches with the plan's tile size
-#define LSKUM_TILED(kern, p, stream, ...)                                                    \
-  do {                                                                                       \
-    const int g_ = grid_for((p)->n, (p)->block);                                             \
-    switch ((p)->block) {                                                                    \
-      case 128: kern<128><<<g_, 128, 0, S(stream)>>>(__VA_ARGS__); break;                    \
-      case 512: kern<512><<<g_, 512, 0, S(stream)>>>(__VA_ARGS__); break;                    \
-      default: kern<256><<<g_, 256, 0, S(stream)>>>(__VA_ARGS__); break;                     \
-    }                                                                                        \
-  } while (0)
-
 int norm_launch(lskum_plan_s *p, const double *R, double *out, const int32_t *counter,
                 int capacity, void *stream) {
   k_norm_partial<<<p->n_chunks, kBlock, 0, S(stream)>>>(p->chunks, p->kind, R, p->partial);
@@ -971,19 +745,18 @@ int norm_launch(lskum_plan_s *p, const double *R, double *out, const int32_t *co
 
 int q_derivs_launch(lskum_plan_s *p, const double *q, double *dq, double *qlim, double *work,
                     void *stream) {
-  const Geo g = geo(p);
   const int ni = p->params[0].n_inner;
   // ping-pong so that the last sweep writes dq
   double *a = (ni % 2 == 0) ? dq : work;
   double *b = (ni % 2 == 0) ? work : dq;
-  LSKUM_TILED(k_deriv_first, p, stream, g, q, a, qlim);
-  for (int it = 0; it < ni; ++it) {
-    LSKUM_TILED(k_deriv_inner, p, stream, g, q, a, b);
+  int rc = deriv_first_launch(p, q, a, qlim, nullptr, stream);
+  for (int it = 0; it < ni && rc == LSKUM_OK; ++it) {
+    rc = deriv_inner_launch(p, q, a, b, stream);
     double *t = a;
     a = b;
     b = t;
   }
-  return launched();
+  return rc;
 }
 
 // The iteration body shared by lskum_iterate and graph capture.  With a
@@ -1010,7 +783,7 @@ int run_iterations(lskum_plan_s *p, int32_t iters, double *U, double *hist, int3
     k_local_dt<<<grid, kBlock, 0, S(stream)>>>(g, f, U, dt);
     k_copy<<<copy_grid, kBlock, 0, S(stream)>>>(4 * n, U, Un);
     for (int s = 0; s < 4; ++s) {
-      k_q_vars<<<grid, kBlock, 0, S(stream)>>>(p->n, p->xcd, f.gamma, f.inv_gm1, U, q, p->status);
+      if ((rc = q_vars_launch(p, U, q, stream))) return rc;
       if ((rc = q_derivs_launch(p, q, dq, qlim, work, stream))) return rc;
       LSKUM_TILED(k_flux, p, stream, g, f, q, dq, qlim, R, p->status);
       if (s == 0) {
@@ -1185,12 +958,15 @@ int lskum_init_state(lskum_plan p, double *U, void *stream) {
   return launched();
 }
 
+int lskum_set_far_field(lskum_plan p, double *U, void *stream) {
+  if (!p || !a32(U)) return LSKUM_ERR_INVALID_ARG;
+  k_far_field<<<grid_for(p->n), kBlock, 0, S(stream)>>>(geo(p), U);
+  return launched();
+}
+
 int lskum_q_vars(lskum_plan p, const double *U, double *q, void *stream) {
   if (!p || !a32(U) || !a32(q)) return LSKUM_ERR_INVALID_ARG;
-  const Flow f = flow(p);
-  k_q_vars<<<grid_for(p->n), kBlock, 0, S(stream)>>>(p->n, p->xcd, f.gamma, f.inv_gm1, U, q,
-                                                     p->status);
-  return launched();
+  return q_vars_launch(p, U, q, stream);
 }
 
 int lskum_q_derivs(lskum_plan p, const double *q, double *dq, double *qlim, double *work,

@@ -1,0 +1,885 @@
+// lskum_adjoint.hip -- vector-Jacobian products of the residual sweep and of
+// the force coefficients (gfx950).
+//
+// Reverse mode written by hand over the forward formulas (arXiv 2403.13287,
+// eq. (9)-(15) and the kinetic split fluxes of eq. (2)-(3)), differentiating
+// the branch the forward takes at every limiter, stencil max/min and split
+// membership test.  Nothing is stored between the forward and the adjoint:
+// a VJP call recomputes q, the first-order derivatives with the slots that
+// attain the stencil bounds, and every inner-iteration iterate, then runs the
+// passes backwards.
+//
+// Every kernel writes only its own point's outputs, so results are
+// deterministic.  Where the forward gathers from neighbours (point i reads
+// point j's data), the reverse has to send cotangents from i to j; that
+// transposed direction is also a gather, over the in-edges of j (the rows
+// that list j), kept as a CSR built once per plan.  The flux reverse stores
+// the cotangent of each edge's neighbour-end modified q in an edge-slot array
+// [slot][point] (32 B per edge) that the transposed gather then reads.
+//
+// Adjoint data of a plan (device, built by the first VJP call):
+//   in_ptr int32 [n+1]   in-edges of point j: in_ent[in_ptr[j] .. in_ptr[j+1])
+//   in_ent int32 [n_in]  (slot << 25) | i for each row i listing j at `slot`,
+//                        sorted by i then slot
+//   lsg    F8    [n]     least-squares geometry: M^-1 = [[a, b], [b, c]] of
+//                        the point's normal matrix, and sum of its edge
+//                        vectors (sdx, sdy)
+//   outer, ooff          outer points of each cloud
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <new>
+#include <vector>
+
+#include "lskum.h"
+#include "lskum_impl.h"
+
+namespace lskum_impl {
+namespace {
+
+constexpr double kInvSqrtPi = 0.56418958354775628695;  // 1 / sqrt(pi)
+
+// ---------------------------------------------------------------------------
+// reverse of the point formulas
+
+// Cotangents of limited(delta, room_max, room_min, eps2) = phi*delta given
+// the cotangent ob of its result: of delta, and of the room it used
+// (sel = +1: room_max, -1: room_min, 0: none).
+struct LimRev {
+  double ddelta, droom;
+  int sel;
+};
+
+__device__ __forceinline__ LimRev limited_rev(double delta, double room_max, double room_min,
+                                              double eps2, double ob) {
+  if (delta == 0.0) return LimRev{ob, 0.0, 0};
+  const double D = delta > 0.0 ? room_max : room_min;
+  const double num = D * D + eps2 + 2.0 * delta * D;
+  const double den = D * D + 2.0 * delta * delta + delta * D + eps2;
+  const double r = lk_div(num, den);
+  if (!(r < 1.0)) return LimRev{ob, 0.0, 0};  // phi = 1
+  // r = num/den: dr/ddelta = (2D - r (4 delta + D))/den,
+  //              dr/dD     = (2D + 2 delta - r (2D + delta))/den
+  const double rden = lk_div(1.0, den);
+  const double r_delta = (2.0 * D - r * (4.0 * delta + D)) * rden;
+  const double r_D = (2.0 * D + 2.0 * delta - r * (2.0 * D + delta)) * rden;
+  return LimRev{ob * (r + delta * r_delta), ob * delta * r_D, delta > 0.0 ? 1 : -1};
+}
+
+// cotangents of the fields of EndState
+struct EndBar {
+  double rho, us, un, p, E, sqb, bcoef;
+};
+
+// Reverse of split_flux: Gb = cotangent of G (mass, d-momentum, o-momentum,
+// energy); adds to the end-state cotangents and to those of ud and uo.
+__device__ __forceinline__ void split_flux_rev(double sg, const EndState &s, double ud, double uo,
+                                               const double Gb[4], EndBar &b, double &udb,
+                                               double &uob) {
+  const double S = ud * s.sqb;
+  const double ex = exp(-(S * S));
+  const double A = 0.5 * (1.0 + sg * erf(S));
+  const double B = ex * s.bcoef;
+  const double F = ud * A + sg * B;
+  const double Fb = Gb[0] * s.rho + Gb[2] * s.rho * uo;
+  b.rho += Gb[0] * F + Gb[1] * (ud * ud * A + sg * ud * B) + Gb[2] * uo * F;
+  uob += Gb[2] * s.rho * F;
+  const double Ab = Gb[1] * (s.p + s.rho * ud * ud) + Gb[3] * (s.E + s.p) * ud + Fb * ud;
+  const double Bb = sg * (Gb[1] * s.rho * ud + Gb[3] * (s.E + 0.5 * s.p) + Fb);
+  double u_b = Gb[1] * (2.0 * s.rho * ud * A + sg * s.rho * B) + Gb[3] * (s.E + s.p) * A + Fb * A;
+  b.p += Gb[1] * A + Gb[3] * (ud * A + 0.5 * sg * B);
+  b.E += Gb[3] * F;
+  // A = (1 + sg erf S)/2, B = exp(-S^2) bcoef, S = ud sqrt(beta)
+  const double Sb = Ab * sg * kInvSqrtPi * ex - 2.0 * S * B * Bb;
+  b.bcoef += Bb * ex;
+  u_b += Sb * s.sqb;
+  b.sqb += Sb * ud;
+  udb += u_b;
+}
+
+// Reverse of end_state: cotangent of the modified q from that of the state.
+__device__ __forceinline__ void end_state_rev(const Flow &P, double tx, double ty, double nx,
+                                              double ny, const EndState &s, const EndExtra &x,
+                                              const EndBar &b, double qb[4]) {
+  const double a = P.inv_gm1;
+  const double inv2b = 0.5 * x.ib;
+  // E = p a + rho uu / 2
+  double pb = b.p + a * b.E;
+  double rhob = b.rho + 0.5 * x.uu * b.E;
+  double uub = 0.5 * s.rho * b.E;
+  // (us, un) = rotation of (u, v)
+  double ub = b.us * tx + b.un * nx;
+  double vb = b.us * ty + b.un * ny;
+  // p = rho / (2 beta)
+  rhob += pb * inv2b;
+  double betab = -pb * s.p * x.ib;
+  // rho = exp(q1 + beta uu) beta^(-a)
+  qb[0] = rhob * s.rho;
+  uub += rhob * s.rho * x.beta;
+  betab += rhob * s.rho * (x.uu - a * x.ib);
+  // uu = u^2 + v^2
+  ub += 2.0 * x.u * uub;
+  vb += 2.0 * x.v * uub;
+  // u = q2 / (2 beta), v = q3 / (2 beta)
+  qb[1] = ub * inv2b;
+  qb[2] = vb * inv2b;
+  betab -= (ub * x.u + vb * x.v) * x.ib;
+  // sqb = sqrt(beta), bcoef = 1/(2 sqrt(pi beta))
+  betab += 0.5 * b.sqb * s.sqb * x.ib - 0.5 * b.bcoef * s.bcoef * x.ib;
+  // beta = -q4 / 2
+  qb[3] = -0.5 * betab;
+}
+
+// ---------------------------------------------------------------------------
+// flux residual, reverse: one thread per point, as the forward
+
+// Writes, for point i with residual cotangent Rb_i:
+//   T[k][i]    cotangent of the neighbour-end modified q of edge slot k;
+//   qbar_i, gbar_i, lbar_i   the own-end part of the cotangents of q, of the
+//              derivatives the flux uses and of the stencil bounds.
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_flux_rev(Geo G, Flow P, const double *__restrict__ q,
+                                                     const double *__restrict__ dq,
+                                                     const double *__restrict__ qlim,
+                                                     const double *__restrict__ Rb,
+                                                     double *__restrict__ T,
+                                                     double *__restrict__ qbar,
+                                                     double *__restrict__ gbar,
+                                                     double *__restrict__ lbar, unsigned *status) {
+  __shared__ double2 s_xy[BLK];
+  __shared__ F4 s_q[BLK];
+  __shared__ F8 s_g[BLK];
+  __shared__ F8 s_l[BLK];
+  const int n = G.n;
+  const int lo = tile_lo<BLK>(G.xcd);
+  const int i = lo + threadIdx.x;
+  const bool active = i < n;
+  double2 xi = make_double2(0.0, 0.0);
+  F4 q0{{0.0, 0.0, 0.0, 0.0}};
+  F8 g0{{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}}, l0 = g0;
+  if (active) {
+    xi = G.xy[i];
+    q0 = ld4(q, i);
+    g0 = ld8(dq, i);
+    l0 = ld8(qlim, i);
+  }
+  s_xy[threadIdx.x] = xi;
+  s_q[threadIdx.x] = q0;
+  s_g[threadIdx.x] = g0;
+  s_l[threadIdx.x] = l0;
+  __syncthreads();
+  if (!active) return;
+  const int kind = G.kind[i];
+  const int c = G.cnt[i];
+  if (kind == 2) {  // Dirichlet: R = 0 does not depend on anything
+    const F4 z4{{0.0, 0.0, 0.0, 0.0}};
+    const F8 z8{{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}};
+    for (int k = 0; k < c; ++k) st4_at(T, (size_t)k * n + i, z4);
+    st4(qbar, i, z4);
+    st8(gbar, i, z8);
+    st8(lbar, i, z8);
+    return;
+  }
+  const bool interior = kind == 0;
+  const double2 nv = G.nrm[i];
+  const double nx = nv.x, ny = nv.y, tx = ny, ty = -nx;
+  const Row row{G.nbr + i, n, c, i};
+  auto fetch_xy = [&](int j) {
+    int lj;
+    return in_tile<BLK>(j, lo, lj) ? s_xy[lj] : G.xy[j];
+  };
+
+  // pass 1: geometry of the four half-plane stencils (as the forward)
+  double sss[4] = {0, 0, 0, 0}, ssn[4] = {0, 0, 0, 0}, snn[4] = {0, 0, 0, 0};
+  int cnt[4] = {0, 0, 0, 0};
+  {
+    int j_next = row(1);
+    double2 xj = fetch_xy(row(0));
+    for (int k = 0; k < c; ++k) {
+      const int j_after = row(k + 2);
+      const double2 xn = fetch_xy(j_next);
+      const double dx = xj.x - xi.x, dy = xj.y - xi.y;
+      const double ds = dot_rn(dx, tx, dy, ty);
+      const double dn = dot_rn(dx, nx, dy, ny);
+      const bool in[4] = {ds < 0.0, ds > 0.0, interior && dn < 0.0, dn > 0.0};
+      for (int h = 0; h < 4; ++h) {
+        const double w = in[h] ? 1.0 : 0.0;
+        sss[h] += w * (ds * ds);
+        ssn[h] += w * (ds * dn);
+        snn[h] += w * (dn * dn);
+        cnt[h] += in[h] ? 1 : 0;
+      }
+      xj = xn;
+      j_next = j_after;
+    }
+  }
+  unsigned f = 0;
+  SplitW W[4];
+  for (int h = 0; h < 4; ++h) {
+    if (h == 2 && !interior) {
+      W[h] = SplitW{0.0, 0.0};
+      continue;
+    }
+    W[h] = split_weights(h < 2, cnt[h], sss[h], ssn[h], snn[h], f);
+  }
+
+  // seed: R = rotation of acc (mass, s-momentum, n-momentum, energy)
+  const F4 rb = ld4(Rb, i);
+  const double ab[4] = {rb.v[0], rb.v[1] * tx + rb.v[2] * ty, rb.v[1] * nx + rb.v[2] * ny,
+                        rb.v[3]};
+  double mx0[4], mn0[4];
+  for (int m = 0; m < 4; ++m) {
+    mx0[m] = l0.v[m] - q0.v[m];
+    mn0[m] = l0.v[4 + m] - q0.v[m];
+  }
+  const double K = P.venkat_k;
+  double qb0[4] = {0, 0, 0, 0};
+  double gb0[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double lb0[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+  int j_next = row(1);
+  int j_cur = row(0);
+  double2 xj = fetch_xy(j_cur);
+  for (int k = 0; k < c; ++k) {
+    const int j_after = row(k + 2);
+    const double2 xn = fetch_xy(j_next);
+    int lj;
+    F4 qj;
+    F8 gj, lj8;
+    if (in_tile<BLK>(j_cur, lo, lj)) {
+      qj = s_q[lj];
+      gj = s_g[lj];
+      lj8 = s_l[lj];
+    } else {
+      qj = ld4(q, j_cur);
+      gj = ld8(dq, j_cur);
+      lj8 = ld8(qlim, j_cur);
+    }
+    const double dx = xj.x - xi.x, dy = xj.y - xi.y;
+    const double ds = dot_rn(dx, tx, dy, ty);
+    const double dn = dot_rn(dx, nx, dy, ny);
+    const double eps2 = edge_eps2(K, dx, dy);
+    double qtj[4], qt0[4], d0[4];
+    for (int m = 0; m < 4; ++m) {
+      const double dj = half_step(dx, dy, gj.v[m], gj.v[4 + m]);
+      qtj[m] = qj.v[m] + limited(dj, lj8.v[m] - qj.v[m], lj8.v[4 + m] - qj.v[m], eps2);
+      d0[m] = half_step(dx, dy, g0.v[m], g0.v[4 + m]);
+      qt0[m] = q0.v[m] + limited(d0[m], mx0[m], mn0[m], eps2);
+    }
+    EndState sj, s0;
+    EndExtra xj_, x0_;
+    f |= end_state_t<true>(qtj, P, tx, ty, nx, ny, sj, &xj_);
+    f |= end_state_t<true>(qt0, P, tx, ty, nx, ny, s0, &x0_);
+    EndBar bj{0, 0, 0, 0, 0, 0, 0}, b0{0, 0, 0, 0, 0, 0, 0};
+
+    // s-direction split (ds < 0: G_s^+, ds > 0: G_s^-)
+    {
+      const bool pos = ds < 0.0;
+      const SplitW w = pos ? W[0] : W[1];
+      const double wt = ds != 0.0 ? w.a * ds + w.b * dn : 0.0;
+      if (wt != 0.0) {
+        const double sg = pos ? 1.0 : -1.0;
+        const double Gb[4] = {wt * ab[0], wt * ab[1], wt * ab[2], wt * ab[3]};
+        const double Gn[4] = {-Gb[0], -Gb[1], -Gb[2], -Gb[3]};
+        split_flux_rev(sg, sj, sj.us, sj.un, Gb, bj, bj.us, bj.un);
+        split_flux_rev(sg, s0, s0.us, s0.un, Gn, b0, b0.us, b0.un);
+      }
+    }
+    // n-direction split (dn < 0: G_n^+ at interior points, dn > 0: G_n^-)
+    {
+      const bool pos = dn < 0.0;
+      const SplitW w = pos ? W[2] : W[3];
+      const bool used = dn > 0.0 || (pos && interior);
+      const double wt = used ? w.a * ds + w.b * dn : 0.0;
+      if (wt != 0.0) {
+        const double sg = pos ? 1.0 : -1.0;
+        const double Gb[4] = {wt * ab[0], wt * ab[2], wt * ab[1], wt * ab[3]};
+        const double Gn[4] = {-Gb[0], -Gb[1], -Gb[2], -Gb[3]};
+        split_flux_rev(sg, sj, sj.un, sj.us, Gb, bj, bj.un, bj.us);
+        split_flux_rev(sg, s0, s0.un, s0.us, Gn, b0, b0.un, b0.us);
+      }
+    }
+    F4 tj;
+    double qtb0[4];
+    end_state_rev(P, tx, ty, nx, ny, sj, xj_, bj, tj.v);
+    end_state_rev(P, tx, ty, nx, ny, s0, x0_, b0, qtb0);
+    st4_at(T, (size_t)k * n + i, tj);
+    // own end: q~_0 = q_0 + phi delta_0, delta_0 = -(d . grad q_0)/2
+    for (int m = 0; m < 4; ++m) {
+      const LimRev r = limited_rev(d0[m], mx0[m], mn0[m], eps2, qtb0[m]);
+      qb0[m] += qtb0[m];
+      gb0[m] += -0.5 * dx * r.ddelta;
+      gb0[4 + m] += -0.5 * dy * r.ddelta;
+      if (r.sel > 0) {
+        lb0[m] += r.droom;
+        qb0[m] -= r.droom;
+      } else if (r.sel < 0) {
+        lb0[4 + m] += r.droom;
+        qb0[m] -= r.droom;
+      }
+    }
+    xj = xn;
+    j_cur = j_next;
+    j_next = j_after;
+  }
+  st4(qbar, i, F4{{qb0[0], qb0[1], qb0[2], qb0[3]}});
+  st8(gbar, i, F8{{gb0[0], gb0[1], gb0[2], gb0[3], gb0[4], gb0[5], gb0[6], gb0[7]}});
+  st8(lbar, i, F8{{lb0[0], lb0[1], lb0[2], lb0[3], lb0[4], lb0[5], lb0[6], lb0[7]}});
+  flag(status, f);
+}
+
+// s = M^-1 g per component: (s_x, s_y) = [[a, b], [b, c]] (g_x, g_y)
+__device__ __forceinline__ void apply_minv(const F8 &L, const double g[8], double s[8]) {
+  for (int m = 0; m < 4; ++m) {
+    s[m] = L.v[0] * g[m] + L.v[1] * g[4 + m];
+    s[4 + m] = L.v[1] * g[m] + L.v[2] * g[4 + m];
+  }
+}
+
+// Transposed gather of the flux reverse at point j: the neighbour-end limiter
+// reverse of every edge that reads j (T of that edge), added to the own-end
+// parts.  In place: qbar_j and lbar_j complete; sbar_j (holding the own-end
+// gbar_j on entry) becomes M_j^-1 gbar_j, the seed of the derivative reverse.
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_flux_gather(Geo G, Flow P,
+                                                        const int32_t *__restrict__ in_ptr,
+                                                        const int32_t *__restrict__ in_ent,
+                                                        const double *__restrict__ lsg,
+                                                        const double *__restrict__ q,
+                                                        const double *__restrict__ dq,
+                                                        const double *__restrict__ qlim,
+                                                        const double *__restrict__ T,
+                                                        double *__restrict__ qbar,
+                                                        double *__restrict__ sbar,
+                                                        double *__restrict__ lbar) {
+  __shared__ double2 s_xy[BLK];
+  const int n = G.n;
+  const int lo = tile_lo<BLK>(G.xcd);
+  const int j = lo + threadIdx.x;
+  const bool active = j < n;
+  const double2 xj = active ? G.xy[j] : make_double2(0.0, 0.0);
+  s_xy[threadIdx.x] = xj;
+  __syncthreads();
+  if (!active) return;
+  const F4 qj = ld4(q, j);
+  const F8 gj = ld8(dq, j), lj = ld8(qlim, j);
+  const F4 qb_own = ld4(qbar, j);
+  const F8 gb_own = ld8(sbar, j), lb_own = ld8(lbar, j);
+  double qb[4], gb[8], lb[8];
+  for (int m = 0; m < 4; ++m) qb[m] = qb_own.v[m];
+  for (int m = 0; m < 8; ++m) {
+    gb[m] = gb_own.v[m];
+    lb[m] = lb_own.v[m];
+  }
+  double rmax[4], rmin[4];
+  for (int m = 0; m < 4; ++m) {
+    rmax[m] = lj.v[m] - qj.v[m];
+    rmin[m] = lj.v[4 + m] - qj.v[m];
+  }
+  const double K = P.venkat_k;
+  const int e1 = in_ptr[j + 1];
+  for (int e = in_ptr[j]; e < e1; ++e) {
+    const int ent = in_ent[e];
+    const int i = ent & kPointMask;
+    const int slot = ent >> kSlotShift;
+    int li;
+    const double2 xi = in_tile<BLK>(i, lo, li) ? s_xy[li] : G.xy[i];
+    const F4 tb = ld4_at(T, (size_t)slot * n + i);
+    // the edge as row i sees it: d = x_j - x_i
+    const double dx = xj.x - xi.x, dy = xj.y - xi.y;
+    const double eps2 = edge_eps2(K, dx, dy);
+    for (int m = 0; m < 4; ++m) {
+      const double dl = half_step(dx, dy, gj.v[m], gj.v[4 + m]);
+      const LimRev r = limited_rev(dl, rmax[m], rmin[m], eps2, tb.v[m]);
+      qb[m] += tb.v[m];
+      gb[m] += -0.5 * dx * r.ddelta;
+      gb[4 + m] += -0.5 * dy * r.ddelta;
+      if (r.sel > 0) {
+        lb[m] += r.droom;
+        qb[m] -= r.droom;
+      } else if (r.sel < 0) {
+        lb[4 + m] += r.droom;
+        qb[m] -= r.droom;
+      }
+    }
+  }
+  double s[8];
+  apply_minv(ld8(lsg, j), gb, s);
+  st4(qbar, j, F4{{qb[0], qb[1], qb[2], qb[3]}});
+  st8(sbar, j, F8{{s[0], s[1], s[2], s[3], s[4], s[5], s[6], s[7]}});
+  st8(lbar, j, F8{{lb[0], lb[1], lb[2], lb[3], lb[4], lb[5], lb[6], lb[7]}});
+}
+
+// ---------------------------------------------------------------------------
+// least-squares derivatives, reverse
+//
+// A derivative pass computes dq_i = M_i^-1 sum_{j in N(i)} d_ij (q~_j - q~_i)
+// per component, with q~ = q - (d . g_prev)/2 (inner sweeps, d the edge
+// vector seen from i) or q~ = q (first-order pass).  With s_i = M_i^-1 gbar_i
+// (M symmetric), the cotangents are
+//   qbar_j      += d_ij . s_i                  (every row i listing j)
+//   qbar_i      -= (sum_j d_ij) . s_i
+//   gbar_prev_j -= d_ij (d_ij . s_i) / 2       (inner sweeps)
+//   gbar_prev_i += M_i s_i / 2 = gbar_i / 2    (inner sweeps)
+// so the next seed is s_prev_j = s_j/2 - M_j^-1 sum_i d_ij (d_ij . s_i) / 2.
+
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_inner_rev(Geo G, const int32_t *__restrict__ in_ptr,
+                                                      const int32_t *__restrict__ in_ent,
+                                                      const double *__restrict__ lsg,
+                                                      const double *__restrict__ s_in,
+                                                      double *__restrict__ qbar,
+                                                      double *__restrict__ s_out) {
+  __shared__ double2 s_xy[BLK];
+  __shared__ F8 s_s[BLK];
+  const int n = G.n;
+  const int lo = tile_lo<BLK>(G.xcd);
+  const int j = lo + threadIdx.x;
+  const bool active = j < n;
+  double2 xj = make_double2(0.0, 0.0);
+  F8 sj{{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}};
+  if (active) {
+    xj = G.xy[j];
+    sj = ld8(s_in, j);
+  }
+  s_xy[threadIdx.x] = xj;
+  s_s[threadIdx.x] = sj;
+  __syncthreads();
+  if (!active) return;
+  double aq[4] = {0, 0, 0, 0}, ax[4] = {0, 0, 0, 0}, ay[4] = {0, 0, 0, 0};
+  const int e1 = in_ptr[j + 1];
+  for (int e = in_ptr[j]; e < e1; ++e) {
+    const int i = in_ent[e] & kPointMask;
+    int li;
+    double2 xi;
+    F8 si;
+    if (in_tile<BLK>(i, lo, li)) {
+      xi = s_xy[li];
+      si = s_s[li];
+    } else {
+      xi = G.xy[i];
+      si = ld8(s_in, i);
+    }
+    const double dx = xj.x - xi.x, dy = xj.y - xi.y;
+    for (int m = 0; m < 4; ++m) {
+      const double t = dx * si.v[m] + dy * si.v[4 + m];
+      aq[m] += t;
+      ax[m] += dx * t;
+      ay[m] += dy * t;
+    }
+  }
+  const F8 L = ld8(lsg, j);
+  F4 qb = ld4(qbar, j);
+  F8 so;
+  for (int m = 0; m < 4; ++m) {
+    qb.v[m] += aq[m] - (L.v[3] * sj.v[m] + L.v[4] * sj.v[4 + m]);
+    so.v[m] = 0.5 * sj.v[m] - 0.5 * (L.v[0] * ax[m] + L.v[1] * ay[m]);
+    so.v[4 + m] = 0.5 * sj.v[4 + m] - 0.5 * (L.v[1] * ax[m] + L.v[2] * ay[m]);
+  }
+  st4(qbar, j, qb);
+  st8(s_out, j, so);
+}
+
+// First-order pass, reverse, then eq. (13) reverse: the cotangent of U.
+// Stencil bounds route their cotangent to the slot that attained them.
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_first_rev(Geo G, Flow P,
+                                                      const int32_t *__restrict__ in_ptr,
+                                                      const int32_t *__restrict__ in_ent,
+                                                      const double *__restrict__ lsg,
+                                                      const double *__restrict__ s0,
+                                                      const int8_t *__restrict__ argext,
+                                                      const double *__restrict__ lbar,
+                                                      const double *__restrict__ U,
+                                                      const double *__restrict__ qbar,
+                                                      double *__restrict__ Ubar) {
+  __shared__ double2 s_xy[BLK];
+  __shared__ F8 s_s[BLK];
+  const int n = G.n;
+  const int lo = tile_lo<BLK>(G.xcd);
+  const int j = lo + threadIdx.x;
+  const bool active = j < n;
+  double2 xj = make_double2(0.0, 0.0);
+  F8 sj{{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}};
+  if (active) {
+    xj = G.xy[j];
+    sj = ld8(s0, j);
+  }
+  s_xy[threadIdx.x] = xj;
+  s_s[threadIdx.x] = sj;
+  __syncthreads();
+  if (!active) return;
+  const uint64_t *arg = reinterpret_cast<const uint64_t *>(argext);
+  double qb[4];
+  {
+    const F4 o = ld4(qbar, j);
+    const F8 lo8 = ld8(lbar, j);
+    const uint64_t a = arg[j];
+    for (int m = 0; m < 4; ++m) {
+      qb[m] = o.v[m];
+      if ((int8_t)(a >> (8 * m)) == -1) qb[m] += lo8.v[m];
+      if ((int8_t)(a >> (8 * (4 + m))) == -1) qb[m] += lo8.v[4 + m];
+    }
+  }
+  const int e1 = in_ptr[j + 1];
+  for (int e = in_ptr[j]; e < e1; ++e) {
+    const int ent = in_ent[e];
+    const int i = ent & kPointMask;
+    const int slot = ent >> kSlotShift;
+    int li;
+    double2 xi;
+    F8 si;
+    if (in_tile<BLK>(i, lo, li)) {
+      xi = s_xy[li];
+      si = s_s[li];
+    } else {
+      xi = G.xy[i];
+      si = ld8(s0, i);
+    }
+    const double dx = xj.x - xi.x, dy = xj.y - xi.y;
+    for (int m = 0; m < 4; ++m) qb[m] += dx * si.v[m] + dy * si.v[4 + m];
+    const uint64_t a = arg[i];
+    bool hit = false;
+    for (int h = 0; h < 8; ++h) hit |= (int8_t)(a >> (8 * h)) == slot;
+    if (hit) {
+      const F8 li8 = ld8(lbar, i);
+      for (int m = 0; m < 4; ++m) {
+        if ((int8_t)(a >> (8 * m)) == slot) qb[m] += li8.v[m];
+        if ((int8_t)(a >> (8 * (4 + m))) == slot) qb[m] += li8.v[4 + m];
+      }
+    }
+  }
+  const F8 L = ld8(lsg, j);
+  for (int m = 0; m < 4; ++m) qb[m] -= L.v[3] * sj.v[m] + L.v[4] * sj.v[4 + m];
+
+  // eq. (13) reverse: q = (ln rho + a ln beta - beta uu, 2 beta u, 2 beta v,
+  // -2 beta), beta = rho/(2p), p = (gamma-1)(E - rho uu/2)
+  const double g = P.gamma, a = P.inv_gm1;
+  double rho, u, v, p;
+  prim_from_cons(g, ld4(U, j), rho, u, v, p);
+  const double beta = 0.5 * rho / p;
+  const double uu = u * u + v * v;
+  const double betab = qb[0] * (a / beta - uu) + 2.0 * u * qb[1] + 2.0 * v * qb[2] - 2.0 * qb[3];
+  double rhob = qb[0] / rho + betab / (2.0 * p);
+  const double pb = -betab * beta / p;
+  const double ub = -2.0 * beta * u * qb[0] + 2.0 * beta * qb[1];
+  const double vb = -2.0 * beta * v * qb[0] + 2.0 * beta * qb[2];
+  const double gm1 = g - 1.0;
+  F4 o;
+  o.v[0] = rhob + pb * gm1 * 0.5 * uu - (ub * u + vb * v) / rho;
+  o.v[1] = ub / rho - pb * gm1 * u;
+  o.v[2] = vb / rho - pb * gm1 * v;
+  o.v[3] = pb * gm1;
+  st4(Ubar, j, o);
+}
+
+// theta cotangent of cloud c (block c): the outer rows hold U_inf(M, alpha);
+// their cotangents are projected on dU_inf/d(M, alpha) and then cleared.
+__global__ void __launch_bounds__(kBlock) k_theta_rev(const int32_t *__restrict__ ooff,
+                                                      const int32_t *__restrict__ outer,
+                                                      const double *__restrict__ mach,
+                                                      const double *__restrict__ aoa,
+                                                      double *__restrict__ Ubar,
+                                                      double *__restrict__ thetabar) {
+  __shared__ double lds[kBlock];
+  const int c = blockIdx.x;
+  const double M = mach[c], ca = cos(aoa[c]), sa = sin(aoa[c]);
+  // U_inf = (1, M cos a, M sin a, p_inf/(gamma-1) + M^2/2)
+  double tm = 0.0, ta = 0.0;
+  for (int k = ooff[c] + (int)threadIdx.x; k < ooff[c + 1]; k += kBlock) {
+    const int j = outer[k];
+    const F4 b = ld4(Ubar, j);
+    tm += b.v[1] * ca + b.v[2] * sa + b.v[3] * M;
+    ta += -b.v[1] * M * sa + b.v[2] * M * ca;
+    st4(Ubar, j, F4{{0.0, 0.0, 0.0, 0.0}});
+  }
+  const double TM = block_sum(tm, lds);
+  __syncthreads();
+  const double TA = block_sum(ta, lds);
+  if (threadIdx.x == 0) {
+    thetabar[2 * c] = TM;
+    thetabar[2 * c + 1] = TA;
+  }
+}
+
+// Least-squares geometry of every point (built once per plan).
+__global__ void __launch_bounds__(kBlock) k_ls_geometry(Geo G, double *__restrict__ lsg) {
+  const int n = G.n;
+  const int i = point_index<kBlock>(G.xcd);
+  if (i >= n) return;
+  const double2 xi = G.xy[i];
+  const int c = G.cnt[i];
+  double sxx = 0.0, sxy = 0.0, syy = 0.0, sx = 0.0, sy = 0.0;
+  for (int k = 0; k < c; ++k) {
+    const double2 xj = G.xy[G.nbr[(size_t)k * n + i]];
+    const double dx = xj.x - xi.x, dy = xj.y - xi.y;
+    sxx += dx * dx;
+    sxy += dx * dy;
+    syy += dy * dy;
+    sx += dx;
+    sy += dy;
+  }
+  const double det = sxx * syy - sxy * sxy;
+  st8(lsg, i, F8{{syy / det, -sxy / det, sxx / det, sx, sy, 0.0, 0.0, 0.0}});
+}
+
+// ---------------------------------------------------------------------------
+// force coefficients, reverse
+
+__global__ void k_zero(size_t count, double *__restrict__ dst) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += stride)
+    dst[k] = 0.0;
+}
+
+// Cloud c (block c): with Cx, Cy recomputed, the cotangent Jb = (Jb_l, Jb_d)
+// of (Cl, Cd) gives Cx_b = -Jb_l sin a + Jb_d cos a, Cy_b = Jb_l cos a +
+// Jb_d sin a, Cp_b(e) = -Cx_b dy_e + Cy_b dx_e, and each wall point takes
+// half of the Cp cotangents of its two edges, divided by the dynamic pressure
+// (through p(U)).  theta: Cx, Cy scale as 1/M^2 at fixed U, and (Cl, Cd)
+// turns with alpha, so dJ/dM = -2 Jb.C/M and dJ/dalpha = -Jb_l Cd + Jb_d Cl.
+__global__ void __launch_bounds__(kBlock) k_force_rev(Geo G, Flow P,
+                                                      const int32_t *__restrict__ woff,
+                                                      const int32_t *__restrict__ wall,
+                                                      const double *__restrict__ mach,
+                                                      const double *__restrict__ aoa,
+                                                      const double *__restrict__ U,
+                                                      const double *__restrict__ Jb,
+                                                      double *__restrict__ Ubar,
+                                                      double *__restrict__ thetabar) {
+  __shared__ double lds[kBlock];
+  const int c = blockIdx.x;
+  const int w0 = woff[c], nw = woff[c + 1] - woff[c];
+  const double g = P.gamma, pinf = 1.0 / g;
+  const double M = mach[c], qinf = 0.5 * M * M;
+  const double ca = cos(aoa[c]), sa = sin(aoa[c]);
+  double fx = 0.0, fy = 0.0;
+  for (int e = threadIdx.x; e < nw; e += kBlock) {
+    const int a = wall[w0 + e], b = wall[w0 + (e + 1) % nw];
+    double ra, ua, va, pa, rb, ub, vb, pb;
+    prim_from_cons(g, ld4(U, a), ra, ua, va, pa);
+    prim_from_cons(g, ld4(U, b), rb, ub, vb, pb);
+    const double cp = (0.5 * (pa + pb) - pinf) / qinf;
+    const double2 xa = G.xy[a], xb = G.xy[b];
+    fx += -cp * (xb.y - xa.y);
+    fy += cp * (xb.x - xa.x);
+  }
+  const double Cx = block_sum(fx, lds);
+  __syncthreads();
+  const double Cy = block_sum(fy, lds);
+  const double jl = Jb[2 * c], jd = Jb[2 * c + 1];
+  const double cxb = -jl * sa + jd * ca, cyb = jl * ca + jd * sa;
+  for (int e = threadIdx.x; e < nw; e += kBlock) {
+    const int a = wall[w0 + e];
+    const int prev = wall[w0 + (e + nw - 1) % nw], next = wall[w0 + (e + 1) % nw];
+    const double2 xp = G.xy[prev], xa = G.xy[a], xn = G.xy[next];
+    // edges (prev, a) and (a, next)
+    const double cpb1 = -cxb * (xa.y - xp.y) + cyb * (xa.x - xp.x);
+    const double cpb2 = -cxb * (xn.y - xa.y) + cyb * (xn.x - xa.x);
+    const double p_b = 0.5 * (cpb1 + cpb2) / qinf;
+    double rho, u, v, p;
+    prim_from_cons(g, ld4(U, a), rho, u, v, p);
+    const double gm1 = g - 1.0;
+    st4(Ubar, a, F4{{p_b * gm1 * 0.5 * (u * u + v * v), -p_b * gm1 * u, -p_b * gm1 * v,
+                     p_b * gm1}});
+  }
+  if (threadIdx.x == 0) {
+    const double Cl = Cy * ca - Cx * sa, Cd = Cx * ca + Cy * sa;
+    thetabar[2 * c] = -2.0 * (jl * Cl + jd * Cd) / M;
+    thetabar[2 * c + 1] = -jl * Cd + jd * Cl;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+size_t f1_bytes(const lskum_plan_s *p) { return align256((size_t)p->n * sizeof(double)); }
+
+int n_levels(const lskum_plan_s *p) { return p->params[0].n_inner + 1; }
+
+// workspace layout, in units of one double per point (f1)
+struct VjpWs {
+  double *q, *dq0, *qlim, *qbar, *sa, *sb, *lbar, *T;
+  int8_t *argext;
+};
+
+VjpWs vjp_layout(const lskum_plan_s *p, void *ws) {
+  const size_t f1 = f1_bytes(p);
+  char *b = static_cast<char *>(ws);
+  VjpWs w;
+  size_t o = 0;
+  w.q = reinterpret_cast<double *>(b + o);
+  o += 4 * f1;
+  w.dq0 = reinterpret_cast<double *>(b + o);
+  o += 8 * f1 * (size_t)n_levels(p);
+  w.qlim = reinterpret_cast<double *>(b + o);
+  o += 8 * f1;
+  w.qbar = reinterpret_cast<double *>(b + o);
+  o += 4 * f1;
+  w.sa = reinterpret_cast<double *>(b + o);
+  o += 8 * f1;
+  w.sb = reinterpret_cast<double *>(b + o);
+  o += 8 * f1;
+  w.lbar = reinterpret_cast<double *>(b + o);
+  o += 8 * f1;
+  w.argext = reinterpret_cast<int8_t *>(b + o);
+  o += f1;
+  w.T = reinterpret_cast<double *>(b + o);
+  return w;
+}
+
+size_t vjp_bytes(const lskum_plan_s *p) {
+  const size_t f1 = f1_bytes(p);
+  const size_t fields = 4 + 8 * (size_t)n_levels(p) + 8 + 4 + 8 + 8 + 8 + 1;
+  return fields * f1 + align256((size_t)p->k_pad * (size_t)p->n * 4 * sizeof(double));
+}
+
+template <class T>
+int download(std::vector<T> &dst, const T *src, size_t count) {
+  dst.resize(count);
+  if (count && hipMemcpy(dst.data(), src, count * sizeof(T), hipMemcpyDeviceToHost) != hipSuccess)
+    return LSKUM_ERR_HIP;
+  return LSKUM_OK;
+}
+
+// Transposed connectivity, least-squares geometry and outer lists.
+// Synchronous.
+int adjoint_prepare(lskum_plan_s *p, void *stream) {
+  if (p->adj_ready) return LSKUM_OK;
+  if (p->n > kPointMask || p->k_pad > 64) return LSKUM_ERR_INVALID_ARG;
+  if (hipStreamSynchronize(S(stream)) != hipSuccess) return LSKUM_ERR_HIP;
+  const int32_t n = p->n, kp = p->k_pad;
+  std::vector<int32_t> nbr, cnt;
+  std::vector<int8_t> kind;
+  std::vector<int32_t> in_ptr, in_ent, outer, ooff;
+  int rc = LSKUM_OK;
+  try {
+    if ((rc = download(nbr, p->nbr, (size_t)n * kp)) || (rc = download(cnt, p->cnt, (size_t)n)) ||
+        (rc = download(kind, p->kind, (size_t)n)))
+      return rc;
+    in_ptr.assign((size_t)n + 1, 0);
+    int64_t nnz = 0;
+    for (int32_t i = 0; i < n; ++i)
+      for (int32_t s = 0; s < cnt[(size_t)i]; ++s) {
+        ++in_ptr[(size_t)nbr[(size_t)s * n + i] + 1];
+        ++nnz;
+      }
+    if (nnz > INT32_MAX) return LSKUM_ERR_INVALID_ARG;
+    for (int32_t j = 0; j < n; ++j) in_ptr[(size_t)j + 1] += in_ptr[(size_t)j];
+    in_ent.resize((size_t)nnz);
+    std::vector<int32_t> fill(in_ptr.begin(), in_ptr.end() - 1);
+    for (int32_t i = 0; i < n; ++i)  // i ascending, then slot: entries sorted
+      for (int32_t s = 0; s < cnt[(size_t)i]; ++s) {
+        const int32_t j = nbr[(size_t)s * n + i];
+        in_ent[(size_t)fill[(size_t)j]++] = (s << kSlotShift) | i;
+      }
+    ooff.push_back(0);
+    for (int32_t c = 0; c < p->n_clouds; ++c) {
+      for (int32_t i = p->offset[(size_t)c]; i < p->offset[(size_t)c + 1]; ++i)
+        if (kind[(size_t)i] == 2) outer.push_back(i);
+      ooff.push_back((int32_t)outer.size());
+    }
+    p->n_in = nnz;
+  } catch (const std::bad_alloc &) {
+    return LSKUM_ERR_NO_MEMORY;
+  }
+  if ((rc = upload(&p->in_ptr, in_ptr.data(), in_ptr.size())) ||
+      (rc = upload(&p->in_ent, in_ent.data(), in_ent.size())) ||
+      (rc = upload(&p->outer, outer.data(), outer.size())) ||
+      (rc = upload(&p->ooff, ooff.data(), ooff.size())))
+    return rc;
+  if (hipMalloc((void **)&p->lsg, (size_t)n * 8 * sizeof(double)) != hipSuccess)
+    return LSKUM_ERR_NO_MEMORY;
+  k_ls_geometry<<<grid_for(n), kBlock, 0, S(stream)>>>(geo(p), p->lsg);
+  if ((rc = launched())) return rc;
+  if (hipStreamSynchronize(S(stream)) != hipSuccess) return LSKUM_ERR_HIP;
+  p->adj_ready = true;
+  return LSKUM_OK;
+}
+
+// free whatever a failed preparation left
+void adjoint_reset(lskum_plan_s *p) {
+  void *bufs[] = {p->in_ptr, p->in_ent, p->lsg, p->outer, p->ooff};
+  for (void *b : bufs) (void)hipFree(b);
+  p->in_ptr = p->in_ent = p->outer = p->ooff = nullptr;
+  p->lsg = nullptr;
+  p->adj_ready = false;
+}
+
+#define LSKUM_TILED_ADJ(kern, p, stream, ...)                                                \
+  do {                                                                                       \
+    const int g_ = grid_for((p)->n, (p)->block);                                             \
+    switch ((p)->block) {                                                                    \
+      case 128: kern<128><<<g_, 128, 0, S(stream)>>>(__VA_ARGS__); break;                    \
+      case 512: kern<512><<<g_, 512, 0, S(stream)>>>(__VA_ARGS__); break;                    \
+      default: kern<256><<<g_, 256, 0, S(stream)>>>(__VA_ARGS__); break;                     \
+    }                                                                                        \
+  } while (0)
+
+}  // namespace
+}  // namespace lskum_impl
+
+using namespace lskum_impl;
+
+extern "C" {
+
+size_t lskum_vjp_workspace_bytes(lskum_plan p) {
+  if (!p) return 0;
+  return vjp_bytes(p);
+}
+
+int lskum_flux_residual_vjp(lskum_plan p, const double *U, const double *Rbar, double *Ubar,
+                            double *thetabar, void *ws, void *stream) {
+  if (!p || !a32(U) || !a32(Rbar) || !a32(Ubar) || !thetabar || !ws ||
+      ((uintptr_t)ws % 256) != 0)
+    return LSKUM_ERR_INVALID_ARG;
+  int rc = adjoint_prepare(p, stream);
+  if (rc) {
+    adjoint_reset(p);
+    return rc;
+  }
+  const VjpWs w = vjp_layout(p, ws);
+  const int K = p->params[0].n_inner;
+  const size_t lev = 8 * f1_bytes(p) / sizeof(double);  // doubles between iterates
+  const Geo g = geo(p);
+  const Flow f = flow(p);
+  // forward recompute: q, first-order derivatives with bound slots, iterates
+  if ((rc = q_vars_launch(p, U, w.q, stream))) return rc;
+  if ((rc = deriv_first_launch(p, w.q, w.dq0, w.qlim, w.argext, stream))) return rc;
+  for (int k = 1; k <= K; ++k)
+    if ((rc = deriv_inner_launch(p, w.q, w.dq0 + (k - 1) * lev, w.dq0 + k * lev, stream)))
+      return rc;
+  const double *dqK = w.dq0 + (size_t)K * lev;
+  // reverse: flux, its transposed gather, inner sweeps K..1, first-order pass
+  LSKUM_TILED_ADJ(k_flux_rev, p, stream, g, f, w.q, dqK, w.qlim, Rbar, w.T, w.qbar, w.sa, w.lbar,
+                  p->status);
+  LSKUM_TILED_ADJ(k_flux_gather, p, stream, g, f, p->in_ptr, p->in_ent, p->lsg, w.q, dqK, w.qlim,
+                  w.T, w.qbar, w.sa, w.lbar);
+  double *cur = w.sa, *nxt = w.sb;
+  for (int k = K; k >= 1; --k) {
+    LSKUM_TILED_ADJ(k_inner_rev, p, stream, g, p->in_ptr, p->in_ent, p->lsg, cur, w.qbar, nxt);
+    double *t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  LSKUM_TILED_ADJ(k_first_rev, p, stream, g, f, p->in_ptr, p->in_ent, p->lsg, cur, w.argext,
+                  w.lbar, U, w.qbar, Ubar);
+  k_theta_rev<<<p->n_clouds, kBlock, 0, S(stream)>>>(p->ooff, p->outer, p->mach, p->aoa, Ubar,
+                                                     thetabar);
+  return launched();
+}
+
+int lskum_force_coeffs_vjp(lskum_plan p, const double *U, const double *Jbar, double *Ubar,
+                           double *thetabar, void *stream) {
+  if (!p || !a32(U) || !Jbar || !a32(Ubar) || !thetabar) return LSKUM_ERR_INVALID_ARG;
+  const size_t count = 4 * (size_t)p->n;
+  k_zero<<<grid_for((int)std::min<size_t>(count, (size_t)1 << 24)), kBlock, 0, S(stream)>>>(count,
+                                                                                          Ubar);
+  k_force_rev<<<p->n_clouds, kBlock, 0, S(stream)>>>(geo(p), flow(p), p->woff, p->wall, p->mach,
+                                                     p->aoa, U, Jbar, Ubar, thetabar);
+  return launched();
+}
+
+}  // extern "C"

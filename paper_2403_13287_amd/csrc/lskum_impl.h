@@ -1,0 +1,372 @@
+// lskum_impl.h -- internals of the LSKUM library shared by its translation
+// units (forward sweep and adjoint): device helpers, the plan record and host
+// launch helpers.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+#include "lskum.h"
+#include "lskum_math.h"
+
+namespace lskum_impl {
+
+using lskum_math::lk_div;
+using lskum_math::lk_rsqrt;
+
+constexpr int kBlock = 256;
+constexpr int kXcds = 8;
+constexpr int kNormChunk = 2048;  // points per residual-norm chunk
+constexpr unsigned kFlagNonPhysical = 1u;
+constexpr unsigned kFlagDegenerate = 2u;
+
+struct Geo {
+  int n;
+  int xcd;  // 1: blocks relabelled so that each XCD walks one contiguous range
+  const double2 *xy;
+  const double2 *nrm;
+  const int8_t *kind;
+  const int32_t *nbr;    // [k_pad][n]
+  const int32_t *cnt;
+  const int32_t *cloud;  // [n] cloud of each point (batched plans)
+  const double *uinf;    // [n_clouds][4] free-stream state of each cloud
+};
+
+struct Flow {
+  double gamma, inv_gm1, cfl, venkat_k;
+  bool gamma_is_14;  // gamma == 1.4 exactly: rho from beta^(-5/2) without a log
+};
+
+// point records
+struct __attribute__((aligned(32))) F4 {
+  double v[4];
+};
+struct __attribute__((aligned(64))) F8 {
+  double v[8];
+};
+
+__device__ __forceinline__ F4 ld4(const double *f, int i) {
+  return reinterpret_cast<const F4 *>(f)[i];
+}
+__device__ __forceinline__ F8 ld8(const double *f, int i) {
+  return reinterpret_cast<const F8 *>(f)[i];
+}
+__device__ __forceinline__ void st4(double *f, int i, const F4 &v) {
+  reinterpret_cast<F4 *>(f)[i] = v;
+}
+__device__ __forceinline__ void st8(double *f, int i, const F8 &v) {
+  reinterpret_cast<F8 *>(f)[i] = v;
+}
+// records addressed by a 64-bit index (edge-slot arrays)
+__device__ __forceinline__ F4 ld4_at(const double *f, size_t i) {
+  return reinterpret_cast<const F4 *>(f)[i];
+}
+__device__ __forceinline__ void st4_at(double *f, size_t i, const F4 &v) {
+  reinterpret_cast<F4 *>(f)[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers
+
+// Blocks are dispatched to the 8 XCDs round-robin.  With xcd set, re-label
+// them so that XCD x processes one contiguous range of logical blocks.  The
+// grid is a multiple of 8; threads past n exit at once.
+__device__ __forceinline__ int block_id(int xcd) {
+  if (!xcd) return blockIdx.x;
+  const int per = gridDim.x / kXcds;
+  return (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+}
+
+template <int BLK>
+__device__ __forceinline__ int point_index(int xcd) {
+  return block_id(xcd) * BLK + threadIdx.x;
+}
+
+inline int grid_for(int n, int blk = kBlock) {
+  int nb = (n + blk - 1) / blk;
+  return (nb + kXcds - 1) / kXcds * kXcds;
+}
+
+// ds = dx*tx + dy*ty and dn = dx*nx + dy*ny with every product and sum
+// rounded separately (no FMA contraction): the sign of ds/dn decides
+// split-stencil membership, and this matches the oracle's uncontracted
+// evaluation bit for bit.
+__device__ __forceinline__ double dot_rn(double a, double b, double c, double d) {
+#pragma clang fp contract(off)
+  const double ab = a * b;
+  const double cd = c * d;
+  return ab + cd;
+}
+
+__device__ __forceinline__ void flag(unsigned *status, unsigned f) {
+  if (f) __hip_atomic_fetch_or(status, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// eq. (13) and its inverse
+
+__device__ __forceinline__ void prim_from_cons(double g, const F4 &U, double &rho, double &u,
+                                               double &v, double &p) {
+  rho = U.v[0];
+  u = U.v[1] / rho;
+  v = U.v[2] / rho;
+  p = (g - 1.0) * (U.v[3] - 0.5 * rho * (u * u + v * v));
+}
+
+// ---------------------------------------------------------------------------
+// block tiles
+//
+// A block owns BLK consecutive points (one Hilbert tile; BLK is the tuned
+// block size, 128, 256 or 512).  Kernels that gather neighbour records first
+// stage the tile's own records in LDS; about 80 % of the neighbours of a
+// 1M-point airfoil cloud fall inside their own 256-point tile, so most
+// gathers become LDS reads and only the remote ones go through the vector
+// memory path.
+
+template <int BLK>
+__device__ __forceinline__ int tile_lo(int xcd) {
+  return block_id(xcd) * BLK;
+}
+
+// lj = j - lo; true when j belongs to the tile starting at lo
+template <int BLK>
+__device__ __forceinline__ bool in_tile(int j, int lo, int &lj) {
+  lj = j - lo;
+  return (unsigned)lj < (unsigned)BLK;
+}
+
+// Reader of point i's neighbour row (column-major connectivity).  Slots at
+// or past the row's count read the last real slot and return i itself, so
+// prefetching ahead never leaves the row: gather loops fetch the index two
+// neighbours ahead and the neighbour's records one ahead, which keeps two
+// dependent memory round trips off each iteration.
+struct Row {
+  const int32_t *col;  // &nbr[i], stride n
+  int n, c, i;
+  __device__ __forceinline__ int operator()(int k) const {
+    const int kk = k < c ? k : c - 1;
+    const int j = col[(size_t)kk * n];
+    return k < c ? j : i;
+  }
+};
+
+// Venkatakrishnan-limited increment phi*delta of one q component at one end
+// of an edge: D is the room to the stencil max (delta > 0) or min (delta < 0),
+// phi = min(1, (D^2 + eps2 + 2 delta D)/(D^2 + 2 delta^2 + delta D + eps2)),
+// phi = 1 for delta = 0.
+__device__ __forceinline__ double limited(double delta, double room_max, double room_min,
+                                          double eps2) {
+  const double D = delta > 0.0 ? room_max : room_min;
+  const double num = D * D + eps2 + 2.0 * delta * D;
+  const double den = D * D + 2.0 * delta * delta + delta * D + eps2;
+  const double phi = delta == 0.0 ? 1.0 : fmin(1.0, lk_div(num, den));
+  return phi * delta;
+}
+
+// Limiter constant of an edge: eps^2 = (K |d|)^3.
+__device__ __forceinline__ double edge_eps2(double K, double dx, double dy) {
+  const double d2 = dx * dx + dy * dy;
+  const double kd = K * (d2 > 0.0 ? d2 * lk_rsqrt(d2) : 0.0);
+  return kd * kd * kd;
+}
+
+// Increment of the modified q of eq. (14) at one end of edge d:
+// -(d . grad q)/2.
+__device__ __forceinline__ double half_step(double dx, double dy, double gx, double gy) {
+  return -0.5 * (dx * gx + dy * gy);
+}
+
+// State at one end of an edge, recovered from the limited modified q.
+struct EndState {
+  double rho, us, un, p, E;
+  double sqb;    // sqrt(beta)
+  double bcoef;  // 1 / (2 sqrt(pi beta))
+};
+
+// Inverse of eq. (13): beta = -q4/2, (u, v) = (q2, q3)/(2 beta),
+// rho = exp(q1 + beta (u^2+v^2)) beta^(-1/(gamma-1)), p = rho/(2 beta).
+// For gamma = 1.4 the power is beta^(-5/2) = rsqrt(beta) / beta^2, so one
+// rsqrt gives sqrt(beta), 1/beta and the power without a log or a divide.
+// Intermediates of end_state kept for the adjoint.
+struct EndExtra {
+  double beta, ib, u, v, uu;  // ib = 1/beta
+};
+
+template <bool KEEP>
+__device__ __forceinline__ unsigned end_state_t(const double qt[4], const Flow &P, double tx,
+                                                double ty, double nx, double ny, EndState &s,
+                                                EndExtra *x) {
+  constexpr double kHalfRsqrtPi = 0.28209479177387814347;  // 1 / (2 sqrt(pi))
+  const double beta = -0.5 * qt[3];
+  const double rsb = lk_rsqrt(beta);
+  const double ib = rsb * rsb;
+  const double inv2b = 0.5 * ib;
+  const double u = qt[1] * inv2b;
+  const double v = qt[2] * inv2b;
+  const double uu = u * u + v * v;
+  double rho;
+  if (P.gamma_is_14)
+    rho = exp(qt[0] + beta * uu) * (rsb * ib * ib);
+  else
+    rho = exp(qt[0] + beta * uu - log(beta) * P.inv_gm1);
+  const double p = rho * inv2b;
+  s.rho = rho;
+  s.p = p;
+  s.us = u * tx + v * ty;
+  s.un = u * nx + v * ny;
+  s.E = p * P.inv_gm1 + 0.5 * rho * uu;
+  s.sqb = beta * rsb;
+  s.bcoef = kHalfRsqrtPi * rsb;
+  if (KEEP) *x = EndExtra{beta, ib, u, v, uu};
+  return (!(beta > 0.0) || !(rho > 0.0) || !(p > 0.0) || !isfinite(rho) || !isfinite(p))
+             ? kFlagNonPhysical
+             : 0u;
+}
+
+__device__ __forceinline__ unsigned end_state(const double qt[4], const Flow &P, double tx,
+                                              double ty, double nx, double ny, EndState &s) {
+  return end_state_t<false>(qt, P, tx, ty, nx, ny, s, nullptr);
+}
+
+// Kinetic split flux along direction d with sign sg (+1 or -1): half-range
+// moments of the Maxwellian of eq. (2) under the CIR split of eq. (3).
+// ud: velocity along d, uo: the other component.  Output (mass, d-momentum,
+// o-momentum, energy).
+__device__ __forceinline__ void split_flux(double sg, const EndState &s, double ud, double uo,
+                                           double G[4]) {
+  const double S = ud * s.sqb;
+  const double A = 0.5 * (1.0 + sg * erf(S));
+  const double B = exp(-(S * S)) * s.bcoef;
+  const double F = ud * A + sg * B;
+  G[0] = s.rho * F;
+  G[1] = (s.p + s.rho * ud * ud) * A + sg * s.rho * ud * B;
+  G[2] = s.rho * uo * F;
+  G[3] = (s.E + s.p) * ud * A + sg * (s.E + 0.5 * s.p) * B;
+}
+
+// Least-squares weights of one half-plane stencil: for an s-split the
+// derivative is sum_i (Snn ds_i - Ssn dn_i)/det * dG_i, for an n-split
+// sum_i (Sss dn_i - Ssn ds_i)/det * dG_i (eq. (11) in the (s, n) frame).
+struct SplitW {
+  double a, b;  // weight of edge i = a*ds_i + b*dn_i
+};
+
+__device__ __forceinline__ SplitW split_weights(bool s_dir, int count, double sss, double ssn,
+                                                double snn, unsigned &f) {
+  const double det = sss * snn - ssn * ssn;
+  if (count < 2 || !(det > 1e-12 * sss * snn)) {
+    f |= kFlagDegenerate;
+    return SplitW{0.0, 0.0};
+  }
+  const double inv = 1.0 / det;
+  return s_dir ? SplitW{snn * inv, -ssn * inv} : SplitW{-ssn * inv, sss * inv};
+}
+
+// Sum over the block (blockDim.x a power of two), fixed order.
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+  lds[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
+    __syncthreads();
+  }
+  return lds[0];
+}
+
+// in-edge entries of the adjoint: slot in the source row, source point
+constexpr int kSlotShift = 25;
+constexpr int32_t kPointMask = (1 << kSlotShift) - 1;
+
+}  // namespace lskum_impl
+
+// ---------------------------------------------------------------------------
+// plan
+
+struct lskum_plan_s {
+  int device = 0;
+  int32_t n = 0, k_pad = 0, n_clouds = 0, n_wall = 0, n_chunks = 0;
+  int block = 256, xcd = 1;
+  std::vector<lskum_params> params;  // one per cloud
+  std::vector<int32_t> offset;       // first point of each cloud (+ total)
+  double2 *xy = nullptr, *nrm = nullptr;
+  int8_t *kind = nullptr;
+  int32_t *nbr = nullptr, *cnt = nullptr, *cloud = nullptr;
+  int32_t *wall = nullptr, *woff = nullptr;  // concatenated wall loops, offsets [n_clouds+1]
+  double *uinf = nullptr;                    // [n_clouds][4]
+  double *mach = nullptr, *aoa = nullptr;    // [n_clouds]
+  int2 *chunks = nullptr;                    // residual-norm chunks
+  int32_t *chunk_first = nullptr;            // first chunk of each cloud [n_clouds+1]
+  double *partial = nullptr;                 // [n_chunks]
+  double *norm_scratch = nullptr;            // [n_clouds]
+  int32_t *counter = nullptr;                // graph-replay iteration counter
+  unsigned *status = nullptr;
+  // adjoint data, built by the first VJP call on the plan
+  bool adj_ready = false;
+  int64_t n_in = 0;               // real edges
+  int32_t *in_ptr = nullptr;      // [n+1] in-edges of each point (CSR)
+  int32_t *in_ent = nullptr;      // [n_in] (slot << kSlotShift) | source point
+  double *lsg = nullptr;          // [n][8] least-squares geometry of each point
+  int32_t *outer = nullptr;       // outer points, grouped by cloud
+  int32_t *ooff = nullptr;        // [n_clouds+1] offsets into outer
+};
+
+namespace lskum_impl {
+
+inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline Geo geo(const lskum_plan_s *p) {
+  return Geo{p->n, p->xcd, p->xy, p->nrm, p->kind, p->nbr, p->cnt, p->cloud, p->uinf};
+}
+
+inline Flow flow(const lskum_plan_s *p) {
+  Flow f;
+  const lskum_params &q = p->params[0];  // shared settings (validated equal)
+  f.gamma = q.gamma;
+  f.inv_gm1 = 1.0 / (q.gamma - 1.0);
+  f.cfl = q.cfl;
+  f.venkat_k = q.venkat_k;
+  f.gamma_is_14 = q.gamma == 1.4;
+  return f;
+}
+
+inline int launched() { return hipGetLastError() == hipSuccess ? LSKUM_OK : LSKUM_ERR_HIP; }
+
+// 4-double records need 32-byte, 8-double records 64-byte alignment.
+inline bool a32(const void *p) { return p && ((uintptr_t)p % 32) == 0; }
+inline bool a64(const void *p) { return p && ((uintptr_t)p % 64) == 0; }
+
+template <class T>
+int upload(T **dst, const void *src, size_t count) {
+  if (hipMalloc((void **)dst, count * sizeof(T) + (count == 0 ? sizeof(T) : 0)) != hipSuccess)
+    return LSKUM_ERR_NO_MEMORY;
+  if (count && hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return LSKUM_ERR_HIP;
+  return LSKUM_OK;
+}
+
+inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// kernel launches with the plan's tile size
+#define LSKUM_TILED(kern, p, stream, ...)                                                    \
+  do {                                                                                       \
+    const int g_ = grid_for((p)->n, (p)->block);                                             \
+    switch ((p)->block) {                                                                    \
+      case 128: kern<128><<<g_, 128, 0, S(stream)>>>(__VA_ARGS__); break;                    \
+      case 512: kern<512><<<g_, 512, 0, S(stream)>>>(__VA_ARGS__); break;                    \
+      default: kern<256><<<g_, 256, 0, S(stream)>>>(__VA_ARGS__); break;                     \
+    }                                                                                        \
+  } while (0)
+
+// launchers of the forward kernels (lskum.hip), reused by the adjoint
+int q_vars_launch(lskum_plan_s *p, const double *U, double *q, void *stream);
+// argext (nullable): per point and component, the stencil slot that attains
+// qlim (-1: the point itself), rows 0..3 for the max, 4..7 for the min
+int deriv_first_launch(lskum_plan_s *p, const double *q, double *dq, double *qlim,
+                       int8_t *argext, void *stream);
+int deriv_inner_launch(lskum_plan_s *p, const double *q, const double *dqp, double *dqn,
+                       void *stream);
+
+}  // namespace lskum_impl

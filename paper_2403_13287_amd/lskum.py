@@ -80,6 +80,10 @@ _SIGS = {
     "lskum_status": (ctypes.c_int, "vv"),
     "lskum_clear_status": (ctypes.c_int, "vv"),
     "lskum_strerror": (ctypes.c_char_p, "i"),
+    "lskum_set_far_field": (ctypes.c_int, "vvv"),
+    "lskum_vjp_workspace_bytes": (ctypes.c_size_t, "v"),
+    "lskum_flux_residual_vjp": (ctypes.c_int, "vvvvvvv"),
+    "lskum_force_coeffs_vjp": (ctypes.c_int, "vvvvvv"),
 }
 _CT = {"v": ctypes.c_void_p, "i": ctypes.c_int32, "d": ctypes.c_double}
 
@@ -133,9 +137,13 @@ class Params:
     venkat_k: float = 5.0
     n_inner: int = 2
     gamma: float = 1.4
+    aoa_rad: float | None = None  # if set, the angle in radians (aoa_deg ignored)
+
+    def alpha(self) -> float:
+        return float(self.aoa_rad) if self.aoa_rad is not None else math.radians(self.aoa_deg)
 
     def c(self) -> _Params:
-        return _Params(self.gamma, self.mach, math.radians(self.aoa_deg), self.cfl,
+        return _Params(self.gamma, self.mach, self.alpha(), self.cfl,
                        self.venkat_k, int(self.n_inner), 0)
 
 
@@ -314,6 +322,46 @@ def lskum_iterate(plan: Plan, iters: int, U, hist, ws, stream=None):
         raise ValueError("ws: need a cuda tensor of lskum_workspace_bytes(plan) bytes")
     _check(plan.lib.lskum_iterate(plan.handle, int(iters), plan._arg(U, 4, "U"), hp, ws.data_ptr(),
                                   _stream(stream)), "lskum_iterate")
+
+
+def lskum_set_far_field(plan: Plan, U, stream=None):
+    _check(plan.lib.lskum_set_far_field(plan.handle, plan._arg(U, 4, "U"), _stream(stream)),
+           "lskum_set_far_field")
+
+
+def lskum_vjp_workspace_bytes(plan: Plan) -> int:
+    return int(plan.lib.lskum_vjp_workspace_bytes(plan.handle))
+
+
+def vjp_workspace(plan: Plan) -> torch.Tensor:
+    ws = torch.empty(lskum_vjp_workspace_bytes(plan), dtype=torch.uint8,
+                     device=f"cuda:{plan.device}")
+    if ws.data_ptr() % 256:
+        raise RuntimeError("workspace not 256-byte aligned")
+    return ws
+
+
+def lskum_flux_residual_vjp(plan: Plan, U, Rbar, Ubar, thetabar, ws, stream=None):
+    """Ubar (n, 4) and thetabar (n_clouds, 2) = (Mach, alpha [rad]) cotangents."""
+    if not isinstance(ws, torch.Tensor) or not ws.is_cuda or \
+            ws.numel() < lskum_vjp_workspace_bytes(plan):
+        raise ValueError("ws: need a cuda tensor of lskum_vjp_workspace_bytes(plan) bytes")
+    _check(plan.lib.lskum_flux_residual_vjp(plan.handle, plan._arg(U, 4, "U"),
+                                            plan._arg(Rbar, 4, "Rbar"), plan._arg(Ubar, 4, "Ubar"),
+                                            _scalar_out(plan, thetabar, 2 * plan.n_clouds,
+                                                        "thetabar"),
+                                            ws.data_ptr(), _stream(stream)),
+           "lskum_flux_residual_vjp")
+
+
+def lskum_force_coeffs_vjp(plan: Plan, U, Jbar, Ubar, thetabar, stream=None):
+    """Jbar: (n_clouds, 2) weights of (Cl, Cd); Ubar (n, 4); thetabar (n_clouds, 2)."""
+    _check(plan.lib.lskum_force_coeffs_vjp(plan.handle, plan._arg(U, 4, "U"),
+                                           _scalar_out(plan, Jbar, 2 * plan.n_clouds, "Jbar"),
+                                           plan._arg(Ubar, 4, "Ubar"),
+                                           _scalar_out(plan, thetabar, 2 * plan.n_clouds,
+                                                       "thetabar"),
+                                           _stream(stream)), "lskum_force_coeffs_vjp")
 
 
 def lskum_status(plan: Plan, stream=None) -> int:
