@@ -200,6 +200,98 @@ def bench_batch(args) -> int:
     return 0 if status == L.OK and loop_status == L.OK else 1
 
 
+def bench_adjoint(args) -> int:
+    """Cost of the residual VJP (q and every derivative iterate recomputed)
+    against one forward residual evaluation (q-variables, q-derivatives,
+    flux residual) on the 1M-point cloud at M 0.63, AoA 2 deg, three inner
+    sweeps; the state is the free stream advanced a few hundred iterations,
+    the cotangents are N(0, 1) draws with seed 7."""
+    import numpy as np
+    import torch
+
+    from cloudgen import named_cloud
+    from paper_2403_13287_amd import lskum as L
+    from paper_2403_13287_amd.solver import Solver
+
+    torch.cuda.set_device(0)
+    reps = 20 if args.steps is None else args.steps
+    state_iters = 300
+    log("[bench] generating the 1m cloud (1000 x 1000)")
+    cloud = named_cloud("1m")
+    params = L.Params(0.63, 2.0, 0.2, 5.0, 3)
+    s = Solver(cloud, params)
+    s.run(state_iters)
+    torch.cuda.synchronize()
+    plan, U, n = s.plan, s.U, s.n
+    gen = torch.Generator().manual_seed(7)
+    Rb = torch.randn((n, 4), generator=gen, dtype=torch.float64).cuda()
+    Jb = torch.tensor([1.0, 0.0], dtype=torch.float64, device="cuda")
+    q, dq, qlim, work, R = (plan.field(c) for c in (4, 8, 8, 8, 4))
+    Ub, Fb = plan.field(4), plan.field(4)
+    tb = torch.empty(2, dtype=torch.float64, device="cuda")
+    ws = L.vjp_workspace(plan)
+
+    def forward():
+        L.lskum_q_vars(plan, U, q)
+        L.lskum_q_derivs(plan, q, dq, qlim, work)
+        L.lskum_flux_residual(plan, q, dq, qlim, R)
+
+    def vjp():
+        L.lskum_flux_residual_vjp(plan, U, Rb, Ub, tb, ws)
+
+    def force_vjp():
+        L.lskum_force_coeffs_vjp(plan, U, Jb, Fb, tb)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    vjp()  # builds the plan's transposed connectivity once
+    torch.cuda.synchronize()
+    t_fwd = timed(forward)
+    t_vjp = timed(vjp)
+    t_force = timed(force_vjp)
+    status = s.status()
+    ratio = t_vjp / t_fwd
+    log(f"[bench] forward {t_fwd:.4f} ms, vjp {t_vjp:.4f} ms, ratio {ratio:.3f}, "
+        f"force vjp {t_force:.4f} ms, status {status}")
+    out = {
+        "metric": "adjoint/forward time ratio (residual VJP incl. recompute / forward residual)",
+        "value": ratio,
+        "unit": "x",
+        "n_gpus": 1,
+        "steps": reps,
+        "warmup": args.warmup,
+        "ms_per_step": t_vjp,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "adjoint: NACA 0012 O-type airfoil cloud 1000 x 1000, k_max 30, "
+                               f"M 0.63, AoA 2 deg, n_inner 3, state = free stream + {state_iters} "
+                               "iterations, cotangents N(0,1) seed 7",
+                   "points": n, "edges": int(cloud.nbr_count.astype(np.int64).sum())},
+        "forward_ms": t_fwd,
+        "vjp_ms": t_vjp,
+        "force_vjp_ms": t_force,
+        "vjp_workspace_bytes": L.lskum_vjp_workspace_bytes(plan),
+        "status": L.strerror(status),
+        "finite": bool(torch.isfinite(Ub).all()),
+    }
+    print(json.dumps(out), flush=True)
+    return 0 if status == L.OK and out["finite"] else 1
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,6 +324,8 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "adjoint":
+        return bench_adjoint(args)
 
     import numpy as np
     import torch

@@ -204,8 +204,9 @@ int lskum_set_far_field(lskum_plan plan, double *U, void *stream);
 
 /* Bytes of device workspace lskum_flux_residual_vjp needs:
  * (49 + 8 n_inner) doubles per point for q, every derivative iterate, the
- * bounds and the cotangents, plus 32 bytes per (point, row slot) for the
- * edge cotangents. */
+ * bounds and the cotangents, plus 32 bytes per point and in-edge slot for
+ * the edge cotangents (in-edge slots: the largest number of rows that list
+ * one point). */
 size_t lskum_vjp_workspace_bytes(lskum_plan plan);
 
 /* Ubar = (dR/dU)^T Rbar at interior and wall rows, 0 at outer rows;
@@ -226,6 +227,26 @@ int lskum_flux_residual_vjp(lskum_plan plan, const double *U, const double *Rbar
  * d(Jbar . C)/d(M, alpha) at fixed U (device). */
 int lskum_force_coeffs_vjp(lskum_plan plan, const double *U, const double *Jbar, double *Ubar,
                            double *thetabar, void *stream);
+
+/* Steady adjoint.  At a steady state U of the projected system (outer rows
+ * Dirichlet, wall rows with zero normal momentum), the total derivative of
+ * an output J(U, theta) is dJ/dtheta = dJ/dtheta|_U - thetabar(Lambda),
+ * where thetabar(Lambda) is the theta cotangent of lskum_flux_residual_vjp
+ * with Rbar = Lambda and Lambda solves Pi (dR/dU)^T Lambda = Pi g,
+ * g = (dJ/dU)^T, Pi clearing outer rows and the normal momentum of wall
+ * rows.  lskum_adjoint_iterate runs `iters` pseudo-time steps
+ *   Lambda <- Pi (Lambda - dt/2 ((dR/dU)^T Lambda - g)),
+ * dt the local time step of U (lskum_local_dt); the iteration matrix is
+ * similar to the transpose of the linearised forward iteration's, so it
+ * converges where the forward does.  Lambda (device [n][4]) is read as the
+ * initial iterate and overwritten; hist[k*n_clouds + c] (device, may be
+ * NULL) receives the L2 norm over cloud c of Pi((dR/dU)^T Lambda - g)
+ * before step k.  g: device [n][4].  ws: device,
+ * lskum_adjoint_workspace_bytes(plan) bytes, 256-byte aligned.  q and the
+ * derivative iterates of U are computed once per call. */
+size_t lskum_adjoint_workspace_bytes(lskum_plan plan);
+int lskum_adjoint_iterate(lskum_plan plan, const double *U, const double *g, double *Lambda,
+                          int32_t iters, double *hist, void *ws, void *stream);
 
 /* Synchronises `stream`, then returns LSKUM_ERR_NONPHYSICAL or
  * LSKUM_ERR_DEGENERATE if a kernel has recorded one since the last clear,

@@ -51,9 +51,39 @@ class Adjoint:
             self.plan.set_params(new)
 
     def workspace(self) -> torch.Tensor:
+        """Device workspace of the VJP and of the steady adjoint iteration."""
         if self._ws is None:
-            self._ws = L.vjp_workspace(self.plan)
+            self._ws = L.adjoint_workspace(self.plan)
         return self._ws
+
+    def steady_gradient(self, U: torch.Tensor, Jbar, iters: int, Lam: torch.Tensor | None = None):
+        """Total derivative of J = sum_c Jbar_c . (Cl, Cd)_c with respect to
+        theta = (M, alpha [rad]) of each cloud, at a steady state U.
+
+        The adjoint Lambda of the projected residual is found by `iters`
+        pseudo-time steps of lskum_adjoint_iterate (from Lam, or zero); then
+        dJ/dtheta = dJ/dtheta|_U - thetabar(Lambda).  Returns a dict with
+        the total and partial derivatives ((n_clouds, 2) each), Lambda and
+        the adjoint residual history ((iters, n_clouds))."""
+        p, s = self.plan, self.stream
+        dev = U.device
+        Jb = torch.as_tensor(Jbar, dtype=torch.float64).reshape(p.n_clouds, 2).to(dev).contiguous()
+        g = p.field(4)
+        partial = torch.empty(2 * p.n_clouds, dtype=torch.float64, device=dev)
+        L.lskum_force_coeffs_vjp(p, U, Jb.view(-1), g, partial, s)
+        lam = p.field(4)
+        if Lam is None:
+            lam.zero_()
+        else:
+            lam.copy_(Lam)
+        hist = torch.empty((max(int(iters), 1), p.n_clouds), dtype=torch.float64, device=dev)
+        ws = self.workspace()
+        L.lskum_adjoint_iterate(p, U, g, lam, iters, hist, ws, s)
+        Ub = p.field(4)
+        tr = torch.empty(2 * p.n_clouds, dtype=torch.float64, device=dev)
+        L.lskum_flux_residual_vjp(p, U, lam, Ub, tr, ws, s)
+        return {"total": (partial - tr).view(p.n_clouds, 2), "partial": partial.view(p.n_clouds, 2),
+                "Lambda": lam, "history": hist[:iters]}
 
     def residual(self, U: torch.Tensor, theta: torch.Tensor) -> torch.Tensor:
         return _ResidualFn.apply(U, theta, self)

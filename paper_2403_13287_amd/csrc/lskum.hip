@@ -666,7 +666,7 @@ void release(lskum_plan_s *p) {
   void *bufs[] = {p->xy,     p->nrm,  p->kind,   p->nbr,         p->cnt,     p->cloud,
                   p->wall,   p->woff, p->uinf,   p->mach,        p->aoa,     p->chunks,
                   p->chunk_first, p->partial, p->norm_scratch, p->counter, p->status,
-                  p->in_ptr, p->in_ent, p->lsg, p->outer, p->ooff};
+                  p->in_cnt, p->in_ent, p->tpos, p->lsg, p->outer, p->ooff};
   for (void *b : bufs) (void)hipFree(b);
   (void)hipSetDevice(cur);
   delete p;
@@ -859,6 +859,18 @@ int lskum_batch_plan_create(lskum_plan *out, int32_t n_clouds, const lskum_cloud
     for (int32_t s = 0; s < kp; ++s) nbr[(size_t)s * n + i] = rows[(size_t)i * kp + s];
   rows.clear();
   rows.shrink_to_fit();
+  // largest in-degree (the width of the adjoint's transposed connectivity)
+  int32_t k_in = 1;
+  try {
+    std::vector<int32_t> indeg((size_t)n, 0);
+    for (int32_t i = 0; i < n; ++i)
+      for (int32_t s = 0; s < cnt[(size_t)i]; ++s) {
+        const int32_t d = ++indeg[(size_t)nbr[(size_t)s * n + i]];
+        if (d > k_in) k_in = d;
+      }
+  } catch (const std::bad_alloc &) {
+    return LSKUM_ERR_NO_MEMORY;
+  }
   // residual-norm chunks, per cloud
   std::vector<int2> chunks;
   std::vector<int32_t> chunk_first(1, 0);
@@ -878,6 +890,7 @@ int lskum_batch_plan_create(lskum_plan *out, int32_t n_clouds, const lskum_cloud
   p->n_clouds = n_clouds;
   p->n_wall = (int32_t)wall.size();
   p->n_chunks = (int32_t)chunks.size();
+  p->k_in = k_in;
   p->params.assign(params, params + n_clouds);
   p->offset = offset;
   if (tuning) {

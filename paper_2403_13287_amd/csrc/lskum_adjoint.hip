@@ -13,14 +13,22 @@
 // deterministic.  Where the forward gathers from neighbours (point i reads
 // point j's data), the reverse has to send cotangents from i to j; that
 // transposed direction is also a gather, over the in-edges of j (the rows
-// that list j), kept as a CSR built once per plan.  The flux reverse stores
-// the cotangent of each edge's neighbour-end modified q in an edge-slot array
-// [slot][point] (32 B per edge) that the transposed gather then reads.
+// that list j), kept as a padded column-major table built once per plan.
+// The flux reverse stores the cotangent of each edge's neighbour-end
+// modified q (32 B per edge) straight at that edge's place in the in-edge
+// table of its target, so the transposed gather reads it coalesced; the
+// scattered side is the store, which does not stall the storing thread.
 //
 // Adjoint data of a plan (device, built by the first VJP call):
-//   in_ptr int32 [n+1]   in-edges of point j: in_ent[in_ptr[j] .. in_ptr[j+1])
-//   in_ent int32 [n_in]  (slot << 25) | i for each row i listing j at `slot`,
-//                        sorted by i then slot
+//   in_cnt int32 [n]       in-degree of each point
+//   in_ent int32 [k_in][n] column-major: entry e of point j is
+//                          (slot << 25) | i for the e-th row i listing j (at
+//                          `slot`), sorted by i then slot; k_in = largest
+//                          in-degree
+//   tpos   int32 [k_pad][n] e*n + j for row slot (k, i) listing j as its
+//                          e-th in-edge: where the flux reverse writes that
+//                          edge's cotangent, so the transposed gather reads
+//                          its in-edges' cotangents coalesced
 //   lsg    F8    [n]     least-squares geometry: M^-1 = [[a, b], [b, c]] of
 //                        the point's normal matrix, and sum of its edge
 //                        vectors (sdx, sdy)
@@ -135,19 +143,28 @@ __device__ __forceinline__ void end_state_rev(const Flow &P, double tx, double t
 // ---------------------------------------------------------------------------
 // flux residual, reverse: one thread per point, as the forward
 
-// Writes, for point i with residual cotangent Rb_i:
-//   T[k][i]    cotangent of the neighbour-end modified q of edge slot k;
-//   qbar_i, gbar_i, lbar_i   the own-end part of the cotangents of q, of the
-//              derivatives the flux uses and of the stencil bounds.
-template <int BLK>
-__global__ void __launch_bounds__(BLK) k_flux_rev(Geo G, Flow P, const double *__restrict__ q,
-                                                     const double *__restrict__ dq,
-                                                     const double *__restrict__ qlim,
-                                                     const double *__restrict__ Rb,
-                                                     double *__restrict__ T,
-                                                     double *__restrict__ qbar,
-                                                     double *__restrict__ gbar,
-                                                     double *__restrict__ lbar, unsigned *status) {
+// The residual of point i holds wt (G(q~_j) - G(q~_0)) per split and edge,
+// so the two ends of an edge take opposite cotangents and reverse
+// independently.  Two kernels share this body:
+//   NBR: the neighbour end of every edge, T[k][i] = cotangent of q~_j of
+//        edge slot k (read back by the transposed gather);
+//   OWN: the own end of every edge, accumulated into qbar_i, gbar_i and
+//        lbar_i (cotangents of q, of the derivatives the flux reads and of
+//        the stencil bounds).
+// Splitting the ends halves the state a thread carries through its edge
+// loop.
+template <int BLK, bool OWN>
+__device__ __forceinline__ void flux_rev_body(const Geo &G, const Flow &P,
+                                              const double *__restrict__ q,
+                                              const double *__restrict__ dq,
+                                              const double *__restrict__ qlim,
+                                              const double *__restrict__ Rb,
+                                              const int32_t *__restrict__ tpos,
+                                              double *__restrict__ T, double *__restrict__ qbar,
+                                              double *__restrict__ gbar,
+                                              double *__restrict__ lbar, unsigned *status) {
+  // the tile's records (NBR: neighbour gathers; OWN: the thread's own
+  // record, re-read from LDS at every edge instead of held in registers)
   __shared__ double2 s_xy[BLK];
   __shared__ F4 s_q[BLK];
   __shared__ F8 s_g[BLK];
@@ -156,30 +173,34 @@ __global__ void __launch_bounds__(BLK) k_flux_rev(Geo G, Flow P, const double *_
   const int lo = tile_lo<BLK>(G.xcd);
   const int i = lo + threadIdx.x;
   const bool active = i < n;
-  double2 xi = make_double2(0.0, 0.0);
-  F4 q0{{0.0, 0.0, 0.0, 0.0}};
-  F8 g0{{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}}, l0 = g0;
-  if (active) {
-    xi = G.xy[i];
-    q0 = ld4(q, i);
-    g0 = ld8(dq, i);
-    l0 = ld8(qlim, i);
+  s_xy[threadIdx.x] = active ? G.xy[i] : make_double2(0.0, 0.0);
+  {
+    F4 q0{{0.0, 0.0, 0.0, 0.0}};
+    F8 g0{{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}}, l0 = g0;
+    if (active) {
+      q0 = ld4(q, i);
+      g0 = ld8(dq, i);
+      l0 = ld8(qlim, i);
+    }
+    s_q[threadIdx.x] = q0;
+    s_g[threadIdx.x] = g0;
+    s_l[threadIdx.x] = l0;
   }
-  s_xy[threadIdx.x] = xi;
-  s_q[threadIdx.x] = q0;
-  s_g[threadIdx.x] = g0;
-  s_l[threadIdx.x] = l0;
   __syncthreads();
   if (!active) return;
+  const double2 xi = s_xy[threadIdx.x];
   const int kind = G.kind[i];
   const int c = G.cnt[i];
   if (kind == 2) {  // Dirichlet: R = 0 does not depend on anything
     const F4 z4{{0.0, 0.0, 0.0, 0.0}};
     const F8 z8{{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}};
-    for (int k = 0; k < c; ++k) st4_at(T, (size_t)k * n + i, z4);
-    st4(qbar, i, z4);
-    st8(gbar, i, z8);
-    st8(lbar, i, z8);
+    if (OWN) {
+      st4(qbar, i, z4);
+      st8(gbar, i, z8);
+      st8(lbar, i, z8);
+    } else {
+      for (int k = 0; k < c; ++k) st4_at(T, (size_t)(uint32_t)tpos[(size_t)k * n + i], z4);
+    }
     return;
   }
   const bool interior = kind == 0;
@@ -224,17 +245,15 @@ __global__ void __launch_bounds__(BLK) k_flux_rev(Geo G, Flow P, const double *_
     }
     W[h] = split_weights(h < 2, cnt[h], sss[h], ssn[h], snn[h], f);
   }
-
-  // seed: R = rotation of acc (mass, s-momentum, n-momentum, energy)
+  // seed: R = rotation of (mass, s-momentum, n-momentum, energy); the own
+  // end takes the opposite sign
   const F4 rb = ld4(Rb, i);
-  const double ab[4] = {rb.v[0], rb.v[1] * tx + rb.v[2] * ty, rb.v[1] * nx + rb.v[2] * ny,
-                        rb.v[3]};
-  double mx0[4], mn0[4];
-  for (int m = 0; m < 4; ++m) {
-    mx0[m] = l0.v[m] - q0.v[m];
-    mn0[m] = l0.v[4 + m] - q0.v[m];
-  }
+  const double sgn_end = OWN ? -1.0 : 1.0;
+  const double ab[4] = {sgn_end * rb.v[0], sgn_end * (rb.v[1] * tx + rb.v[2] * ty),
+                        sgn_end * (rb.v[1] * nx + rb.v[2] * ny), sgn_end * rb.v[3]};
   const double K = P.venkat_k;
+
+  // own-end accumulators (OWN only)
   double qb0[4] = {0, 0, 0, 0};
   double gb0[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   double lb0[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -245,89 +264,116 @@ __global__ void __launch_bounds__(BLK) k_flux_rev(Geo G, Flow P, const double *_
   for (int k = 0; k < c; ++k) {
     const int j_after = row(k + 2);
     const double2 xn = fetch_xy(j_next);
-    int lj;
-    F4 qj;
-    F8 gj, lj8;
-    if (in_tile<BLK>(j_cur, lo, lj)) {
-      qj = s_q[lj];
-      gj = s_g[lj];
-      lj8 = s_l[lj];
-    } else {
-      qj = ld4(q, j_cur);
-      gj = ld8(dq, j_cur);
-      lj8 = ld8(qlim, j_cur);
-    }
     const double dx = xj.x - xi.x, dy = xj.y - xi.y;
     const double ds = dot_rn(dx, tx, dy, ty);
     const double dn = dot_rn(dx, nx, dy, ny);
     const double eps2 = edge_eps2(K, dx, dy);
-    double qtj[4], qt0[4], d0[4];
-    for (int m = 0; m < 4; ++m) {
-      const double dj = half_step(dx, dy, gj.v[m], gj.v[4 + m]);
-      qtj[m] = qj.v[m] + limited(dj, lj8.v[m] - qj.v[m], lj8.v[4 + m] - qj.v[m], eps2);
-      d0[m] = half_step(dx, dy, g0.v[m], g0.v[4 + m]);
-      qt0[m] = q0.v[m] + limited(d0[m], mx0[m], mn0[m], eps2);
-    }
-    EndState sj, s0;
-    EndExtra xj_, x0_;
-    f |= end_state_t<true>(qtj, P, tx, ty, nx, ny, sj, &xj_);
-    f |= end_state_t<true>(qt0, P, tx, ty, nx, ny, s0, &x0_);
-    EndBar bj{0, 0, 0, 0, 0, 0, 0}, b0{0, 0, 0, 0, 0, 0, 0};
+    // split weights of this edge: s-split (ds < 0: G_s^+, ds > 0: G_s^-),
+    // n-split (dn < 0: G_n^+ at interior points, dn > 0: G_n^-)
+    const bool s_pos = ds < 0.0, n_pos = dn < 0.0;
+    const SplitW ws_ = s_pos ? W[0] : W[1];
+    const SplitW wn_ = n_pos ? W[2] : W[3];
+    const double wt_s = ds != 0.0 ? ws_.a * ds + ws_.b * dn : 0.0;
+    const double wt_n = (dn > 0.0 || (n_pos && interior)) ? wn_.a * ds + wn_.b * dn : 0.0;
+    const double sg_s = s_pos ? 1.0 : -1.0, sg_n = n_pos ? 1.0 : -1.0;
+    // (mass, d-momentum, o-momentum, energy) order of each split
+    const double Gs[4] = {wt_s * ab[0], wt_s * ab[1], wt_s * ab[2], wt_s * ab[3]};
+    const double Gn[4] = {wt_n * ab[0], wt_n * ab[2], wt_n * ab[1], wt_n * ab[3]};
 
-    // s-direction split (ds < 0: G_s^+, ds > 0: G_s^-)
-    {
-      const bool pos = ds < 0.0;
-      const SplitW w = pos ? W[0] : W[1];
-      const double wt = ds != 0.0 ? w.a * ds + w.b * dn : 0.0;
-      if (wt != 0.0) {
-        const double sg = pos ? 1.0 : -1.0;
-        const double Gb[4] = {wt * ab[0], wt * ab[1], wt * ab[2], wt * ab[3]};
-        const double Gn[4] = {-Gb[0], -Gb[1], -Gb[2], -Gb[3]};
-        split_flux_rev(sg, sj, sj.us, sj.un, Gb, bj, bj.us, bj.un);
-        split_flux_rev(sg, s0, s0.us, s0.un, Gn, b0, b0.us, b0.un);
+    // this end's limited modified q
+    double qt[4], d[4], rmax[4], rmin[4];
+    if (OWN) {
+      // keeps the compiler from hoisting the own-record reads out of the loop
+      asm volatile("" ::: "memory");
+      const F4 q0 = s_q[threadIdx.x];
+      const F8 g0 = s_g[threadIdx.x], l0 = s_l[threadIdx.x];
+      for (int m = 0; m < 4; ++m) {
+        d[m] = half_step(dx, dy, g0.v[m], g0.v[4 + m]);
+        rmax[m] = l0.v[m] - q0.v[m];
+        rmin[m] = l0.v[4 + m] - q0.v[m];
+        qt[m] = q0.v[m] + limited(d[m], rmax[m], rmin[m], eps2);
+      }
+    } else {
+      int lj;
+      F4 qj;
+      F8 gj, lj8;
+      if (in_tile<BLK>(j_cur, lo, lj)) {
+        qj = s_q[lj];
+        gj = s_g[lj];
+        lj8 = s_l[lj];
+      } else {
+        qj = ld4(q, j_cur);
+        gj = ld8(dq, j_cur);
+        lj8 = ld8(qlim, j_cur);
+      }
+      for (int m = 0; m < 4; ++m) {
+        d[m] = half_step(dx, dy, gj.v[m], gj.v[4 + m]);
+        qt[m] = qj.v[m] + limited(d[m], lj8.v[m] - qj.v[m], lj8.v[4 + m] - qj.v[m], eps2);
       }
     }
-    // n-direction split (dn < 0: G_n^+ at interior points, dn > 0: G_n^-)
-    {
-      const bool pos = dn < 0.0;
-      const SplitW w = pos ? W[2] : W[3];
-      const bool used = dn > 0.0 || (pos && interior);
-      const double wt = used ? w.a * ds + w.b * dn : 0.0;
-      if (wt != 0.0) {
-        const double sg = pos ? 1.0 : -1.0;
-        const double Gb[4] = {wt * ab[0], wt * ab[2], wt * ab[1], wt * ab[3]};
-        const double Gn[4] = {-Gb[0], -Gb[1], -Gb[2], -Gb[3]};
-        split_flux_rev(sg, sj, sj.un, sj.us, Gb, bj, bj.un, bj.us);
-        split_flux_rev(sg, s0, s0.un, s0.us, Gn, b0, b0.un, b0.us);
+    EndState st;
+    EndExtra ex;
+    f |= end_state_t<true>(qt, P, tx, ty, nx, ny, st, &ex);
+    EndBar b{0, 0, 0, 0, 0, 0, 0};
+    if (wt_s != 0.0) split_flux_rev(sg_s, st, st.us, st.un, Gs, b, b.us, b.un);
+    if (wt_n != 0.0) split_flux_rev(sg_n, st, st.un, st.us, Gn, b, b.un, b.us);
+    double qtb[4];
+    end_state_rev(P, tx, ty, nx, ny, st, ex, b, qtb);
+    if (OWN) {
+      // q~_0 = q_0 + phi delta_0, delta_0 = -(d . grad q_0)/2
+      for (int m = 0; m < 4; ++m) {
+        const LimRev r = limited_rev(d[m], rmax[m], rmin[m], eps2, qtb[m]);
+        qb0[m] += qtb[m];
+        gb0[m] += -0.5 * dx * r.ddelta;
+        gb0[4 + m] += -0.5 * dy * r.ddelta;
+        if (r.sel > 0) {
+          lb0[m] += r.droom;
+          qb0[m] -= r.droom;
+        } else if (r.sel < 0) {
+          lb0[4 + m] += r.droom;
+          qb0[m] -= r.droom;
+        }
       }
-    }
-    F4 tj;
-    double qtb0[4];
-    end_state_rev(P, tx, ty, nx, ny, sj, xj_, bj, tj.v);
-    end_state_rev(P, tx, ty, nx, ny, s0, x0_, b0, qtb0);
-    st4_at(T, (size_t)k * n + i, tj);
-    // own end: q~_0 = q_0 + phi delta_0, delta_0 = -(d . grad q_0)/2
-    for (int m = 0; m < 4; ++m) {
-      const LimRev r = limited_rev(d0[m], mx0[m], mn0[m], eps2, qtb0[m]);
-      qb0[m] += qtb0[m];
-      gb0[m] += -0.5 * dx * r.ddelta;
-      gb0[4 + m] += -0.5 * dy * r.ddelta;
-      if (r.sel > 0) {
-        lb0[m] += r.droom;
-        qb0[m] -= r.droom;
-      } else if (r.sel < 0) {
-        lb0[4 + m] += r.droom;
-        qb0[m] -= r.droom;
-      }
+    } else {
+      st4_at(T, (size_t)(uint32_t)tpos[(size_t)k * n + i], F4{{qtb[0], qtb[1], qtb[2], qtb[3]}});
     }
     xj = xn;
     j_cur = j_next;
     j_next = j_after;
   }
-  st4(qbar, i, F4{{qb0[0], qb0[1], qb0[2], qb0[3]}});
-  st8(gbar, i, F8{{gb0[0], gb0[1], gb0[2], gb0[3], gb0[4], gb0[5], gb0[6], gb0[7]}});
-  st8(lbar, i, F8{{lb0[0], lb0[1], lb0[2], lb0[3], lb0[4], lb0[5], lb0[6], lb0[7]}});
-  flag(status, f);
+  if (OWN) {
+    st4(qbar, i, F4{{qb0[0], qb0[1], qb0[2], qb0[3]}});
+    st8(gbar, i, F8{{gb0[0], gb0[1], gb0[2], gb0[3], gb0[4], gb0[5], gb0[6], gb0[7]}});
+    st8(lbar, i, F8{{lb0[0], lb0[1], lb0[2], lb0[3], lb0[4], lb0[5], lb0[6], lb0[7]}});
+  } else {
+    flag(status, f);
+  }
+}
+
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_flux_rev_nbr(Geo G, Flow P,
+                                                         const double *__restrict__ q,
+                                                         const double *__restrict__ dq,
+                                                         const double *__restrict__ qlim,
+                                                         const double *__restrict__ Rb,
+                                                         const int32_t *__restrict__ tpos,
+                                                         double *__restrict__ T,
+                                                         unsigned *status) {
+  flux_rev_body<BLK, false>(G, P, q, dq, qlim, Rb, tpos, T, nullptr, nullptr, nullptr, status);
+}
+
+// two waves per SIMD: the register budget is 256 per lane
+template <int BLK>
+__global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(2)))
+k_flux_rev_own(Geo G, Flow P,
+                                                         const double *__restrict__ q,
+                                                         const double *__restrict__ dq,
+                                                         const double *__restrict__ qlim,
+                                                         const double *__restrict__ Rb,
+                                                         double *__restrict__ qbar,
+                                                         double *__restrict__ gbar,
+                                                         double *__restrict__ lbar) {
+  flux_rev_body<BLK, true>(G, P, q, dq, qlim, Rb, nullptr, nullptr, qbar, gbar, lbar, nullptr);
 }
 
 // s = M^-1 g per component: (s_x, s_y) = [[a, b], [b, c]] (g_x, g_y)
@@ -338,13 +384,27 @@ __device__ __forceinline__ void apply_minv(const F8 &L, const double g[8], doubl
   }
 }
 
+// Reader of point j's in-edge row (column-major).  Entries at or past the
+// in-degree c read the last real entry, and a point with no in-edge reads
+// (slot 0, j), so prefetching ahead never leaves the table.
+struct InRow {
+  const int32_t *ent;  // &in_ent[j], stride n
+  int n, c, j;
+  __device__ __forceinline__ int operator()(int e) const {
+    if (c == 0) return j;
+    const int ee = e < c ? e : c - 1;
+    return ent[(size_t)ee * n];
+  }
+};
+
 // Transposed gather of the flux reverse at point j: the neighbour-end limiter
-// reverse of every edge that reads j (T of that edge), added to the own-end
-// parts.  In place: qbar_j and lbar_j complete; sbar_j (holding the own-end
-// gbar_j on entry) becomes M_j^-1 gbar_j, the seed of the derivative reverse.
+// reverse of every edge that reads j (its cotangent T in j's in-edge row),
+// added to the own-end parts.  In place: qbar_j and lbar_j complete; sbar_j
+// (holding the own-end gbar_j on entry) becomes M_j^-1 gbar_j, the seed of
+// the derivative reverse.
 template <int BLK>
 __global__ void __launch_bounds__(BLK) k_flux_gather(Geo G, Flow P,
-                                                        const int32_t *__restrict__ in_ptr,
+                                                        const int32_t *__restrict__ in_cnt,
                                                         const int32_t *__restrict__ in_ent,
                                                         const double *__restrict__ lsg,
                                                         const double *__restrict__ q,
@@ -379,14 +439,20 @@ __global__ void __launch_bounds__(BLK) k_flux_gather(Geo G, Flow P,
     rmin[m] = lj.v[4 + m] - qj.v[m];
   }
   const double K = P.venkat_k;
-  const int e1 = in_ptr[j + 1];
-  for (int e = in_ptr[j]; e < e1; ++e) {
-    const int ent = in_ent[e];
-    const int i = ent & kPointMask;
-    const int slot = ent >> kSlotShift;
+  auto fetch_xy = [&](int i) {
     int li;
-    const double2 xi = in_tile<BLK>(i, lo, li) ? s_xy[li] : G.xy[i];
-    const F4 tb = ld4_at(T, (size_t)slot * n + i);
+    return in_tile<BLK>(i, lo, li) ? s_xy[li] : G.xy[i];
+  };
+  const int c = in_cnt[j];
+  const InRow row{in_ent + j, n, c, j};
+  const int clast = c > 0 ? c - 1 : 0;
+  int ent_next = row(1);
+  double2 xi = fetch_xy(row(0) & kPointMask);
+  F4 tb = ld4_at(T, (size_t)j);
+  for (int e = 0; e < c; ++e) {
+    const int ent_after = row(e + 2);
+    const double2 xi_n = fetch_xy(ent_next & kPointMask);
+    const F4 tb_n = ld4_at(T, (size_t)(e + 1 < c ? e + 1 : clast) * n + j);
     // the edge as row i sees it: d = x_j - x_i
     const double dx = xj.x - xi.x, dy = xj.y - xi.y;
     const double eps2 = edge_eps2(K, dx, dy);
@@ -404,11 +470,14 @@ __global__ void __launch_bounds__(BLK) k_flux_gather(Geo G, Flow P,
         qb[m] -= r.droom;
       }
     }
+    xi = xi_n;
+    tb = tb_n;
+    ent_next = ent_after;
   }
-  double s[8];
-  apply_minv(ld8(lsg, j), gb, s);
+  double sv[8];
+  apply_minv(ld8(lsg, j), gb, sv);
   st4(qbar, j, F4{{qb[0], qb[1], qb[2], qb[3]}});
-  st8(sbar, j, F8{{s[0], s[1], s[2], s[3], s[4], s[5], s[6], s[7]}});
+  st8(sbar, j, F8{{sv[0], sv[1], sv[2], sv[3], sv[4], sv[5], sv[6], sv[7]}});
   st8(lbar, j, F8{{lb[0], lb[1], lb[2], lb[3], lb[4], lb[5], lb[6], lb[7]}});
 }
 
@@ -426,7 +495,7 @@ __global__ void __launch_bounds__(BLK) k_flux_gather(Geo G, Flow P,
 // so the next seed is s_prev_j = s_j/2 - M_j^-1 sum_i d_ij (d_ij . s_i) / 2.
 
 template <int BLK>
-__global__ void __launch_bounds__(BLK) k_inner_rev(Geo G, const int32_t *__restrict__ in_ptr,
+__global__ void __launch_bounds__(BLK) k_inner_rev(Geo G, const int32_t *__restrict__ in_cnt,
                                                       const int32_t *__restrict__ in_ent,
                                                       const double *__restrict__ lsg,
                                                       const double *__restrict__ s_in,
@@ -448,20 +517,28 @@ __global__ void __launch_bounds__(BLK) k_inner_rev(Geo G, const int32_t *__restr
   s_s[threadIdx.x] = sj;
   __syncthreads();
   if (!active) return;
-  double aq[4] = {0, 0, 0, 0}, ax[4] = {0, 0, 0, 0}, ay[4] = {0, 0, 0, 0};
-  const int e1 = in_ptr[j + 1];
-  for (int e = in_ptr[j]; e < e1; ++e) {
-    const int i = in_ent[e] & kPointMask;
+  auto fetch = [&](int i, double2 &x, F8 &sv) {
     int li;
-    double2 xi;
-    F8 si;
     if (in_tile<BLK>(i, lo, li)) {
-      xi = s_xy[li];
-      si = s_s[li];
+      x = s_xy[li];
+      sv = s_s[li];
     } else {
-      xi = G.xy[i];
-      si = ld8(s_in, i);
+      x = G.xy[i];
+      sv = ld8(s_in, i);
     }
+  };
+  double aq[4] = {0, 0, 0, 0}, ax[4] = {0, 0, 0, 0}, ay[4] = {0, 0, 0, 0};
+  const int c = in_cnt[j];
+  const InRow row{in_ent + j, n, c, j};
+  int ent_next = row(1);
+  double2 xi;
+  F8 si;
+  fetch(row(0) & kPointMask, xi, si);
+  for (int e = 0; e < c; ++e) {
+    const int ent_after = row(e + 2);
+    double2 xn;
+    F8 sn;
+    fetch(ent_next & kPointMask, xn, sn);
     const double dx = xj.x - xi.x, dy = xj.y - xi.y;
     for (int m = 0; m < 4; ++m) {
       const double t = dx * si.v[m] + dy * si.v[4 + m];
@@ -469,6 +546,9 @@ __global__ void __launch_bounds__(BLK) k_inner_rev(Geo G, const int32_t *__restr
       ax[m] += dx * t;
       ay[m] += dy * t;
     }
+    xi = xn;
+    si = sn;
+    ent_next = ent_after;
   }
   const F8 L = ld8(lsg, j);
   F4 qb = ld4(qbar, j);
@@ -486,7 +566,7 @@ __global__ void __launch_bounds__(BLK) k_inner_rev(Geo G, const int32_t *__restr
 // Stencil bounds route their cotangent to the slot that attained them.
 template <int BLK>
 __global__ void __launch_bounds__(BLK) k_first_rev(Geo G, Flow P,
-                                                      const int32_t *__restrict__ in_ptr,
+                                                      const int32_t *__restrict__ in_cnt,
                                                       const int32_t *__restrict__ in_ent,
                                                       const double *__restrict__ lsg,
                                                       const double *__restrict__ s0,
@@ -497,59 +577,78 @@ __global__ void __launch_bounds__(BLK) k_first_rev(Geo G, Flow P,
                                                       double *__restrict__ Ubar) {
   __shared__ double2 s_xy[BLK];
   __shared__ F8 s_s[BLK];
+  __shared__ uint64_t s_a[BLK];
+  const uint64_t *arg = reinterpret_cast<const uint64_t *>(argext);
   const int n = G.n;
   const int lo = tile_lo<BLK>(G.xcd);
   const int j = lo + threadIdx.x;
   const bool active = j < n;
   double2 xj = make_double2(0.0, 0.0);
   F8 sj{{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}};
+  uint64_t aj = 0;
   if (active) {
     xj = G.xy[j];
     sj = ld8(s0, j);
+    aj = arg[j];
   }
   s_xy[threadIdx.x] = xj;
   s_s[threadIdx.x] = sj;
+  s_a[threadIdx.x] = aj;
   __syncthreads();
   if (!active) return;
-  const uint64_t *arg = reinterpret_cast<const uint64_t *>(argext);
   double qb[4];
   {
     const F4 o = ld4(qbar, j);
     const F8 lo8 = ld8(lbar, j);
-    const uint64_t a = arg[j];
     for (int m = 0; m < 4; ++m) {
       qb[m] = o.v[m];
-      if ((int8_t)(a >> (8 * m)) == -1) qb[m] += lo8.v[m];
-      if ((int8_t)(a >> (8 * (4 + m))) == -1) qb[m] += lo8.v[4 + m];
+      if ((int8_t)(aj >> (8 * m)) == -1) qb[m] += lo8.v[m];
+      if ((int8_t)(aj >> (8 * (4 + m))) == -1) qb[m] += lo8.v[4 + m];
     }
   }
-  const int e1 = in_ptr[j + 1];
-  for (int e = in_ptr[j]; e < e1; ++e) {
-    const int ent = in_ent[e];
-    const int i = ent & kPointMask;
-    const int slot = ent >> kSlotShift;
+  auto fetch = [&](int i, double2 &x, F8 &sv, uint64_t &a) {
     int li;
-    double2 xi;
-    F8 si;
     if (in_tile<BLK>(i, lo, li)) {
-      xi = s_xy[li];
-      si = s_s[li];
+      x = s_xy[li];
+      sv = s_s[li];
+      a = s_a[li];
     } else {
-      xi = G.xy[i];
-      si = ld8(s0, i);
+      x = G.xy[i];
+      sv = ld8(s0, i);
+      a = arg[i];
     }
+  };
+  const int c = in_cnt[j];
+  const InRow row{in_ent + j, n, c, j};
+  int ent_next = row(1);
+  int ent = row(0);
+  double2 xi;
+  F8 si;
+  uint64_t ai;
+  fetch(ent & kPointMask, xi, si, ai);
+  for (int e = 0; e < c; ++e) {
+    const int ent_after = row(e + 2);
+    double2 xn;
+    F8 sn;
+    uint64_t an;
+    fetch(ent_next & kPointMask, xn, sn, an);
     const double dx = xj.x - xi.x, dy = xj.y - xi.y;
     for (int m = 0; m < 4; ++m) qb[m] += dx * si.v[m] + dy * si.v[4 + m];
-    const uint64_t a = arg[i];
+    const int slot = ent >> kSlotShift;
     bool hit = false;
-    for (int h = 0; h < 8; ++h) hit |= (int8_t)(a >> (8 * h)) == slot;
+    for (int h = 0; h < 8; ++h) hit |= (int8_t)(ai >> (8 * h)) == slot;
     if (hit) {
-      const F8 li8 = ld8(lbar, i);
+      const F8 li8 = ld8(lbar, ent & kPointMask);
       for (int m = 0; m < 4; ++m) {
-        if ((int8_t)(a >> (8 * m)) == slot) qb[m] += li8.v[m];
-        if ((int8_t)(a >> (8 * (4 + m))) == slot) qb[m] += li8.v[4 + m];
+        if ((int8_t)(ai >> (8 * m)) == slot) qb[m] += li8.v[m];
+        if ((int8_t)(ai >> (8 * (4 + m))) == slot) qb[m] += li8.v[4 + m];
       }
     }
+    xi = xn;
+    si = sn;
+    ai = an;
+    ent = ent_next;
+    ent_next = ent_after;
   }
   const F8 L = ld8(lsg, j);
   for (int m = 0; m < 4; ++m) qb[m] -= L.v[3] * sj.v[m] + L.v[4] * sj.v[4 + m];
@@ -562,7 +661,7 @@ __global__ void __launch_bounds__(BLK) k_first_rev(Geo G, Flow P,
   const double beta = 0.5 * rho / p;
   const double uu = u * u + v * v;
   const double betab = qb[0] * (a / beta - uu) + 2.0 * u * qb[1] + 2.0 * v * qb[2] - 2.0 * qb[3];
-  double rhob = qb[0] / rho + betab / (2.0 * p);
+  const double rhob = qb[0] / rho + betab / (2.0 * p);
   const double pb = -betab * beta / p;
   const double ub = -2.0 * beta * u * qb[0] + 2.0 * beta * qb[1];
   const double vb = -2.0 * beta * v * qb[0] + 2.0 * beta * qb[2];
@@ -602,6 +701,36 @@ __global__ void __launch_bounds__(kBlock) k_theta_rev(const int32_t *__restrict_
     thetabar[2 * c] = TM;
     thetabar[2 * c + 1] = TA;
   }
+}
+
+// One pseudo-time step of the steady adjoint at every point:
+// r = Pi(Ubar - g), Lambda <- Pi(Lambda - dt/2 r), where Pi clears outer
+// rows and the normal momentum of wall rows.  |r| is left in Ubar[i][0]
+// for the residual norm.
+__global__ void __launch_bounds__(kBlock) k_adjoint_step(Geo G, const double *__restrict__ dt,
+                                                         const double *__restrict__ g,
+                                                         double *__restrict__ Ub,
+                                                         double *__restrict__ Lam) {
+  const int i = point_index<kBlock>(G.xcd);
+  if (i >= G.n) return;
+  const int kind = G.kind[i];
+  const F4 b = ld4(Ub, i), gi = ld4(g, i);
+  F4 r, l = ld4(Lam, i);
+  for (int m = 0; m < 4; ++m) r.v[m] = kind == 2 ? 0.0 : b.v[m] - gi.v[m];
+  const double h = 0.5 * dt[i];
+  for (int m = 0; m < 4; ++m) l.v[m] = kind == 2 ? 0.0 : l.v[m] - h * r.v[m];
+  if (kind == 1) {
+    const double2 nv = G.nrm[i];
+    const double rn = r.v[1] * nv.x + r.v[2] * nv.y;
+    r.v[1] -= rn * nv.x;
+    r.v[2] -= rn * nv.y;
+    const double ln = l.v[1] * nv.x + l.v[2] * nv.y;
+    l.v[1] -= ln * nv.x;
+    l.v[2] -= ln * nv.y;
+  }
+  st4(Lam, i, l);
+  const double rr = r.v[0] * r.v[0] + r.v[1] * r.v[1] + r.v[2] * r.v[2] + r.v[3] * r.v[3];
+  st4(Ub, i, F4{{sqrt(rr), 0.0, 0.0, 0.0}});
 }
 
 // Least-squares geometry of every point (built once per plan).
@@ -733,7 +862,7 @@ VjpWs vjp_layout(const lskum_plan_s *p, void *ws) {
 size_t vjp_bytes(const lskum_plan_s *p) {
   const size_t f1 = f1_bytes(p);
   const size_t fields = 4 + 8 * (size_t)n_levels(p) + 8 + 4 + 8 + 8 + 8 + 1;
-  return fields * f1 + align256((size_t)p->k_pad * (size_t)p->n * 4 * sizeof(double));
+  return fields * f1 + align256((size_t)p->k_in * (size_t)p->n * 4 * sizeof(double));
 }
 
 template <class T>
@@ -748,32 +877,30 @@ int download(std::vector<T> &dst, const T *src, size_t count) {
 // Synchronous.
 int adjoint_prepare(lskum_plan_s *p, void *stream) {
   if (p->adj_ready) return LSKUM_OK;
-  if (p->n > kPointMask || p->k_pad > 64) return LSKUM_ERR_INVALID_ARG;
+  if (p->n > kPointMask || p->k_pad > 64 || p->k_in < 1 ||
+      (int64_t)p->k_in * p->n > (int64_t)INT32_MAX)
+    return LSKUM_ERR_INVALID_ARG;
   if (hipStreamSynchronize(S(stream)) != hipSuccess) return LSKUM_ERR_HIP;
-  const int32_t n = p->n, kp = p->k_pad;
+  const int32_t n = p->n, kp = p->k_pad, ki = p->k_in;
   std::vector<int32_t> nbr, cnt;
   std::vector<int8_t> kind;
-  std::vector<int32_t> in_ptr, in_ent, outer, ooff;
+  std::vector<int32_t> in_cnt, in_ent, tpos, outer, ooff;
   int rc = LSKUM_OK;
   try {
     if ((rc = download(nbr, p->nbr, (size_t)n * kp)) || (rc = download(cnt, p->cnt, (size_t)n)) ||
         (rc = download(kind, p->kind, (size_t)n)))
       return rc;
-    in_ptr.assign((size_t)n + 1, 0);
-    int64_t nnz = 0;
-    for (int32_t i = 0; i < n; ++i)
-      for (int32_t s = 0; s < cnt[(size_t)i]; ++s) {
-        ++in_ptr[(size_t)nbr[(size_t)s * n + i] + 1];
-        ++nnz;
-      }
-    if (nnz > INT32_MAX) return LSKUM_ERR_INVALID_ARG;
-    for (int32_t j = 0; j < n; ++j) in_ptr[(size_t)j + 1] += in_ptr[(size_t)j];
-    in_ent.resize((size_t)nnz);
-    std::vector<int32_t> fill(in_ptr.begin(), in_ptr.end() - 1);
-    for (int32_t i = 0; i < n; ++i)  // i ascending, then slot: entries sorted
+    in_cnt.assign((size_t)n, 0);
+    in_ent.resize((size_t)ki * n);
+    for (int32_t j = 0; j < n; ++j) in_ent[(size_t)j] = j;  // a point with no in-edge
+    tpos.assign((size_t)kp * n, 0);
+    for (int32_t i = 0; i < n; ++i)  // i ascending, then slot: rows sorted
       for (int32_t s = 0; s < cnt[(size_t)i]; ++s) {
         const int32_t j = nbr[(size_t)s * n + i];
-        in_ent[(size_t)fill[(size_t)j]++] = (s << kSlotShift) | i;
+        const int32_t e = in_cnt[(size_t)j]++;
+        if (e >= ki) return LSKUM_ERR_BAD_CLOUD;  // k_in is the largest in-degree
+        in_ent[(size_t)e * n + j] = (s << kSlotShift) | i;
+        tpos[(size_t)s * n + i] = e * n + j;
       }
     ooff.push_back(0);
     for (int32_t c = 0; c < p->n_clouds; ++c) {
@@ -781,12 +908,12 @@ int adjoint_prepare(lskum_plan_s *p, void *stream) {
         if (kind[(size_t)i] == 2) outer.push_back(i);
       ooff.push_back((int32_t)outer.size());
     }
-    p->n_in = nnz;
   } catch (const std::bad_alloc &) {
     return LSKUM_ERR_NO_MEMORY;
   }
-  if ((rc = upload(&p->in_ptr, in_ptr.data(), in_ptr.size())) ||
+  if ((rc = upload(&p->in_cnt, in_cnt.data(), in_cnt.size())) ||
       (rc = upload(&p->in_ent, in_ent.data(), in_ent.size())) ||
+      (rc = upload(&p->tpos, tpos.data(), tpos.size())) ||
       (rc = upload(&p->outer, outer.data(), outer.size())) ||
       (rc = upload(&p->ooff, ooff.data(), ooff.size())))
     return rc;
@@ -801,9 +928,9 @@ int adjoint_prepare(lskum_plan_s *p, void *stream) {
 
 // free whatever a failed preparation left
 void adjoint_reset(lskum_plan_s *p) {
-  void *bufs[] = {p->in_ptr, p->in_ent, p->lsg, p->outer, p->ooff};
+  void *bufs[] = {p->in_cnt, p->in_ent, p->tpos, p->lsg, p->outer, p->ooff};
   for (void *b : bufs) (void)hipFree(b);
-  p->in_ptr = p->in_ent = p->outer = p->ooff = nullptr;
+  p->in_cnt = p->in_ent = p->tpos = p->outer = p->ooff = nullptr;
   p->lsg = nullptr;
   p->adj_ready = false;
 }
@@ -817,6 +944,53 @@ void adjoint_reset(lskum_plan_s *p) {
       default: kern<256><<<g_, 256, 0, S(stream)>>>(__VA_ARGS__); break;                     \
     }                                                                                        \
   } while (0)
+
+int prepare_checked(lskum_plan_s *p, void *stream) {
+  const int rc = adjoint_prepare(p, stream);
+  if (rc) adjoint_reset(p);
+  return rc;
+}
+
+// q, the first-order derivatives with the slots attaining the bounds, and
+// every inner iterate of U, into the workspace.
+int forward_recompute(lskum_plan_s *p, const VjpWs &w, const double *U, void *stream) {
+  const int K = p->params[0].n_inner;
+  const size_t lev = 8 * f1_bytes(p) / sizeof(double);  // doubles between iterates
+  int rc;
+  if ((rc = q_vars_launch(p, U, w.q, stream))) return rc;
+  if ((rc = deriv_first_launch(p, w.q, w.dq0, w.qlim, w.argext, stream))) return rc;
+  for (int k = 1; k <= K; ++k)
+    if ((rc = deriv_inner_launch(p, w.q, w.dq0 + (k - 1) * lev, w.dq0 + k * lev, stream)))
+      return rc;
+  return LSKUM_OK;
+}
+
+// Reverse passes from the residual cotangent Rbar to Ubar (every row,
+// outer rows included): flux, its transposed gather, inner sweeps K..1,
+// first-order pass and q-variables.
+int reverse_passes(lskum_plan_s *p, const VjpWs &w, const double *U, const double *Rbar,
+                   double *Ubar, void *stream) {
+  const int K = p->params[0].n_inner;
+  const size_t lev = 8 * f1_bytes(p) / sizeof(double);
+  const double *dqK = w.dq0 + (size_t)K * lev;
+  const Geo g = geo(p);
+  const Flow f = flow(p);
+  LSKUM_TILED_ADJ(k_flux_rev_nbr, p, stream, g, f, w.q, dqK, w.qlim, Rbar, p->tpos, w.T,
+                  p->status);
+  LSKUM_TILED_ADJ(k_flux_rev_own, p, stream, g, f, w.q, dqK, w.qlim, Rbar, w.qbar, w.sa, w.lbar);
+  LSKUM_TILED_ADJ(k_flux_gather, p, stream, g, f, p->in_cnt, p->in_ent, p->lsg, w.q, dqK, w.qlim,
+                  w.T, w.qbar, w.sa, w.lbar);
+  double *cur = w.sa, *nxt = w.sb;
+  for (int k = K; k >= 1; --k) {
+    LSKUM_TILED_ADJ(k_inner_rev, p, stream, g, p->in_cnt, p->in_ent, p->lsg, cur, w.qbar, nxt);
+    double *t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  LSKUM_TILED_ADJ(k_first_rev, p, stream, g, f, p->in_cnt, p->in_ent, p->lsg, cur, w.argext,
+                  w.lbar, U, w.qbar, Ubar);
+  return launched();
+}
 
 }  // namespace
 }  // namespace lskum_impl
@@ -835,39 +1009,41 @@ int lskum_flux_residual_vjp(lskum_plan p, const double *U, const double *Rbar, d
   if (!p || !a32(U) || !a32(Rbar) || !a32(Ubar) || !thetabar || !ws ||
       ((uintptr_t)ws % 256) != 0)
     return LSKUM_ERR_INVALID_ARG;
-  int rc = adjoint_prepare(p, stream);
-  if (rc) {
-    adjoint_reset(p);
-    return rc;
-  }
+  int rc = prepare_checked(p, stream);
+  if (rc) return rc;
   const VjpWs w = vjp_layout(p, ws);
-  const int K = p->params[0].n_inner;
-  const size_t lev = 8 * f1_bytes(p) / sizeof(double);  // doubles between iterates
-  const Geo g = geo(p);
-  const Flow f = flow(p);
-  // forward recompute: q, first-order derivatives with bound slots, iterates
-  if ((rc = q_vars_launch(p, U, w.q, stream))) return rc;
-  if ((rc = deriv_first_launch(p, w.q, w.dq0, w.qlim, w.argext, stream))) return rc;
-  for (int k = 1; k <= K; ++k)
-    if ((rc = deriv_inner_launch(p, w.q, w.dq0 + (k - 1) * lev, w.dq0 + k * lev, stream)))
-      return rc;
-  const double *dqK = w.dq0 + (size_t)K * lev;
-  // reverse: flux, its transposed gather, inner sweeps K..1, first-order pass
-  LSKUM_TILED_ADJ(k_flux_rev, p, stream, g, f, w.q, dqK, w.qlim, Rbar, w.T, w.qbar, w.sa, w.lbar,
-                  p->status);
-  LSKUM_TILED_ADJ(k_flux_gather, p, stream, g, f, p->in_ptr, p->in_ent, p->lsg, w.q, dqK, w.qlim,
-                  w.T, w.qbar, w.sa, w.lbar);
-  double *cur = w.sa, *nxt = w.sb;
-  for (int k = K; k >= 1; --k) {
-    LSKUM_TILED_ADJ(k_inner_rev, p, stream, g, p->in_ptr, p->in_ent, p->lsg, cur, w.qbar, nxt);
-    double *t = cur;
-    cur = nxt;
-    nxt = t;
-  }
-  LSKUM_TILED_ADJ(k_first_rev, p, stream, g, f, p->in_ptr, p->in_ent, p->lsg, cur, w.argext,
-                  w.lbar, U, w.qbar, Ubar);
+  if ((rc = forward_recompute(p, w, U, stream))) return rc;
+  if ((rc = reverse_passes(p, w, U, Rbar, Ubar, stream))) return rc;
   k_theta_rev<<<p->n_clouds, kBlock, 0, S(stream)>>>(p->ooff, p->outer, p->mach, p->aoa, Ubar,
                                                      thetabar);
+  return launched();
+}
+
+size_t lskum_adjoint_workspace_bytes(lskum_plan p) {
+  if (!p) return 0;
+  return vjp_bytes(p) + 5 * f1_bytes(p);
+}
+
+int lskum_adjoint_iterate(lskum_plan p, const double *U, const double *g, double *Lambda,
+                          int32_t iters, double *hist, void *ws, void *stream) {
+  if (!p || !a32(U) || !a32(g) || !a32(Lambda) || iters < 0 || !ws ||
+      ((uintptr_t)ws % 256) != 0)
+    return LSKUM_ERR_INVALID_ARG;
+  int rc = prepare_checked(p, stream);
+  if (rc) return rc;
+  const VjpWs w = vjp_layout(p, ws);
+  char *extra = static_cast<char *>(ws) + vjp_bytes(p);
+  double *dt = reinterpret_cast<double *>(extra);
+  double *Ub = reinterpret_cast<double *>(extra + f1_bytes(p));
+  if ((rc = lskum_local_dt(p, U, dt, stream))) return rc;
+  if ((rc = forward_recompute(p, w, U, stream))) return rc;
+  const Geo geo_ = geo(p);
+  for (int32_t k = 0; k < iters; ++k) {
+    if ((rc = reverse_passes(p, w, U, Lambda, Ub, stream))) return rc;
+    k_adjoint_step<<<grid_for(p->n), kBlock, 0, S(stream)>>>(geo_, dt, g, Ub, Lambda);
+    if (hist && (rc = lskum_residual_norm(p, Ub, hist + (size_t)k * p->n_clouds, stream)))
+      return rc;
+  }
   return launched();
 }
 

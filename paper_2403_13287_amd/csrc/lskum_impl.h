@@ -305,9 +305,10 @@ struct lskum_plan_s {
   unsigned *status = nullptr;
   // adjoint data, built by the first VJP call on the plan
   bool adj_ready = false;
-  int64_t n_in = 0;               // real edges
-  int32_t *in_ptr = nullptr;      // [n+1] in-edges of each point (CSR)
-  int32_t *in_ent = nullptr;      // [n_in] (slot << kSlotShift) | source point
+  int32_t k_in = 0;               // padded in-edge row width (largest in-degree)
+  int32_t *in_cnt = nullptr;      // [n] in-edges of each point
+  int32_t *in_ent = nullptr;      // [k_in][n] (slot << kSlotShift) | source point
+  int32_t *tpos = nullptr;        // [k_pad][n] in-edge position e*n + j of row slot (k, i)
   double *lsg = nullptr;          // [n][8] least-squares geometry of each point
   int32_t *outer = nullptr;       // outer points, grouped by cloud
   int32_t *ooff = nullptr;        // [n_clouds+1] offsets into outer

@@ -84,6 +84,8 @@ _SIGS = {
     "lskum_vjp_workspace_bytes": (ctypes.c_size_t, "v"),
     "lskum_flux_residual_vjp": (ctypes.c_int, "vvvvvvv"),
     "lskum_force_coeffs_vjp": (ctypes.c_int, "vvvvvv"),
+    "lskum_adjoint_workspace_bytes": (ctypes.c_size_t, "v"),
+    "lskum_adjoint_iterate": (ctypes.c_int, "vvvvivvv"),
 }
 _CT = {"v": ctypes.c_void_p, "i": ctypes.c_int32, "d": ctypes.c_double}
 
@@ -362,6 +364,29 @@ def lskum_force_coeffs_vjp(plan: Plan, U, Jbar, Ubar, thetabar, stream=None):
                                            _scalar_out(plan, thetabar, 2 * plan.n_clouds,
                                                        "thetabar"),
                                            _stream(stream)), "lskum_force_coeffs_vjp")
+
+
+def lskum_adjoint_workspace_bytes(plan: Plan) -> int:
+    return int(plan.lib.lskum_adjoint_workspace_bytes(plan.handle))
+
+
+def adjoint_workspace(plan: Plan) -> torch.Tensor:
+    ws = torch.empty(lskum_adjoint_workspace_bytes(plan), dtype=torch.uint8,
+                     device=f"cuda:{plan.device}")
+    if ws.data_ptr() % 256:
+        raise RuntimeError("workspace not 256-byte aligned")
+    return ws
+
+
+def lskum_adjoint_iterate(plan: Plan, U, g, Lam, iters: int, hist, ws, stream=None):
+    """hist: iters x n_clouds adjoint residual norms (or None)."""
+    hp = 0 if hist is None else _scalar_out(plan, hist, int(iters) * plan.n_clouds, "hist")
+    if not isinstance(ws, torch.Tensor) or not ws.is_cuda or \
+            ws.numel() < lskum_adjoint_workspace_bytes(plan):
+        raise ValueError("ws: need a cuda tensor of lskum_adjoint_workspace_bytes(plan) bytes")
+    _check(plan.lib.lskum_adjoint_iterate(plan.handle, plan._arg(U, 4, "U"), plan._arg(g, 4, "g"),
+                                          plan._arg(Lam, 4, "Lambda"), int(iters), hp,
+                                          ws.data_ptr(), _stream(stream)), "lskum_adjoint_iterate")
 
 
 def lskum_status(plan: Plan, stream=None) -> int:

@@ -100,6 +100,10 @@ def test_validation_rejects_bad_clouds(cyl):
     rp[3] += 1  # row length differs from k_pad
     s, keep = _c_cloud(c, row_ptr=rp)
     assert _create(s)[0] == L.ERR_BAD_CLOUD
+    wl = c.wall_loop.copy()
+    wl[1] = wl[0]  # the wall loop visits a point twice
+    s, keep = _c_cloud(c, wall_loop=wl)
+    assert _create(s)[0] == L.ERR_BAD_CLOUD
 
 
 def test_validation_rejects_bad_params(cyl):
@@ -116,3 +120,9 @@ def test_null_arguments_are_rejected():
     assert lib.lskum_flux_residual(None, None, None, None, None, None) == L.ERR_INVALID_ARG
     assert lib.lskum_rk_stage(None, 0, None, None, None, None, None) == L.ERR_INVALID_ARG
     assert lib.lskum_workspace_bytes(None) == 0
+    assert lib.lskum_set_far_field(None, None, None) == L.ERR_INVALID_ARG
+    assert lib.lskum_flux_residual_vjp(None, None, None, None, None, None, None) == L.ERR_INVALID_ARG
+    assert lib.lskum_force_coeffs_vjp(None, None, None, None, None, None) == L.ERR_INVALID_ARG
+    assert lib.lskum_adjoint_iterate(None, None, None, None, 1, None, None, None) == L.ERR_INVALID_ARG
+    assert lib.lskum_vjp_workspace_bytes(None) == 0
+    assert lib.lskum_adjoint_workspace_bytes(None) == 0
