@@ -666,7 +666,7 @@ void release(lskum_plan_s *p) {
   void *bufs[] = {p->xy,     p->nrm,  p->kind,   p->nbr,         p->cnt,     p->cloud,
                   p->wall,   p->woff, p->uinf,   p->mach,        p->aoa,     p->chunks,
                   p->chunk_first, p->partial, p->norm_scratch, p->counter, p->status,
-                  p->in_cnt, p->in_ent, p->tpos, p->lsg, p->outer, p->ooff};
+                  p->in_cnt, p->in_ent, p->spw, p->lsg, p->outer, p->ooff};
   for (void *b : bufs) (void)hipFree(b);
   (void)hipSetDevice(cur);
   delete p;

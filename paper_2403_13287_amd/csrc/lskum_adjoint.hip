@@ -14,10 +14,6 @@
 // point j's data), the reverse has to send cotangents from i to j; that
 // transposed direction is also a gather, over the in-edges of j (the rows
 // that list j), kept as a padded column-major table built once per plan.
-// The flux reverse stores the cotangent of each edge's neighbour-end
-// modified q (32 B per edge) straight at that edge's place in the in-edge
-// table of its target, so the transposed gather reads it coalesced; the
-// scattered side is the store, which does not stall the storing thread.
 //
 // Adjoint data of a plan (device, built by the first VJP call):
 //   in_cnt int32 [n]       in-degree of each point
@@ -25,14 +21,12 @@
 //                          (slot << 25) | i for the e-th row i listing j (at
 //                          `slot`), sorted by i then slot; k_in = largest
 //                          in-degree
-//   tpos   int32 [k_pad][n] e*n + j for row slot (k, i) listing j as its
-//                          e-th in-edge: where the flux reverse writes that
-//                          edge's cotangent, so the transposed gather reads
-//                          its in-edges' cotangents coalesced
-//   lsg    F8    [n]     least-squares geometry: M^-1 = [[a, b], [b, c]] of
-//                        the point's normal matrix, and sum of its edge
-//                        vectors (sdx, sdy)
-//   outer, ooff          outer points of each cloud
+//   spw    F8    [n]       least-squares weights of the four half-plane
+//                          stencils (geometry only)
+//   lsg    F8    [n]       least-squares geometry: M^-1 = [[a, b], [b, c]] of
+//                          the point's normal matrix, and sum of its edge
+//                          vectors (sdx, sdy)
+//   outer, ooff            outer points of each cloud
 
 #include <hip/hip_runtime.h>
 
@@ -141,30 +135,157 @@ __device__ __forceinline__ void end_state_rev(const Flow &P, double tx, double t
 }
 
 // ---------------------------------------------------------------------------
-// flux residual, reverse: one thread per point, as the forward
+// flux residual, reverse
+//
+// Point i's residual holds, per edge (i, j) and split, wt (G(q~_j) - G(q~_i))
+// with wt a least-squares weight of i's half-plane stencil (geometry only).
+// The two ends of an edge therefore reverse independently, each from the
+// seed of row i rotated into i's frame:
+//   own end (q~_i): k_flux_rev_own, one thread per row i over its edges;
+//   neighbour end (q~_j): k_flux_gather, one thread per point j over the
+//     rows that list it, recomputing each edge from the source's weights,
+//     normal and seed, which are precomputed or cheap (k_split_weights).
+// Neither end's intermediate is stored: the reverse of an edge end is
+// recomputed where its cotangent is consumed.
 
-// The residual of point i holds wt (G(q~_j) - G(q~_0)) per split and edge,
-// so the two ends of an edge take opposite cotangents and reverse
-// independently.  Two kernels share this body:
-//   NBR: the neighbour end of every edge, T[k][i] = cotangent of q~_j of
-//        edge slot k (read back by the transposed gather);
-//   OWN: the own end of every edge, accumulated into qbar_i, gbar_i and
-//        lbar_i (cotangents of q, of the derivatives the flux reads and of
-//        the stencil bounds).
-// Splitting the ends halves the state a thread carries through its edge
-// loop.
-template <int BLK, bool OWN>
-__device__ __forceinline__ void flux_rev_body(const Geo &G, const Flow &P,
-                                              const double *__restrict__ q,
-                                              const double *__restrict__ dq,
-                                              const double *__restrict__ qlim,
-                                              const double *__restrict__ Rb,
-                                              const int32_t *__restrict__ tpos,
-                                              double *__restrict__ T, double *__restrict__ qbar,
-                                              double *__restrict__ gbar,
-                                              double *__restrict__ lbar, unsigned *status) {
-  // the tile's records (NBR: neighbour gathers; OWN: the thread's own
-  // record, re-read from LDS at every edge instead of held in registers)
+// Least-squares weights of the four half-plane stencils of every point
+// (geometry only, computed once per plan): spw[i] = (a, b) of s+, s-, n+,
+// n-; the weight of edge d in split h is a_h ds + b_h dn.
+__global__ void __launch_bounds__(kBlock) k_split_weights(Geo G, double *__restrict__ spw,
+                                                          unsigned *status) {
+  const int n = G.n;
+  const int i = point_index<kBlock>(G.xcd);
+  if (i >= n) return;
+  const int kind = G.kind[i];
+  if (kind == 2) {
+    st8(spw, i, F8{{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}});
+    return;
+  }
+  const bool interior = kind == 0;
+  const double2 xi = G.xy[i], nv = G.nrm[i];
+  const double nx = nv.x, ny = nv.y, tx = ny, ty = -nx;
+  const int c = G.cnt[i];
+  double sss[4] = {0, 0, 0, 0}, ssn[4] = {0, 0, 0, 0}, snn[4] = {0, 0, 0, 0};
+  int cnt[4] = {0, 0, 0, 0};
+  for (int k = 0; k < c; ++k) {
+    const double2 xj = G.xy[G.nbr[(size_t)k * n + i]];
+    const double dx = xj.x - xi.x, dy = xj.y - xi.y;
+    const double ds = dot_rn(dx, tx, dy, ty);
+    const double dn = dot_rn(dx, nx, dy, ny);
+    const bool in[4] = {ds < 0.0, ds > 0.0, interior && dn < 0.0, dn > 0.0};
+    for (int h = 0; h < 4; ++h) {
+      const double w = in[h] ? 1.0 : 0.0;
+      sss[h] += w * (ds * ds);
+      ssn[h] += w * (ds * dn);
+      snn[h] += w * (dn * dn);
+      cnt[h] += in[h] ? 1 : 0;
+    }
+  }
+  unsigned f = 0;
+  F8 out;
+  for (int h = 0; h < 4; ++h) {
+    SplitW w{0.0, 0.0};
+    if (!(h == 2 && !interior)) w = split_weights(h < 2, cnt[h], sss[h], ssn[h], snn[h], f);
+    out.v[2 * h] = w.a;
+    out.v[2 * h + 1] = w.b;
+  }
+  st8(spw, i, out);
+  flag(status, f);
+}
+
+// Weights and seeds of edge d = x_j - x_i of row i: split weights wt_s, wt_n
+// (zero for an unused split), signs, and the seeds of both splits in their
+// (mass, d-momentum, o-momentum, energy) order, times `sign` (+1 for the
+// neighbour end, -1 for the own end).
+struct EdgeSeed {
+  double ds, dn, sg_s, sg_n, wt_s, wt_n;
+  double Gs[4], Gn[4];
+};
+
+__device__ __forceinline__ EdgeSeed edge_seed(double dx, double dy, double tx, double ty, double nx,
+                                              double ny, bool interior, const F8 &W,
+                                              const double ab[4], double sign) {
+  EdgeSeed e;
+  e.ds = dot_rn(dx, tx, dy, ty);
+  e.dn = dot_rn(dx, nx, dy, ny);
+  const bool s_pos = e.ds < 0.0, n_pos = e.dn < 0.0;
+  const double sa = s_pos ? W.v[0] : W.v[2], sb = s_pos ? W.v[1] : W.v[3];
+  const double na = n_pos ? W.v[4] : W.v[6], nb = n_pos ? W.v[5] : W.v[7];
+  e.wt_s = e.ds != 0.0 ? sa * e.ds + sb * e.dn : 0.0;
+  e.wt_n = (e.dn > 0.0 || (n_pos && interior)) ? na * e.ds + nb * e.dn : 0.0;
+  e.sg_s = s_pos ? 1.0 : -1.0;
+  e.sg_n = n_pos ? 1.0 : -1.0;
+  const double ws = sign * e.wt_s, wn = sign * e.wt_n;
+  e.Gs[0] = ws * ab[0];
+  e.Gs[1] = ws * ab[1];
+  e.Gs[2] = ws * ab[2];
+  e.Gs[3] = ws * ab[3];
+  e.Gn[0] = wn * ab[0];
+  e.Gn[1] = wn * ab[2];
+  e.Gn[2] = wn * ab[1];
+  e.Gn[3] = wn * ab[3];
+  return e;
+}
+
+// Seed of row i in its own frame: R = rotation of (mass, s-momentum,
+// n-momentum, energy).
+__device__ __forceinline__ void frame_seed(const F4 &rb, double tx, double ty, double nx,
+                                           double ny, double ab[4]) {
+  ab[0] = rb.v[0];
+  ab[1] = rb.v[1] * tx + rb.v[2] * ty;
+  ab[2] = rb.v[1] * nx + rb.v[2] * ny;
+  ab[3] = rb.v[3];
+}
+
+// Reverse of one end of one edge: the end's record (qe, ge, le), the edge
+// vector d as row i sees it and row i's frame.  Adds the cotangents of the
+// end's q, dq and qlim records to qb, gb, lb.
+__device__ __forceinline__ unsigned end_reverse(const Flow &P, const F4 &qe, const F8 &ge,
+                                                const F8 &le, double dx, double dy, double eps2,
+                                                double tx, double ty, double nx, double ny,
+                                                const EdgeSeed &e, double qb[4], double gb[8],
+                                                double lb[8]) {
+  double qt[4], d[4], rmax[4], rmin[4];
+  for (int m = 0; m < 4; ++m) {
+    d[m] = half_step(dx, dy, ge.v[m], ge.v[4 + m]);
+    rmax[m] = le.v[m] - qe.v[m];
+    rmin[m] = le.v[4 + m] - qe.v[m];
+    qt[m] = qe.v[m] + limited(d[m], rmax[m], rmin[m], eps2);
+  }
+  EndState st;
+  EndExtra ex;
+  const unsigned f = end_state_t<true>(qt, P, tx, ty, nx, ny, st, &ex);
+  EndBar b{0, 0, 0, 0, 0, 0, 0};
+  if (e.wt_s != 0.0) split_flux_rev(e.sg_s, st, st.us, st.un, e.Gs, b, b.us, b.un);
+  if (e.wt_n != 0.0) split_flux_rev(e.sg_n, st, st.un, st.us, e.Gn, b, b.un, b.us);
+  double qtb[4];
+  end_state_rev(P, tx, ty, nx, ny, st, ex, b, qtb);
+  // q~ = q + phi delta, delta = -(d . grad q)/2
+  for (int m = 0; m < 4; ++m) {
+    const LimRev r = limited_rev(d[m], rmax[m], rmin[m], eps2, qtb[m]);
+    // the room is qlim - q: its cotangent goes to the bound used and, with
+    // the opposite sign, to q (selects, not an indexed update, so the
+    // accumulators stay in registers)
+    const double to_max = r.sel > 0 ? r.droom : 0.0;
+    const double to_min = r.sel < 0 ? r.droom : 0.0;
+    qb[m] += qtb[m] - (to_max + to_min);
+    gb[m] += -0.5 * dx * r.ddelta;
+    gb[4 + m] += -0.5 * dy * r.ddelta;
+    lb[m] += to_max;
+    lb[4 + m] += to_min;
+  }
+  return f;
+}
+
+// Own end of every edge of row i: writes the own-end parts of qbar_i, gbar_i
+// and lbar_i.  The thread's own record is re-read from LDS at every edge
+// rather than held in registers through the loop (two waves per SIMD).
+template <int BLK>
+__global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(2)))
+k_flux_rev_own(Geo G, Flow P, const double *__restrict__ spw, const double *__restrict__ q,
+               const double *__restrict__ dq, const double *__restrict__ qlim,
+               const double *__restrict__ Rb, double *__restrict__ qbar,
+               double *__restrict__ gbar, double *__restrict__ lbar, unsigned *status) {
   __shared__ double2 s_xy[BLK];
   __shared__ F4 s_q[BLK];
   __shared__ F8 s_g[BLK];
@@ -173,207 +294,63 @@ __device__ __forceinline__ void flux_rev_body(const Geo &G, const Flow &P,
   const int lo = tile_lo<BLK>(G.xcd);
   const int i = lo + threadIdx.x;
   const bool active = i < n;
-  s_xy[threadIdx.x] = active ? G.xy[i] : make_double2(0.0, 0.0);
   {
+    double2 xi = make_double2(0.0, 0.0);
     F4 q0{{0.0, 0.0, 0.0, 0.0}};
     F8 g0{{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}}, l0 = g0;
     if (active) {
+      xi = G.xy[i];
       q0 = ld4(q, i);
       g0 = ld8(dq, i);
       l0 = ld8(qlim, i);
     }
+    s_xy[threadIdx.x] = xi;
     s_q[threadIdx.x] = q0;
     s_g[threadIdx.x] = g0;
     s_l[threadIdx.x] = l0;
   }
   __syncthreads();
   if (!active) return;
-  const double2 xi = s_xy[threadIdx.x];
+  double qb[4] = {0, 0, 0, 0};
+  double gb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double lb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int kind = G.kind[i];
-  const int c = G.cnt[i];
-  if (kind == 2) {  // Dirichlet: R = 0 does not depend on anything
-    const F4 z4{{0.0, 0.0, 0.0, 0.0}};
-    const F8 z8{{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}};
-    if (OWN) {
-      st4(qbar, i, z4);
-      st8(gbar, i, z8);
-      st8(lbar, i, z8);
-    } else {
-      for (int k = 0; k < c; ++k) st4_at(T, (size_t)(uint32_t)tpos[(size_t)k * n + i], z4);
-    }
-    return;
-  }
-  const bool interior = kind == 0;
-  const double2 nv = G.nrm[i];
-  const double nx = nv.x, ny = nv.y, tx = ny, ty = -nx;
-  const Row row{G.nbr + i, n, c, i};
-  auto fetch_xy = [&](int j) {
-    int lj;
-    return in_tile<BLK>(j, lo, lj) ? s_xy[lj] : G.xy[j];
-  };
-
-  // pass 1: geometry of the four half-plane stencils (as the forward)
-  double sss[4] = {0, 0, 0, 0}, ssn[4] = {0, 0, 0, 0}, snn[4] = {0, 0, 0, 0};
-  int cnt[4] = {0, 0, 0, 0};
-  {
+  unsigned f = 0;
+  if (kind != 2) {  // outer rows: R = 0 depends on nothing
+    const bool interior = kind == 0;
+    const double2 xi = s_xy[threadIdx.x];
+    const double2 nv = G.nrm[i];
+    const double nx = nv.x, ny = nv.y, tx = ny, ty = -nx;
+    const F8 W = ld8(spw, i);
+    double ab[4];
+    frame_seed(ld4(Rb, i), tx, ty, nx, ny, ab);
+    const double K = P.venkat_k;
+    const int c = G.cnt[i];
+    const Row row{G.nbr + i, n, c, i};
+    auto fetch_xy = [&](int j) {
+      int lj;
+      return in_tile<BLK>(j, lo, lj) ? s_xy[lj] : G.xy[j];
+    };
     int j_next = row(1);
     double2 xj = fetch_xy(row(0));
     for (int k = 0; k < c; ++k) {
       const int j_after = row(k + 2);
       const double2 xn = fetch_xy(j_next);
       const double dx = xj.x - xi.x, dy = xj.y - xi.y;
-      const double ds = dot_rn(dx, tx, dy, ty);
-      const double dn = dot_rn(dx, nx, dy, ny);
-      const bool in[4] = {ds < 0.0, ds > 0.0, interior && dn < 0.0, dn > 0.0};
-      for (int h = 0; h < 4; ++h) {
-        const double w = in[h] ? 1.0 : 0.0;
-        sss[h] += w * (ds * ds);
-        ssn[h] += w * (ds * dn);
-        snn[h] += w * (dn * dn);
-        cnt[h] += in[h] ? 1 : 0;
-      }
-      xj = xn;
-      j_next = j_after;
-    }
-  }
-  unsigned f = 0;
-  SplitW W[4];
-  for (int h = 0; h < 4; ++h) {
-    if (h == 2 && !interior) {
-      W[h] = SplitW{0.0, 0.0};
-      continue;
-    }
-    W[h] = split_weights(h < 2, cnt[h], sss[h], ssn[h], snn[h], f);
-  }
-  // seed: R = rotation of (mass, s-momentum, n-momentum, energy); the own
-  // end takes the opposite sign
-  const F4 rb = ld4(Rb, i);
-  const double sgn_end = OWN ? -1.0 : 1.0;
-  const double ab[4] = {sgn_end * rb.v[0], sgn_end * (rb.v[1] * tx + rb.v[2] * ty),
-                        sgn_end * (rb.v[1] * nx + rb.v[2] * ny), sgn_end * rb.v[3]};
-  const double K = P.venkat_k;
-
-  // own-end accumulators (OWN only)
-  double qb0[4] = {0, 0, 0, 0};
-  double gb0[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  double lb0[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-
-  int j_next = row(1);
-  int j_cur = row(0);
-  double2 xj = fetch_xy(j_cur);
-  for (int k = 0; k < c; ++k) {
-    const int j_after = row(k + 2);
-    const double2 xn = fetch_xy(j_next);
-    const double dx = xj.x - xi.x, dy = xj.y - xi.y;
-    const double ds = dot_rn(dx, tx, dy, ty);
-    const double dn = dot_rn(dx, nx, dy, ny);
-    const double eps2 = edge_eps2(K, dx, dy);
-    // split weights of this edge: s-split (ds < 0: G_s^+, ds > 0: G_s^-),
-    // n-split (dn < 0: G_n^+ at interior points, dn > 0: G_n^-)
-    const bool s_pos = ds < 0.0, n_pos = dn < 0.0;
-    const SplitW ws_ = s_pos ? W[0] : W[1];
-    const SplitW wn_ = n_pos ? W[2] : W[3];
-    const double wt_s = ds != 0.0 ? ws_.a * ds + ws_.b * dn : 0.0;
-    const double wt_n = (dn > 0.0 || (n_pos && interior)) ? wn_.a * ds + wn_.b * dn : 0.0;
-    const double sg_s = s_pos ? 1.0 : -1.0, sg_n = n_pos ? 1.0 : -1.0;
-    // (mass, d-momentum, o-momentum, energy) order of each split
-    const double Gs[4] = {wt_s * ab[0], wt_s * ab[1], wt_s * ab[2], wt_s * ab[3]};
-    const double Gn[4] = {wt_n * ab[0], wt_n * ab[2], wt_n * ab[1], wt_n * ab[3]};
-
-    // this end's limited modified q
-    double qt[4], d[4], rmax[4], rmin[4];
-    if (OWN) {
+      const EdgeSeed e = edge_seed(dx, dy, tx, ty, nx, ny, interior, W, ab, -1.0);
       // keeps the compiler from hoisting the own-record reads out of the loop
       asm volatile("" ::: "memory");
       const F4 q0 = s_q[threadIdx.x];
       const F8 g0 = s_g[threadIdx.x], l0 = s_l[threadIdx.x];
-      for (int m = 0; m < 4; ++m) {
-        d[m] = half_step(dx, dy, g0.v[m], g0.v[4 + m]);
-        rmax[m] = l0.v[m] - q0.v[m];
-        rmin[m] = l0.v[4 + m] - q0.v[m];
-        qt[m] = q0.v[m] + limited(d[m], rmax[m], rmin[m], eps2);
-      }
-    } else {
-      int lj;
-      F4 qj;
-      F8 gj, lj8;
-      if (in_tile<BLK>(j_cur, lo, lj)) {
-        qj = s_q[lj];
-        gj = s_g[lj];
-        lj8 = s_l[lj];
-      } else {
-        qj = ld4(q, j_cur);
-        gj = ld8(dq, j_cur);
-        lj8 = ld8(qlim, j_cur);
-      }
-      for (int m = 0; m < 4; ++m) {
-        d[m] = half_step(dx, dy, gj.v[m], gj.v[4 + m]);
-        qt[m] = qj.v[m] + limited(d[m], lj8.v[m] - qj.v[m], lj8.v[4 + m] - qj.v[m], eps2);
-      }
+      f |= end_reverse(P, q0, g0, l0, dx, dy, edge_eps2(K, dx, dy), tx, ty, nx, ny, e, qb, gb, lb);
+      xj = xn;
+      j_next = j_after;
     }
-    EndState st;
-    EndExtra ex;
-    f |= end_state_t<true>(qt, P, tx, ty, nx, ny, st, &ex);
-    EndBar b{0, 0, 0, 0, 0, 0, 0};
-    if (wt_s != 0.0) split_flux_rev(sg_s, st, st.us, st.un, Gs, b, b.us, b.un);
-    if (wt_n != 0.0) split_flux_rev(sg_n, st, st.un, st.us, Gn, b, b.un, b.us);
-    double qtb[4];
-    end_state_rev(P, tx, ty, nx, ny, st, ex, b, qtb);
-    if (OWN) {
-      // q~_0 = q_0 + phi delta_0, delta_0 = -(d . grad q_0)/2
-      for (int m = 0; m < 4; ++m) {
-        const LimRev r = limited_rev(d[m], rmax[m], rmin[m], eps2, qtb[m]);
-        qb0[m] += qtb[m];
-        gb0[m] += -0.5 * dx * r.ddelta;
-        gb0[4 + m] += -0.5 * dy * r.ddelta;
-        if (r.sel > 0) {
-          lb0[m] += r.droom;
-          qb0[m] -= r.droom;
-        } else if (r.sel < 0) {
-          lb0[4 + m] += r.droom;
-          qb0[m] -= r.droom;
-        }
-      }
-    } else {
-      st4_at(T, (size_t)(uint32_t)tpos[(size_t)k * n + i], F4{{qtb[0], qtb[1], qtb[2], qtb[3]}});
-    }
-    xj = xn;
-    j_cur = j_next;
-    j_next = j_after;
   }
-  if (OWN) {
-    st4(qbar, i, F4{{qb0[0], qb0[1], qb0[2], qb0[3]}});
-    st8(gbar, i, F8{{gb0[0], gb0[1], gb0[2], gb0[3], gb0[4], gb0[5], gb0[6], gb0[7]}});
-    st8(lbar, i, F8{{lb0[0], lb0[1], lb0[2], lb0[3], lb0[4], lb0[5], lb0[6], lb0[7]}});
-  } else {
-    flag(status, f);
-  }
-}
-
-template <int BLK>
-__global__ void __launch_bounds__(BLK) k_flux_rev_nbr(Geo G, Flow P,
-                                                         const double *__restrict__ q,
-                                                         const double *__restrict__ dq,
-                                                         const double *__restrict__ qlim,
-                                                         const double *__restrict__ Rb,
-                                                         const int32_t *__restrict__ tpos,
-                                                         double *__restrict__ T,
-                                                         unsigned *status) {
-  flux_rev_body<BLK, false>(G, P, q, dq, qlim, Rb, tpos, T, nullptr, nullptr, nullptr, status);
-}
-
-// two waves per SIMD: the register budget is 256 per lane
-template <int BLK>
-__global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(2)))
-k_flux_rev_own(Geo G, Flow P,
-                                                         const double *__restrict__ q,
-                                                         const double *__restrict__ dq,
-                                                         const double *__restrict__ qlim,
-                                                         const double *__restrict__ Rb,
-                                                         double *__restrict__ qbar,
-                                                         double *__restrict__ gbar,
-                                                         double *__restrict__ lbar) {
-  flux_rev_body<BLK, true>(G, P, q, dq, qlim, Rb, nullptr, nullptr, qbar, gbar, lbar, nullptr);
+  st4(qbar, i, F4{{qb[0], qb[1], qb[2], qb[3]}});
+  st8(gbar, i, F8{{gb[0], gb[1], gb[2], gb[3], gb[4], gb[5], gb[6], gb[7]}});
+  st8(lbar, i, F8{{lb[0], lb[1], lb[2], lb[3], lb[4], lb[5], lb[6], lb[7]}});
+  flag(status, f);
 }
 
 // s = M^-1 g per component: (s_x, s_y) = [[a, b], [b, c]] (g_x, g_y)
@@ -397,82 +374,104 @@ struct InRow {
   }
 };
 
-// Transposed gather of the flux reverse at point j: the neighbour-end limiter
-// reverse of every edge that reads j (its cotangent T in j's in-edge row),
-// added to the own-end parts.  In place: qbar_j and lbar_j complete; sbar_j
-// (holding the own-end gbar_j on entry) becomes M_j^-1 gbar_j, the seed of
-// the derivative reverse.
+// Neighbour end of every edge that reads point j, as a gather over j's
+// in-edges: each edge (i, j) is recomputed from row i's frame, split
+// weights and seed.  Adds the own-end parts left by k_flux_rev_own; in
+// place: qbar_j, lbar_j complete, and sbar_j (holding the own-end gbar_j on
+// entry) becomes M_j^-1 gbar_j, the seed of the derivative reverse.
 template <int BLK>
-__global__ void __launch_bounds__(BLK) k_flux_gather(Geo G, Flow P,
-                                                        const int32_t *__restrict__ in_cnt,
-                                                        const int32_t *__restrict__ in_ent,
-                                                        const double *__restrict__ lsg,
-                                                        const double *__restrict__ q,
-                                                        const double *__restrict__ dq,
-                                                        const double *__restrict__ qlim,
-                                                        const double *__restrict__ T,
-                                                        double *__restrict__ qbar,
-                                                        double *__restrict__ sbar,
-                                                        double *__restrict__ lbar) {
+__global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(2)))
+k_flux_gather(Geo G, Flow P, const int32_t *__restrict__ in_cnt,
+              const int32_t *__restrict__ in_ent, const double *__restrict__ lsg,
+              const double *__restrict__ spw, const double *__restrict__ q,
+              const double *__restrict__ dq, const double *__restrict__ qlim,
+              const double *__restrict__ Rb, double *__restrict__ qbar,
+              double *__restrict__ sbar, double *__restrict__ lbar) {
   __shared__ double2 s_xy[BLK];
+  __shared__ double2 s_nrm[BLK];
+  __shared__ F8 s_w[BLK];
+  __shared__ F4 s_rb[BLK];
+  __shared__ F4 s_q[BLK];
+  __shared__ F8 s_g[BLK];
+  __shared__ F8 s_l[BLK];
+  __shared__ int8_t s_kind[BLK];
   const int n = G.n;
   const int lo = tile_lo<BLK>(G.xcd);
   const int j = lo + threadIdx.x;
   const bool active = j < n;
-  const double2 xj = active ? G.xy[j] : make_double2(0.0, 0.0);
-  s_xy[threadIdx.x] = xj;
+  {
+    double2 x = make_double2(0.0, 0.0), nv = x;
+    F8 w{{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}}, g = w, l = w;
+    F4 r{{0.0, 0.0, 0.0, 0.0}}, qq = r;
+    int8_t kd = 2;
+    if (active) {
+      x = G.xy[j];
+      nv = G.nrm[j];
+      w = ld8(spw, j);
+      r = ld4(Rb, j);
+      qq = ld4(q, j);
+      g = ld8(dq, j);
+      l = ld8(qlim, j);
+      kd = G.kind[j];
+    }
+    s_xy[threadIdx.x] = x;
+    s_nrm[threadIdx.x] = nv;
+    s_w[threadIdx.x] = w;
+    s_rb[threadIdx.x] = r;
+    s_q[threadIdx.x] = qq;
+    s_g[threadIdx.x] = g;
+    s_l[threadIdx.x] = l;
+    s_kind[threadIdx.x] = kd;
+  }
   __syncthreads();
   if (!active) return;
-  const F4 qj = ld4(q, j);
-  const F8 gj = ld8(dq, j), lj = ld8(qlim, j);
-  const F4 qb_own = ld4(qbar, j);
-  const F8 gb_own = ld8(sbar, j), lb_own = ld8(lbar, j);
-  double qb[4], gb[8], lb[8];
-  for (int m = 0; m < 4; ++m) qb[m] = qb_own.v[m];
-  for (int m = 0; m < 8; ++m) {
-    gb[m] = gb_own.v[m];
-    lb[m] = lb_own.v[m];
-  }
-  double rmax[4], rmin[4];
-  for (int m = 0; m < 4; ++m) {
-    rmax[m] = lj.v[m] - qj.v[m];
-    rmin[m] = lj.v[4 + m] - qj.v[m];
-  }
+  double qb[4] = {0, 0, 0, 0};
+  double gb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double lb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const double2 xj = s_xy[threadIdx.x];
   const double K = P.venkat_k;
-  auto fetch_xy = [&](int i) {
-    int li;
-    return in_tile<BLK>(i, lo, li) ? s_xy[li] : G.xy[i];
-  };
   const int c = in_cnt[j];
   const InRow row{in_ent + j, n, c, j};
-  const int clast = c > 0 ? c - 1 : 0;
-  int ent_next = row(1);
-  double2 xi = fetch_xy(row(0) & kPointMask);
-  F4 tb = ld4_at(T, (size_t)j);
+  int ent_next = row(0);
   for (int e = 0; e < c; ++e) {
-    const int ent_after = row(e + 2);
-    const double2 xi_n = fetch_xy(ent_next & kPointMask);
-    const F4 tb_n = ld4_at(T, (size_t)(e + 1 < c ? e + 1 : clast) * n + j);
+    const int i = ent_next & kPointMask;
+    ent_next = row(e + 1);
+    int li;
+    double2 xi, nv;
+    F8 W;
+    F4 rb;
+    int ki;
+    if (in_tile<BLK>(i, lo, li)) {
+      ki = s_kind[li];
+      xi = s_xy[li];
+      nv = s_nrm[li];
+      W = s_w[li];
+      rb = s_rb[li];
+    } else {
+      ki = G.kind[i];
+      xi = G.xy[i];
+      nv = G.nrm[i];
+      W = ld8(spw, i);
+      rb = ld4(Rb, i);
+    }
+    if (ki == 2) continue;  // outer rows have no residual
+    const double nx = nv.x, ny = nv.y, tx = ny, ty = -nx;
+    double ab[4];
+    frame_seed(rb, tx, ty, nx, ny, ab);
     // the edge as row i sees it: d = x_j - x_i
     const double dx = xj.x - xi.x, dy = xj.y - xi.y;
-    const double eps2 = edge_eps2(K, dx, dy);
-    for (int m = 0; m < 4; ++m) {
-      const double dl = half_step(dx, dy, gj.v[m], gj.v[4 + m]);
-      const LimRev r = limited_rev(dl, rmax[m], rmin[m], eps2, tb.v[m]);
-      qb[m] += tb.v[m];
-      gb[m] += -0.5 * dx * r.ddelta;
-      gb[4 + m] += -0.5 * dy * r.ddelta;
-      if (r.sel > 0) {
-        lb[m] += r.droom;
-        qb[m] -= r.droom;
-      } else if (r.sel < 0) {
-        lb[4 + m] += r.droom;
-        qb[m] -= r.droom;
-      }
-    }
-    xi = xi_n;
-    tb = tb_n;
-    ent_next = ent_after;
+    const EdgeSeed es = edge_seed(dx, dy, tx, ty, nx, ny, ki == 0, W, ab, 1.0);
+    asm volatile("" ::: "memory");
+    const F4 qj = s_q[threadIdx.x];
+    const F8 gj = s_g[threadIdx.x], lj = s_l[threadIdx.x];
+    end_reverse(P, qj, gj, lj, dx, dy, edge_eps2(K, dx, dy), tx, ty, nx, ny, es, qb, gb, lb);
+  }
+  const F4 qo = ld4(qbar, j);
+  const F8 go = ld8(sbar, j), lo8 = ld8(lbar, j);
+  for (int m = 0; m < 4; ++m) qb[m] += qo.v[m];
+  for (int m = 0; m < 8; ++m) {
+    gb[m] += go.v[m];
+    lb[m] += lo8.v[m];
   }
   double sv[8];
   apply_minv(ld8(lsg, j), gb, sv);
@@ -830,7 +829,7 @@ int n_levels(const lskum_plan_s *p) { return p->params[0].n_inner + 1; }
 
 // workspace layout, in units of one double per point (f1)
 struct VjpWs {
-  double *q, *dq0, *qlim, *qbar, *sa, *sb, *lbar, *T;
+  double *q, *dq0, *qlim, *qbar, *sa, *sb, *lbar;
   int8_t *argext;
 };
 
@@ -854,15 +853,13 @@ VjpWs vjp_layout(const lskum_plan_s *p, void *ws) {
   w.lbar = reinterpret_cast<double *>(b + o);
   o += 8 * f1;
   w.argext = reinterpret_cast<int8_t *>(b + o);
-  o += f1;
-  w.T = reinterpret_cast<double *>(b + o);
   return w;
 }
 
 size_t vjp_bytes(const lskum_plan_s *p) {
   const size_t f1 = f1_bytes(p);
   const size_t fields = 4 + 8 * (size_t)n_levels(p) + 8 + 4 + 8 + 8 + 8 + 1;
-  return fields * f1 + align256((size_t)p->k_in * (size_t)p->n * 4 * sizeof(double));
+  return fields * f1;
 }
 
 template <class T>
@@ -884,7 +881,7 @@ int adjoint_prepare(lskum_plan_s *p, void *stream) {
   const int32_t n = p->n, kp = p->k_pad, ki = p->k_in;
   std::vector<int32_t> nbr, cnt;
   std::vector<int8_t> kind;
-  std::vector<int32_t> in_cnt, in_ent, tpos, outer, ooff;
+  std::vector<int32_t> in_cnt, in_ent, outer, ooff;
   int rc = LSKUM_OK;
   try {
     if ((rc = download(nbr, p->nbr, (size_t)n * kp)) || (rc = download(cnt, p->cnt, (size_t)n)) ||
@@ -893,14 +890,12 @@ int adjoint_prepare(lskum_plan_s *p, void *stream) {
     in_cnt.assign((size_t)n, 0);
     in_ent.resize((size_t)ki * n);
     for (int32_t j = 0; j < n; ++j) in_ent[(size_t)j] = j;  // a point with no in-edge
-    tpos.assign((size_t)kp * n, 0);
     for (int32_t i = 0; i < n; ++i)  // i ascending, then slot: rows sorted
       for (int32_t s = 0; s < cnt[(size_t)i]; ++s) {
         const int32_t j = nbr[(size_t)s * n + i];
         const int32_t e = in_cnt[(size_t)j]++;
         if (e >= ki) return LSKUM_ERR_BAD_CLOUD;  // k_in is the largest in-degree
         in_ent[(size_t)e * n + j] = (s << kSlotShift) | i;
-        tpos[(size_t)s * n + i] = e * n + j;
       }
     ooff.push_back(0);
     for (int32_t c = 0; c < p->n_clouds; ++c) {
@@ -913,13 +908,14 @@ int adjoint_prepare(lskum_plan_s *p, void *stream) {
   }
   if ((rc = upload(&p->in_cnt, in_cnt.data(), in_cnt.size())) ||
       (rc = upload(&p->in_ent, in_ent.data(), in_ent.size())) ||
-      (rc = upload(&p->tpos, tpos.data(), tpos.size())) ||
       (rc = upload(&p->outer, outer.data(), outer.size())) ||
       (rc = upload(&p->ooff, ooff.data(), ooff.size())))
     return rc;
-  if (hipMalloc((void **)&p->lsg, (size_t)n * 8 * sizeof(double)) != hipSuccess)
+  if (hipMalloc((void **)&p->lsg, (size_t)n * 8 * sizeof(double)) != hipSuccess ||
+      hipMalloc((void **)&p->spw, (size_t)n * 8 * sizeof(double)) != hipSuccess)
     return LSKUM_ERR_NO_MEMORY;
   k_ls_geometry<<<grid_for(n), kBlock, 0, S(stream)>>>(geo(p), p->lsg);
+  k_split_weights<<<grid_for(n), kBlock, 0, S(stream)>>>(geo(p), p->spw, p->status);
   if ((rc = launched())) return rc;
   if (hipStreamSynchronize(S(stream)) != hipSuccess) return LSKUM_ERR_HIP;
   p->adj_ready = true;
@@ -928,10 +924,10 @@ int adjoint_prepare(lskum_plan_s *p, void *stream) {
 
 // free whatever a failed preparation left
 void adjoint_reset(lskum_plan_s *p) {
-  void *bufs[] = {p->in_cnt, p->in_ent, p->tpos, p->lsg, p->outer, p->ooff};
+  void *bufs[] = {p->in_cnt, p->in_ent, p->lsg, p->spw, p->outer, p->ooff};
   for (void *b : bufs) (void)hipFree(b);
-  p->in_cnt = p->in_ent = p->tpos = p->outer = p->ooff = nullptr;
-  p->lsg = nullptr;
+  p->in_cnt = p->in_ent = p->outer = p->ooff = nullptr;
+  p->lsg = p->spw = nullptr;
   p->adj_ready = false;
 }
 
@@ -975,11 +971,10 @@ int reverse_passes(lskum_plan_s *p, const VjpWs &w, const double *U, const doubl
   const double *dqK = w.dq0 + (size_t)K * lev;
   const Geo g = geo(p);
   const Flow f = flow(p);
-  LSKUM_TILED_ADJ(k_flux_rev_nbr, p, stream, g, f, w.q, dqK, w.qlim, Rbar, p->tpos, w.T,
-                  p->status);
-  LSKUM_TILED_ADJ(k_flux_rev_own, p, stream, g, f, w.q, dqK, w.qlim, Rbar, w.qbar, w.sa, w.lbar);
-  LSKUM_TILED_ADJ(k_flux_gather, p, stream, g, f, p->in_cnt, p->in_ent, p->lsg, w.q, dqK, w.qlim,
-                  w.T, w.qbar, w.sa, w.lbar);
+  LSKUM_TILED_ADJ(k_flux_rev_own, p, stream, g, f, p->spw, w.q, dqK, w.qlim, Rbar, w.qbar, w.sa,
+                  w.lbar, p->status);
+  LSKUM_TILED_ADJ(k_flux_gather, p, stream, g, f, p->in_cnt, p->in_ent, p->lsg, p->spw, w.q, dqK,
+                  w.qlim, Rbar, w.qbar, w.sa, w.lbar);
   double *cur = w.sa, *nxt = w.sb;
   for (int k = K; k >= 1; --k) {
     LSKUM_TILED_ADJ(k_inner_rev, p, stream, g, p->in_cnt, p->in_ent, p->lsg, cur, w.qbar, nxt);

@@ -308,7 +308,7 @@ struct lskum_plan_s {
   int32_t k_in = 0;               // padded in-edge row width (largest in-degree)
   int32_t *in_cnt = nullptr;      // [n] in-edges of each point
   int32_t *in_ent = nullptr;      // [k_in][n] (slot << kSlotShift) | source point
-  int32_t *tpos = nullptr;        // [k_pad][n] in-edge position e*n + j of row slot (k, i)
+  double *spw = nullptr;          // [n][8] half-plane least-squares weights
   double *lsg = nullptr;          // [n][8] least-squares geometry of each point
   int32_t *outer = nullptr;       // outer points, grouped by cloud
   int32_t *ooff = nullptr;        // [n_clouds+1] offsets into outer
