@@ -337,9 +337,11 @@ def main():
     wl = WORKLOADS[args.workload]
     steps = wl.iters if args.steps is None else args.steps
     warm = args.warmup
-    torch.cuda.set_device(0)
+    # the cloud is built (in worker processes for large clouds) before the
+    # GPU is touched
     log(f"[bench] generating the {wl.name} cloud ({wl.W} x {wl.L})")
     cloud = wl.cloud()
+    torch.cuda.set_device(0)
     n = cloud.n
     edges = int(cloud.nbr_count.astype(np.int64).sum())
     p = L.Params(wl.mach, wl.aoa_deg, wl.cfl, wl.venkat_k, wl.n_inner, wl.gamma)

@@ -32,8 +32,11 @@ Construction (an O-type point distribution, then Hilbert reordering):
    the ``k_max`` nearest within 2.5x the distance to the 8th nearest
    candidate.  No wall-to-wall link joins the upper and lower surfaces aft
    of mid-chord (such a link would cross the body near the trailing edge).
-   The window is widened for any point whose full stencil or whose used
-   half-plane (split) stencils are too small or ill-conditioned.
+   The window is widened (up to 8) for any point whose full stencil or whose
+   used half-plane (split) stencils are too small or ill-conditioned; a
+   point still failing takes the k_max nearest of the widest window without
+   the radius cut (wall points at the trailing edge of the 16M cloud, where
+   the wall spacing is far below the first layer's distance).
 5. Points are reordered along a Hilbert curve on a 2^20 x 2^20 lattice over
    the bounding box (ties by original id); rows keep their order.
 """
@@ -41,6 +44,8 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import multiprocessing
+import os
 
 import numpy as np
 
@@ -110,7 +115,11 @@ def _solve_growth(L: int, first_step: float) -> float:
     if first_step >= 1.0 / (L - 1):
         raise ValueError("wall spacing too coarse for the layer count")
     lo, hi = 1.0 + 1e-14, 2.0
-    f = lambda g: (g - 1.0) / (g ** (L - 1) - 1.0) - first_step
+
+    def f(g):
+        if (L - 1) * math.log(g) > 700.0:  # g^(L-1) beyond double range: ratio ~ 0
+            return -first_step
+        return (g - 1.0) / (g ** (L - 1) - 1.0) - first_step
     for _ in range(200):
         mid = 0.5 * (lo + hi)
         if f(mid) > 0.0:
@@ -179,8 +188,10 @@ def _window_offsets(w: int):
     return dj[keep], dl[keep]
 
 
-def _select(ids, W, L, side, xflat, yflat, w, k_max):
-    """Neighbour selection for the points ``ids`` with index window ``w``.
+def _select(ids, W, L, side, xflat, yflat, w, k_max, radius=2.5):
+    """Neighbour selection for the points ``ids`` with index window ``w``:
+    the k_max nearest candidates within ``radius`` times the distance to the
+    8th nearest (no radius cut when ``radius`` is None).
 
     Returns (nbr [m, k_max] int64 padded with -1, count [m])."""
     j = ids % W
@@ -211,7 +222,10 @@ def _select(ids, W, L, side, xflat, yflat, w, k_max):
     if np.any(n_valid < 8):
         raise RuntimeError("index window too small")
     r8 = np.sqrt(d2s[:, 7])
-    inside = np.sqrt(d2s) <= 2.5 * r8[:, None]
+    if radius is None:
+        inside = np.ones(d2s.shape, dtype=bool)
+    else:
+        inside = np.sqrt(d2s) <= radius * r8[:, None]
     rank = np.arange(d2s.shape[1])[None, :]
     take = inside & (rank < k_max) & np.isfinite(d2s)
     count = take.sum(axis=1)
@@ -286,6 +300,41 @@ def hilbert_order(x: np.ndarray, y: np.ndarray, order: int = 20) -> np.ndarray:
     return np.argsort(_hilbert_key(xq, yq, order), kind="stable")
 
 
+# clouds above this many points build their stencils in worker processes
+PARALLEL_POINTS = 1 << 22
+_POOL_ARGS = None
+
+
+def _chunk_stencils(start, W, L, side, xflat, yflat, kind, nxf, nyf, k_max, chunk, n):
+    """Stencils of the points start .. start+chunk-1: the nearest-neighbour
+    selection in the index window w = 3, widened for the points whose
+    stencil fails the sufficiency test until it passes."""
+    ids = np.arange(start, min(n, start + chunk), dtype=np.int64)
+    nbr_out = np.full((ids.size, k_max), -1, dtype=np.int64)
+    cnt_out = np.zeros(ids.size, dtype=np.int64)
+    w = 3
+    todo = ids
+    while todo.size:
+        if w > 9:
+            raise RuntimeError(f"no valid stencil for {todo.size} points")
+        # last resort (w = 9): the window of 8 without the radius cut, for
+        # points whose 8 nearest candidates all lie on one side (wall points
+        # at the trailing edge of very fine clouds, where the wall spacing is
+        # far below the first layer's distance)
+        nbr, cnt = _select(todo, W, L, side, xflat, yflat, min(w, 8), k_max,
+                           radius=2.5 if w <= 8 else None)
+        ok = _stencil_ok(todo, nbr, cnt, kind, xflat, yflat, nxf, nyf)
+        nbr_out[todo[ok] - start] = nbr[ok]
+        cnt_out[todo[ok] - start] = cnt[ok]
+        todo = todo[~ok]
+        w += 1
+    return ids, nbr_out, cnt_out
+
+
+def _chunk_stencils_pooled(start):
+    return _chunk_stencils(start, *_POOL_ARGS)
+
+
 def make_airfoil_cloud(W: int, L: int, k_max: int, seed: int, *, t: float = 0.12,
                        r_outer: float = 15.0, jitter: float = 0.2, reorder: bool = True,
                        chunk: int = 1 << 18) -> Cloud:
@@ -305,19 +354,26 @@ def make_airfoil_cloud(W: int, L: int, k_max: int, seed: int, *, t: float = 0.12
 
     nbr_all = np.full((n, k_max), -1, dtype=np.int64)
     cnt_all = np.zeros(n, dtype=np.int64)
-    for start in range(0, n, chunk):
-        ids = np.arange(start, min(n, start + chunk), dtype=np.int64)
-        w = 3
-        todo = ids
-        while todo.size:
-            if w > 8:
-                raise RuntimeError(f"no valid stencil for {todo.size} points")
-            nbr, cnt = _select(todo, W, L, side, xflat, yflat, w, k_max)
-            ok = _stencil_ok(todo, nbr, cnt, kind, xflat, yflat, nxf, nyf)
-            nbr_all[todo[ok]] = nbr[ok]
-            cnt_all[todo[ok]] = cnt[ok]
-            todo = todo[~ok]
-            w += 1
+    starts = list(range(0, n, chunk))
+    args = (W, L, side, xflat, yflat, kind, nxf, nyf, k_max, chunk, n)
+    workers = min(len(starts), os.cpu_count() or 1, 16)
+    if n > PARALLEL_POINTS and workers > 1:
+        # chunks are independent (each point's stencil depends only on the
+        # positions in its index window), so the result does not depend on
+        # how they are distributed
+        global _POOL_ARGS
+        _POOL_ARGS = args
+        try:
+            with multiprocessing.get_context("fork").Pool(workers) as pool:
+                parts = pool.map(_chunk_stencils_pooled, starts)
+        finally:
+            _POOL_ARGS = None
+    else:
+        parts = [_chunk_stencils(start, *args) for start in starts]
+    for start, (ids, nbr, cnt) in zip(starts, parts):
+        nbr_all[ids] = nbr
+        cnt_all[ids] = cnt
+    del parts
 
     wall_loop = np.arange(W, dtype=np.int64)  # ids l*W + j with l == 0
     if reorder:

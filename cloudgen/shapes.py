@@ -122,3 +122,37 @@ def square_cloud(nside: int, jitter: float = 0.25, seed: int = 0, k: int = 20,
         a = rng.uniform(0, 2 * np.pi, x.size)
         nx, ny = np.cos(a), np.sin(a)
     return from_points(x, y, nx, ny, kind, k=k)
+
+
+def restrict(cloud: Cloud, seeds, depth: int):
+    """The sub-cloud of the points within `depth` stencil hops of `seeds`.
+
+    Points keep their relative order and their rows keep the stored order of
+    the neighbours that stay; rows of the outermost ring lose the neighbours
+    outside.  A quantity of a seed point that reads rows up to depth - 1 and
+    pointwise values up to `depth` (the residual with n inner sweeps reads
+    derivative rows up to n + 1 hops, q up to n + 2) is the same on the
+    sub-cloud as on the whole cloud.  Returns (sub-cloud, original ids)."""
+    n, kp = cloud.n, cloud.k_pad
+    col = cloud.col.reshape(n, kp)
+    cnt = cloud.nbr_count
+    mask = np.arange(kp)[None, :] < cnt[:, None]
+    member = np.zeros(n, bool)
+    frontier = np.unique(np.asarray(seeds, np.int64))
+    member[frontier] = True
+    for _ in range(depth):
+        nb = col[frontier][mask[frontier]]
+        nb = np.unique(nb[~member[nb]])
+        member[nb] = True
+        frontier = nb
+    ids = np.nonzero(member)[0]
+    new = np.full(n, -1, np.int64)
+    new[ids] = np.arange(ids.size)
+    rows = []
+    for i in ids:
+        r = col[i, :cnt[i]]
+        rows.append(new[r[member[r]]])
+    wall = [int(new[w]) for w in cloud.wall_loop if member[w]]
+    sub = from_lists(cloud.x[ids], cloud.y[ids], cloud.nx[ids], cloud.ny[ids], cloud.kind[ids],
+                     rows, wall_loop=wall, k_pad=kp)
+    return sub, ids

@@ -114,3 +114,26 @@ def test_batch_draws():
     sizes = np.array([d["W"] * d["L"] for d in draws])
     assert sizes.min() >= 4000 and sizes.max() <= 260000
     assert all(0.3 <= d["mach"] <= 0.9 and -4 <= d["aoa_deg"] <= 6 for d in draws)
+
+
+def test_restricted_cloud_reproduces_the_residual_at_its_seeds(tiny_cloud):
+    """The residual at a seed reads derivative rows n_inner + 1 hops out and
+    q n_inner + 2 hops out, so the sub-cloud of that depth gives the seeds'
+    residual bit for bit (full-size parity tests compare sampled points this
+    way)."""
+    from cloudgen.shapes import restrict
+    from oracle.ref import Oracle
+    c = tiny_cloud
+    o = Oracle(c, 0.63, 2.0, n_inner=2)
+    U, _, _ = o.iterate(o.init_state(), 3)
+    R, _ = o.residual(U)
+    rng = np.random.default_rng(5)
+    seeds = np.concatenate([rng.choice(np.nonzero(c.kind == 0)[0], 12, replace=False),
+                            rng.choice(np.nonzero(c.kind == 1)[0], 6, replace=False)])
+    sub, ids = restrict(c, seeds, 4)
+    assert sub.n < c.n
+    pos = np.searchsorted(ids, seeds)
+    assert np.array_equal(ids[pos], seeds)
+    os_ = Oracle(sub, 0.63, 2.0, n_inner=2)
+    Rs, _ = os_.residual(U[:, ids])
+    assert np.array_equal(Rs[:, pos], R[:, seeds])

@@ -245,6 +245,45 @@ def test_parity_1m_bench_configuration():
     assert s.status() == L.OK
 
 
+@pytest.mark.timeout(600)
+def test_parity_16m_sampled_points():
+    """The 16M-point workload after 2 GPU iterations: q, dq, qlim and R at
+    sampled points (random interior and wall points, and the wall points
+    at the trailing edge, where the wall spacing is finest) against the
+    oracle on the sub-cloud within n_inner + 2 hops of the samples, which
+    reproduces their values exactly."""
+    from cloudgen.shapes import restrict
+    wl = WORKLOADS["16m"]
+    say("generating the 16M cloud")
+    cloud = wl.cloud()
+    p = params_of(wl)
+    s = Solver(cloud, p)
+    say("2 GPU iterations at 16M")
+    s.run(2)
+    q, dq, qlim, R = s.residual()
+    assert s.status() == L.OK
+    rng = np.random.default_rng(16)
+    wall = np.nonzero(cloud.kind == 1)[0]
+    te = wall[np.argsort(-cloud.x[wall])[:6]]
+    samples = np.unique(np.concatenate([
+        rng.choice(np.nonzero(cloud.kind == 0)[0], 48, replace=False),
+        rng.choice(wall, 16, replace=False), te]))
+    sub, ids = restrict(cloud, samples, p.n_inner + 2)
+    say(f"oracle on the {sub.n}-point sub-cloud of {samples.size} samples")
+    pos = np.searchsorted(ids, samples)
+    idx = torch.from_numpy(ids).cuda()
+    U_sub = host(s.U[idx]).T
+    o = oracle_of(sub, p)
+    qo, _ = o.q_vars(U_sub)
+    dqo, qlimo = o.q_derivs(qo)
+    Ro, _ = o.flux_residual(qo, dqo, qlimo)
+    sidx = torch.from_numpy(samples).cuda()
+    assert_field("q 16M", host(q[sidx]).T, qo[:, pos])
+    assert_field("dq 16M", host(dq[sidx]).T, dqo[:, pos])
+    assert_field("qlim 16M", host(qlim[sidx]).T, qlimo[:, pos])
+    assert_field("R 16M", host(R[sidx]).T, Ro[:, pos])
+
+
 @pytest.mark.parametrize("M,Lr", [(24, 8), (32, 8), (48, 12)])  # 192, 256, 576 points
 def test_small_and_ragged_clouds_with_garbage_padding(M, Lr):
     c = cylinder_cloud(M=M, L=Lr)
