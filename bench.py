@@ -226,7 +226,7 @@ def bench_adjoint(args) -> int:
     gen = torch.Generator().manual_seed(7)
     Rb = torch.randn((n, 4), generator=gen, dtype=torch.float64).cuda()
     Jb = torch.tensor([1.0, 0.0], dtype=torch.float64, device="cuda")
-    q, dq, qlim, work, R = (plan.field(c) for c in (4, 8, 8, 8, 4))
+    q, dq, qlim, work, R = (plan.field(c) for c in (4, 8, 8, 16, 4))
     Ub, Fb = plan.field(4), plan.field(4)
     tb = torch.empty(2, dtype=torch.float64, device="cuda")
     ws = L.vjp_workspace(plan)
@@ -349,7 +349,7 @@ def main():
     U = plan.field(4)
     L.lskum_init_state(plan, U)
     U0_host = U.cpu().numpy().T.copy()  # oracle layout (4, n)
-    Un, q, dq, qlim, work, R = (plan.field(c) for c in (4, 4, 8, 8, 8, 4))
+    Un, q, dq, qlim, work, R = (plan.field(c) for c in (4, 4, 8, 8, 16, 4))
     dt = plan.field(1)
     hist = torch.zeros(max(steps + warm, 1), dtype=torch.float64, device="cuda")
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))

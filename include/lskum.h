@@ -134,7 +134,8 @@ int lskum_q_vars(lskum_plan plan, const double *U, double *q, void *stream);
 
 /* Least-squares q-derivatives (eq. (9) with dq_i = q_i - q_0, then
  * params.n_inner Jacobi sweeps of eq. (14)-(15)) and the stencil bounds
- * qlim.  `work` is an [n][8] scratch buffer; the final iterate is in dq. */
+ * qlim.  `work` is an [n][16] scratch buffer (64-byte aligned; unused when
+ * n_inner is 0); the final iterate is in dq. */
 int lskum_q_derivs(lskum_plan plan, const double *q, double *dq, double *qlim, double *work,
                    void *stream);
 

@@ -95,7 +95,7 @@ class Adjoint:
     # plain kernel sequences used by the Functions
     def _residual(self, Ue: torch.Tensor) -> torch.Tensor:
         p, s = self.plan, self.stream
-        q, dq, qlim, work, R = p.field(4), p.field(8), p.field(8), p.field(8), p.field(4)
+        q, dq, qlim, work, R = p.field(4), p.field(8), p.field(8), p.field(16), p.field(4)
         L.lskum_q_vars(p, Ue, q, s)
         L.lskum_q_derivs(p, q, dq, qlim, work, s)
         L.lskum_flux_residual(p, q, dq, qlim, R, s)

@@ -157,80 +157,73 @@ __global__ void __launch_bounds__(BLK) k_deriv_first(Geo G, const double *__rest
   }
 }
 
-// One Jacobi inner sweep (eq. (14)-(15)): modified differences from the
-// previous iterate at both ends of each edge.
+// One Jacobi inner sweep (eq. (14)-(15)).  The modified differences are
+// q~_j - q~_i = (q_j - q_i) - d.(g_j - g_i)/2 with g the previous iterate,
+// and M_i^-1 sum_j d (q_j - q_i) is the first-order solution dq0_i, so
+//   dq_i = dq0_i + g_i/2 - M_i^-1 sum_j d (d . g_j) / 2:
+// the sweep gathers only the neighbours' previous derivatives.
 template <int BLK>
-__global__ void __launch_bounds__(BLK) k_deriv_inner(Geo G, const double *__restrict__ q,
+__global__ void __launch_bounds__(BLK) k_deriv_inner(Geo G, const double *__restrict__ dq0,
                                                         const double *__restrict__ dqp,
                                                         double *__restrict__ dqn) {
   __shared__ double2 s_xy[BLK];
-  __shared__ F4 s_q[BLK];
   __shared__ F8 s_g[BLK];
   const int n = G.n;
   const int lo = tile_lo<BLK>(G.xcd);
   const int i = lo + threadIdx.x;
   const bool active = i < n;
   double2 xi = make_double2(0.0, 0.0);
-  F4 q0{{0.0, 0.0, 0.0, 0.0}};
   F8 g0{{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}};
   if (active) {
     xi = G.xy[i];
-    q0 = ld4(q, i);
     g0 = ld8(dqp, i);
   }
   s_xy[threadIdx.x] = xi;
-  s_q[threadIdx.x] = q0;
   s_g[threadIdx.x] = g0;
   __syncthreads();
   if (!active) return;
-  double sxq[4] = {0, 0, 0, 0}, syq[4] = {0, 0, 0, 0};
+  double ax[4] = {0, 0, 0, 0}, ay[4] = {0, 0, 0, 0};
   double sxx = 0.0, sxy = 0.0, syy = 0.0;
   const int c = G.cnt[i];
   const Row row{G.nbr + i, n, c, i};
-  auto fetch = [&](int j, double2 &xj, F4 &qj, F8 &gj) {
+  auto fetch = [&](int j, double2 &xj, F8 &gj) {
     int lj;
     if (in_tile<BLK>(j, lo, lj)) {
       xj = s_xy[lj];
-      qj = s_q[lj];
       gj = s_g[lj];
     } else {
       xj = G.xy[j];
-      qj = ld4(q, j);
       gj = ld8(dqp, j);
     }
   };
   int j_next = row(1);
   double2 xj;
-  F4 qj;
   F8 gj;
-  fetch(row(0), xj, qj, gj);
+  fetch(row(0), xj, gj);
   for (int k = 0; k < c; ++k) {
     const int j_after = row(k + 2);
     double2 xn;
-    F4 qn;
     F8 gn;
-    fetch(j_next, xn, qn, gn);
+    fetch(j_next, xn, gn);
     const double dx = xj.x - xi.x, dy = xj.y - xi.y;
     sxx += dx * dx;
     sxy += dx * dy;
     syy += dy * dy;
     for (int m = 0; m < 4; ++m) {
-      const double qtj = qj.v[m] - 0.5 * (dx * gj.v[m] + dy * gj.v[4 + m]);
-      const double qt0 = q0.v[m] - 0.5 * (dx * g0.v[m] + dy * g0.v[4 + m]);
-      const double d = qtj - qt0;
-      sxq[m] += dx * d;
-      syq[m] += dy * d;
+      const double t = dx * gj.v[m] + dy * gj.v[4 + m];
+      ax[m] += dx * t;
+      ay[m] += dy * t;
     }
     xj = xn;
-    qj = qn;
     gj = gn;
     j_next = j_after;
   }
   const double det = sxx * syy - sxy * sxy;
+  const F8 d0 = ld8(dq0, i);
   F8 g;
   for (int m = 0; m < 4; ++m) {
-    g.v[m] = (syy * sxq[m] - sxy * syq[m]) / det;
-    g.v[4 + m] = (sxx * syq[m] - sxy * sxq[m]) / det;
+    g.v[m] = d0.v[m] + 0.5 * g0.v[m] - 0.5 * ((syy * ax[m] - sxy * ay[m]) / det);
+    g.v[4 + m] = d0.v[4 + m] + 0.5 * g0.v[4 + m] - 0.5 * ((sxx * ay[m] - sxy * ax[m]) / det);
   }
   st8(dqn, i, g);
 }
@@ -238,58 +231,28 @@ __global__ void __launch_bounds__(BLK) k_deriv_inner(Geo G, const double *__rest
 // ---------------------------------------------------------------------------
 // flux residual
 
-template <int BLK>
-__global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__restrict__ q,
-                                                 const double *__restrict__ dq,
-                                                 const double *__restrict__ qlim,
-                                                 double *__restrict__ R, unsigned *status) {
-  __shared__ double2 s_xy[BLK];
-  __shared__ F4 s_q[BLK];
-  __shared__ F8 s_g[BLK];
-  __shared__ F8 s_l[BLK];
+// Least-squares weights of the four half-plane stencils of every point
+// (geometry only; computed when the plan is built): spw[i] = (a, b) of s+,
+// s-, n+, n-, and the weight of edge d in split h is a_h ds + b_h dn.  A used
+// split that is singular, and the n+ split of wall and outer points, get
+// (0, 0).
+__global__ void __launch_bounds__(kBlock) k_split_weights(Geo G, double *__restrict__ spw) {
   const int n = G.n;
-  const int lo = tile_lo<BLK>(G.xcd);
-  const int i = lo + threadIdx.x;
-  const bool active = i < n;
-  double2 xi = make_double2(0.0, 0.0);
-  F4 q0{{0.0, 0.0, 0.0, 0.0}};
-  F8 g0{{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}}, l0 = g0;
-  if (active) {
-    xi = G.xy[i];
-    q0 = ld4(q, i);
-    g0 = ld8(dq, i);
-    l0 = ld8(qlim, i);
-  }
-  s_xy[threadIdx.x] = xi;
-  s_q[threadIdx.x] = q0;
-  s_g[threadIdx.x] = g0;
-  s_l[threadIdx.x] = l0;
-  __syncthreads();
-  if (!active) return;
+  const int i = point_index<kBlock>(G.xcd);
+  if (i >= n) return;
   const int kind = G.kind[i];
   if (kind == 2) {
-    st4(R, i, F4{{0.0, 0.0, 0.0, 0.0}});
+    st8(spw, i, F8{{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}});
     return;
   }
   const bool interior = kind == 0;
-  const double2 nv = G.nrm[i];
+  const double2 xi = G.xy[i], nv = G.nrm[i];
   const double nx = nv.x, ny = nv.y, tx = ny, ty = -nx;
   const int c = G.cnt[i];
-  const Row row{G.nbr + i, n, c, i};
-  auto fetch_xy = [&](int j) {
-    int lj;
-    return in_tile<BLK>(j, lo, lj) ? s_xy[lj] : G.xy[j];
-  };
-
-  // pass 1: geometry of the four half-plane stencils
   double sss[4] = {0, 0, 0, 0}, ssn[4] = {0, 0, 0, 0}, snn[4] = {0, 0, 0, 0};
   int cnt[4] = {0, 0, 0, 0};
-  {
-  int j_next = row(1);
-  double2 xj = fetch_xy(row(0));
   for (int k = 0; k < c; ++k) {
-    const int j_after = row(k + 2);
-    const double2 xn = fetch_xy(j_next);
+    const double2 xj = G.xy[G.nbr[(size_t)k * n + i]];
     const double dx = xj.x - xi.x, dy = xj.y - xi.y;
     const double ds = dot_rn(dx, tx, dy, ty);
     const double dn = dot_rn(dx, nx, dy, ny);
@@ -301,32 +264,86 @@ __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__res
       snn[h] += w * (dn * dn);
       cnt[h] += in[h] ? 1 : 0;
     }
-    xj = xn;
-    j_next = j_after;
-  }
   }
   unsigned f = 0;
-  SplitW W[4];
+  F8 out;
   for (int h = 0; h < 4; ++h) {
-    if (h == 2 && !interior) {
-      W[h] = SplitW{0.0, 0.0};
-      continue;
-    }
-    W[h] = split_weights(h < 2, cnt[h], sss[h], ssn[h], snn[h], f);
+    SplitW w{0.0, 0.0};
+    if (!(h == 2 && !interior)) w = split_weights(h < 2, cnt[h], sss[h], ssn[h], snn[h], f);
+    out.v[2 * h] = w.a;
+    out.v[2 * h + 1] = w.b;
   }
+  st8(spw, i, out);
+}
 
-  double mx0[4], mn0[4];
-  for (int m = 0; m < 4; ++m) {
-    mx0[m] = l0.v[m] - q0.v[m];
-    mn0[m] = l0.v[4 + m] - q0.v[m];
+// A used split is singular exactly when its weights are (0, 0): a regular
+// s-split has a = Snn/det > 0, a regular n-split b = Sss/det > 0.
+__device__ __forceinline__ unsigned degenerate_splits(const F8 &W, bool interior) {
+  const bool bad = W.v[0] == 0.0 || W.v[2] == 0.0 || (interior && W.v[5] == 0.0) ||
+                   W.v[7] == 0.0;
+  return bad ? kFlagDegenerate : 0u;
+}
+
+// Flux residual of every point: for each edge, the limited modified q at
+// both ends, their states, and the split fluxes of the edge's s- and
+// n-split, weighted by the point's half-plane least-squares weights.  The
+// point's own records and weights are re-read from LDS at every edge
+// instead of being held in registers through the loop.
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__restrict__ spw,
+                                                 const double *__restrict__ q,
+                                                 const double *__restrict__ dq,
+                                                 const double *__restrict__ qlim,
+                                                 double *__restrict__ R, unsigned *status) {
+  __shared__ double2 s_xy[BLK];
+  __shared__ F4 s_q[BLK];
+  __shared__ F8 s_g[BLK];
+  __shared__ F8 s_l[BLK];
+  __shared__ F8 s_w[BLK];
+  const int n = G.n;
+  const int lo = tile_lo<BLK>(G.xcd);
+  const int i = lo + threadIdx.x;
+  const bool active = i < n;
+  {
+    double2 xi = make_double2(0.0, 0.0);
+    F4 q0{{0.0, 0.0, 0.0, 0.0}};
+    F8 g0{{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}}, l0 = g0, w0 = g0;
+    if (active) {
+      xi = G.xy[i];
+      q0 = ld4(q, i);
+      g0 = ld8(dq, i);
+      l0 = ld8(qlim, i);
+      w0 = ld8(spw, i);
+    }
+    s_xy[threadIdx.x] = xi;
+    s_q[threadIdx.x] = q0;
+    s_g[threadIdx.x] = g0;
+    s_l[threadIdx.x] = l0;
+    s_w[threadIdx.x] = w0;
   }
+  __syncthreads();
+  if (!active) return;
+  const int kind = G.kind[i];
+  if (kind == 2) {
+    st4(R, i, F4{{0.0, 0.0, 0.0, 0.0}});
+    return;
+  }
+  const bool interior = kind == 0;
+  const double2 xi = s_xy[threadIdx.x];
+  const double2 nv = G.nrm[i];
+  const double nx = nv.x, ny = nv.y, tx = ny, ty = -nx;
+  const int c = G.cnt[i];
+  const Row row{G.nbr + i, n, c, i};
+  auto fetch_xy = [&](int j) {
+    int lj;
+    return in_tile<BLK>(j, lo, lj) ? s_xy[lj] : G.xy[j];
+  };
+  unsigned f = degenerate_splits(s_w[threadIdx.x], interior);
   const double K = P.venkat_k;
   double acc[4] = {0, 0, 0, 0};  // (mass, s-momentum, n-momentum, energy)
 
-  // pass 2: limited modified q at both ends, split fluxes, weighted sums.
   // The index and coordinates are prefetched ahead; the neighbour's larger
-  // records are loaded at the top of the iteration, while the own end's
-  // reconstruction (which needs only the coordinates) proceeds.
+  // records are loaded at the top of the iteration.
   int j_next = row(1);
   int j_cur = row(0);
   double2 xj = fetch_xy(j_cur);
@@ -350,21 +367,28 @@ __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__res
     const double dn = dot_rn(dx, nx, dy, ny);
     const double eps2 = edge_eps2(K, dx, dy);
     double qtj[4], qt0[4];
-    for (int m = 0; m < 4; ++m) {
-      const double dj = half_step(dx, dy, gj.v[m], gj.v[4 + m]);
-      qtj[m] = qj.v[m] + limited(dj, lj8.v[m] - qj.v[m], lj8.v[4 + m] - qj.v[m], eps2);
-      const double d0 = half_step(dx, dy, g0.v[m], g0.v[4 + m]);
-      qt0[m] = q0.v[m] + limited(d0, mx0[m], mn0[m], eps2);
+    {
+      // keeps the compiler from hoisting the own-record reads out of the loop
+      asm volatile("" ::: "memory");
+      const F4 q0 = s_q[threadIdx.x];
+      const F8 g0 = s_g[threadIdx.x], l0 = s_l[threadIdx.x];
+      for (int m = 0; m < 4; ++m) {
+        const double dj = half_step(dx, dy, gj.v[m], gj.v[4 + m]);
+        qtj[m] = qj.v[m] + limited(dj, lj8.v[m] - qj.v[m], lj8.v[4 + m] - qj.v[m], eps2);
+        const double d0 = half_step(dx, dy, g0.v[m], g0.v[4 + m]);
+        qt0[m] = q0.v[m] + limited(d0, l0.v[m] - q0.v[m], l0.v[4 + m] - q0.v[m], eps2);
+      }
     }
     EndState sj, s0;
     f |= end_state(qtj, P, tx, ty, nx, ny, sj);
     f |= end_state(qt0, P, tx, ty, nx, ny, s0);
+    const F8 W = s_w[threadIdx.x];
 
     // s-direction split: ds < 0 -> G_s^+, ds > 0 -> G_s^-
     {
       const bool pos = ds < 0.0;
-      const SplitW w = pos ? W[0] : W[1];
-      const double wt = ds != 0.0 ? w.a * ds + w.b * dn : 0.0;
+      const double wa = pos ? W.v[0] : W.v[2], wb = pos ? W.v[1] : W.v[3];
+      const double wt = ds != 0.0 ? wa * ds + wb * dn : 0.0;
       const double sg = pos ? 1.0 : -1.0;
       double Gj[4], G0[4];
       split_flux(sg, sj, sj.us, sj.un, Gj);
@@ -377,9 +401,9 @@ __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__res
     // n-direction split: dn < 0 -> G_n^+ (interior only), dn > 0 -> G_n^-
     {
       const bool pos = dn < 0.0;
-      const SplitW w = pos ? W[2] : W[3];
+      const double wa = pos ? W.v[4] : W.v[6], wb = pos ? W.v[5] : W.v[7];
       const bool used = dn > 0.0 || (pos && interior);
-      const double wt = used ? w.a * ds + w.b * dn : 0.0;
+      const double wt = used ? wa * ds + wb * dn : 0.0;
       const double sg = pos ? 1.0 : -1.0;
       double Gj[4], G0[4];
       split_flux(sg, sj, sj.un, sj.us, Gj);
@@ -616,9 +640,9 @@ int deriv_first_launch(lskum_plan_s *p, const double *q, double *dq, double *qli
   return launched();
 }
 
-int deriv_inner_launch(lskum_plan_s *p, const double *q, const double *dqp, double *dqn,
+int deriv_inner_launch(lskum_plan_s *p, const double *dq0, const double *dqp, double *dqn,
                        void *stream) {
-  LSKUM_TILED(k_deriv_inner, p, stream, geo(p), q, dqp, dqn);
+  LSKUM_TILED(k_deriv_inner, p, stream, geo(p), dq0, dqp, dqn);
   return launched();
 }
 
@@ -672,7 +696,7 @@ void release(lskum_plan_s *p) {
   delete p;
 }
 
-constexpr size_t kNumWorkFields = 4 + 4 + 8 + 8 + 8 + 4 + 1;  // Un q dq qlim work R dt
+constexpr size_t kNumWorkFields = 4 + 4 + 8 + 8 + 16 + 4 + 1;  // Un q dq qlim work R dt
 
 // Validate one cloud and append it (point ids shifted by base) to the
 // concatenated host arrays.
@@ -743,18 +767,20 @@ int norm_launch(lskum_plan_s *p, const double *R, double *out, const int32_t *co
   return launched();
 }
 
+// First-order solve, then n_inner sweeps.  work holds two [n][8] fields:
+// the first-order solution (kept through the sweeps) and the ping-pong
+// partner of dq, arranged so that the last sweep writes dq.
 int q_derivs_launch(lskum_plan_s *p, const double *q, double *dq, double *qlim, double *work,
                     void *stream) {
   const int ni = p->params[0].n_inner;
-  // ping-pong so that the last sweep writes dq
-  double *a = (ni % 2 == 0) ? dq : work;
-  double *b = (ni % 2 == 0) ? work : dq;
-  int rc = deriv_first_launch(p, q, a, qlim, nullptr, stream);
-  for (int it = 0; it < ni && rc == LSKUM_OK; ++it) {
-    rc = deriv_inner_launch(p, q, a, b, stream);
-    double *t = a;
-    a = b;
-    b = t;
+  if (ni == 0) return deriv_first_launch(p, q, dq, qlim, nullptr, stream);
+  double *dq0 = work + (size_t)8 * p->n;
+  int rc = deriv_first_launch(p, q, dq0, qlim, nullptr, stream);
+  const double *prev = dq0;
+  for (int k = 1; k <= ni && rc == LSKUM_OK; ++k) {
+    double *next = ((ni - k) % 2 == 0) ? dq : work;
+    rc = deriv_inner_launch(p, dq0, prev, next, stream);
+    prev = next;
   }
   return rc;
 }
@@ -772,8 +798,8 @@ int run_iterations(lskum_plan_s *p, int32_t iters, double *U, double *hist, int3
   double *dq = reinterpret_cast<double *>(base + 8 * f1);
   double *qlim = reinterpret_cast<double *>(base + 16 * f1);
   double *work = reinterpret_cast<double *>(base + 24 * f1);
-  double *R = reinterpret_cast<double *>(base + 32 * f1);
-  double *dt = reinterpret_cast<double *>(base + 36 * f1);
+  double *R = reinterpret_cast<double *>(base + 40 * f1);
+  double *dt = reinterpret_cast<double *>(base + 44 * f1);
   const Geo g = geo(p);
   const Flow f = flow(p);
   const int grid = grid_for(p->n);
@@ -785,7 +811,7 @@ int run_iterations(lskum_plan_s *p, int32_t iters, double *U, double *hist, int3
     for (int s = 0; s < 4; ++s) {
       if ((rc = q_vars_launch(p, U, q, stream))) return rc;
       if ((rc = q_derivs_launch(p, q, dq, qlim, work, stream))) return rc;
-      LSKUM_TILED(k_flux, p, stream, g, f, q, dq, qlim, R, p->status);
+      LSKUM_TILED(k_flux, p, stream, g, f, p->spw, q, dq, qlim, R, p->status);
       if (s == 0) {
         if (counter)
           rc = norm_launch(p, R, hist ? hist : p->norm_scratch, counter, hist ? hist_rows : 1,
@@ -917,6 +943,12 @@ int lskum_batch_plan_create(lskum_plan *out, int32_t n_clouds, const lskum_cloud
                          hipMalloc((void **)&p->status, sizeof(unsigned)) != hipSuccess))
     rc = LSKUM_ERR_NO_MEMORY;
   if (rc == LSKUM_OK) rc = upload_uinf(p);
+  if (rc == LSKUM_OK && hipMalloc((void **)&p->spw, (size_t)n * 8 * sizeof(double)) != hipSuccess)
+    rc = LSKUM_ERR_NO_MEMORY;
+  if (rc == LSKUM_OK) {
+    k_split_weights<<<grid_for(n), kBlock, 0, S(stream)>>>(geo(p), p->spw);
+    rc = launched();
+  }
   if (rc == LSKUM_OK && (hipMemsetAsync(p->status, 0, sizeof(unsigned), S(stream)) != hipSuccess ||
                          hipMemsetAsync(p->counter, 0, sizeof(int32_t), S(stream)) != hipSuccess ||
                          hipStreamSynchronize(S(stream)) != hipSuccess))
@@ -992,7 +1024,7 @@ int lskum_q_derivs(lskum_plan p, const double *q, double *dq, double *qlim, doub
 int lskum_flux_residual(lskum_plan p, const double *q, const double *dq, const double *qlim,
                         double *R, void *stream) {
   if (!p || !a32(q) || !a64(dq) || !a64(qlim) || !a32(R)) return LSKUM_ERR_INVALID_ARG;
-  LSKUM_TILED(k_flux, p, stream, geo(p), flow(p), q, dq, qlim, R, p->status);
+  LSKUM_TILED(k_flux, p, stream, geo(p), flow(p), p->spw, q, dq, qlim, R, p->status);
   return launched();
 }
 

@@ -21,8 +21,6 @@
 //                          (slot << 25) | i for the e-th row i listing j (at
 //                          `slot`), sorted by i then slot; k_in = largest
 //                          in-degree
-//   spw    F8    [n]       least-squares weights of the four half-plane
-//                          stencils (geometry only)
 //   lsg    F8    [n]       least-squares geometry: M^-1 = [[a, b], [b, c]] of
 //                          the point's normal matrix, and sum of its edge
 //                          vectors (sdx, sdy)
@@ -143,55 +141,10 @@ __device__ __forceinline__ void end_state_rev(const Flow &P, double tx, double t
 // seed of row i rotated into i's frame:
 //   own end (q~_i): k_flux_rev_own, one thread per row i over its edges;
 //   neighbour end (q~_j): k_flux_gather, one thread per point j over the
-//     rows that list it, recomputing each edge from the source's weights,
-//     normal and seed, which are precomputed or cheap (k_split_weights).
+//     rows that list it, recomputing each edge from the source's half-plane
+//     weights (computed with the plan), normal and seed.
 // Neither end's intermediate is stored: the reverse of an edge end is
 // recomputed where its cotangent is consumed.
-
-// Least-squares weights of the four half-plane stencils of every point
-// (geometry only, computed once per plan): spw[i] = (a, b) of s+, s-, n+,
-// n-; the weight of edge d in split h is a_h ds + b_h dn.
-__global__ void __launch_bounds__(kBlock) k_split_weights(Geo G, double *__restrict__ spw,
-                                                          unsigned *status) {
-  const int n = G.n;
-  const int i = point_index<kBlock>(G.xcd);
-  if (i >= n) return;
-  const int kind = G.kind[i];
-  if (kind == 2) {
-    st8(spw, i, F8{{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}});
-    return;
-  }
-  const bool interior = kind == 0;
-  const double2 xi = G.xy[i], nv = G.nrm[i];
-  const double nx = nv.x, ny = nv.y, tx = ny, ty = -nx;
-  const int c = G.cnt[i];
-  double sss[4] = {0, 0, 0, 0}, ssn[4] = {0, 0, 0, 0}, snn[4] = {0, 0, 0, 0};
-  int cnt[4] = {0, 0, 0, 0};
-  for (int k = 0; k < c; ++k) {
-    const double2 xj = G.xy[G.nbr[(size_t)k * n + i]];
-    const double dx = xj.x - xi.x, dy = xj.y - xi.y;
-    const double ds = dot_rn(dx, tx, dy, ty);
-    const double dn = dot_rn(dx, nx, dy, ny);
-    const bool in[4] = {ds < 0.0, ds > 0.0, interior && dn < 0.0, dn > 0.0};
-    for (int h = 0; h < 4; ++h) {
-      const double w = in[h] ? 1.0 : 0.0;
-      sss[h] += w * (ds * ds);
-      ssn[h] += w * (ds * dn);
-      snn[h] += w * (dn * dn);
-      cnt[h] += in[h] ? 1 : 0;
-    }
-  }
-  unsigned f = 0;
-  F8 out;
-  for (int h = 0; h < 4; ++h) {
-    SplitW w{0.0, 0.0};
-    if (!(h == 2 && !interior)) w = split_weights(h < 2, cnt[h], sss[h], ssn[h], snn[h], f);
-    out.v[2 * h] = w.a;
-    out.v[2 * h + 1] = w.b;
-  }
-  st8(spw, i, out);
-  flag(status, f);
-}
 
 // Weights and seeds of edge d = x_j - x_i of row i: split weights wt_s, wt_n
 // (zero for an unused split), signs, and the seeds of both splits in their
@@ -911,11 +864,9 @@ int adjoint_prepare(lskum_plan_s *p, void *stream) {
       (rc = upload(&p->outer, outer.data(), outer.size())) ||
       (rc = upload(&p->ooff, ooff.data(), ooff.size())))
     return rc;
-  if (hipMalloc((void **)&p->lsg, (size_t)n * 8 * sizeof(double)) != hipSuccess ||
-      hipMalloc((void **)&p->spw, (size_t)n * 8 * sizeof(double)) != hipSuccess)
+  if (hipMalloc((void **)&p->lsg, (size_t)n * 8 * sizeof(double)) != hipSuccess)
     return LSKUM_ERR_NO_MEMORY;
   k_ls_geometry<<<grid_for(n), kBlock, 0, S(stream)>>>(geo(p), p->lsg);
-  k_split_weights<<<grid_for(n), kBlock, 0, S(stream)>>>(geo(p), p->spw, p->status);
   if ((rc = launched())) return rc;
   if (hipStreamSynchronize(S(stream)) != hipSuccess) return LSKUM_ERR_HIP;
   p->adj_ready = true;
@@ -924,10 +875,10 @@ int adjoint_prepare(lskum_plan_s *p, void *stream) {
 
 // free whatever a failed preparation left
 void adjoint_reset(lskum_plan_s *p) {
-  void *bufs[] = {p->in_cnt, p->in_ent, p->lsg, p->spw, p->outer, p->ooff};
+  void *bufs[] = {p->in_cnt, p->in_ent, p->lsg, p->outer, p->ooff};
   for (void *b : bufs) (void)hipFree(b);
   p->in_cnt = p->in_ent = p->outer = p->ooff = nullptr;
-  p->lsg = p->spw = nullptr;
+  p->lsg = nullptr;
   p->adj_ready = false;
 }
 
@@ -956,7 +907,7 @@ int forward_recompute(lskum_plan_s *p, const VjpWs &w, const double *U, void *st
   if ((rc = q_vars_launch(p, U, w.q, stream))) return rc;
   if ((rc = deriv_first_launch(p, w.q, w.dq0, w.qlim, w.argext, stream))) return rc;
   for (int k = 1; k <= K; ++k)
-    if ((rc = deriv_inner_launch(p, w.q, w.dq0 + (k - 1) * lev, w.dq0 + k * lev, stream)))
+    if ((rc = deriv_inner_launch(p, w.dq0, w.dq0 + (k - 1) * lev, w.dq0 + k * lev, stream)))
       return rc;
   return LSKUM_OK;
 }

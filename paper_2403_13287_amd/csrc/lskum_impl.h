@@ -308,7 +308,7 @@ struct lskum_plan_s {
   int32_t k_in = 0;               // padded in-edge row width (largest in-degree)
   int32_t *in_cnt = nullptr;      // [n] in-edges of each point
   int32_t *in_ent = nullptr;      // [k_in][n] (slot << kSlotShift) | source point
-  double *spw = nullptr;          // [n][8] half-plane least-squares weights
+  double *spw = nullptr;          // [n][8] half-plane least-squares weights (with the plan)
   double *lsg = nullptr;          // [n][8] least-squares geometry of each point
   int32_t *outer = nullptr;       // outer points, grouped by cloud
   int32_t *ooff = nullptr;        // [n_clouds+1] offsets into outer
@@ -367,7 +367,8 @@ int q_vars_launch(lskum_plan_s *p, const double *U, double *q, void *stream);
 // qlim (-1: the point itself), rows 0..3 for the max, 4..7 for the min
 int deriv_first_launch(lskum_plan_s *p, const double *q, double *dq, double *qlim,
                        int8_t *argext, void *stream);
-int deriv_inner_launch(lskum_plan_s *p, const double *q, const double *dqp, double *dqn,
+// one inner sweep: dq0 = the first-order solution, dqp = previous iterate
+int deriv_inner_launch(lskum_plan_s *p, const double *dq0, const double *dqp, double *dqn,
                        void *stream);
 
 }  // namespace lskum_impl

@@ -264,7 +264,7 @@ def lskum_q_vars(plan: Plan, U, q, stream=None):
 
 def lskum_q_derivs(plan: Plan, q, dq, qlim, work, stream=None):
     _check(plan.lib.lskum_q_derivs(plan.handle, plan._arg(q, 4, "q"), plan._arg(dq, 8, "dq"),
-                                   plan._arg(qlim, 8, "qlim"), plan._arg(work, 8, "work"),
+                                   plan._arg(qlim, 8, "qlim"), plan._arg(work, 16, "work"),
                                    _stream(stream)), "lskum_q_derivs")
 
 

@@ -74,7 +74,7 @@ class Solver:
         """q, dq, qlim and R of the state U (default: the current state)."""
         U = self.U if U is None else U
         p = self.plan
-        q, dq, qlim, work, R = p.field(4), p.field(8), p.field(8), p.field(8), p.field(4)
+        q, dq, qlim, work, R = p.field(4), p.field(8), p.field(8), p.field(16), p.field(4)
         L.lskum_q_vars(p, U, q, self.stream)
         L.lskum_q_derivs(p, q, dq, qlim, work, self.stream)
         L.lskum_flux_residual(p, q, dq, qlim, R, self.stream)

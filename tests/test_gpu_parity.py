@@ -100,7 +100,7 @@ def test_per_kernel_parity_tiny(tiny):
         U, _, _ = o.iterate(o.init_state(), 3)
         plan = L.Plan(cloud, p)
         Ug = up(U)
-        q, dq, qlim, work, R = plan.field(4), plan.field(8), plan.field(8), plan.field(8), plan.field(4)
+        q, dq, qlim, work, R = plan.field(4), plan.field(8), plan.field(8), plan.field(16), plan.field(4)
         L.lskum_q_vars(plan, Ug, q)
         qo, _ = o.q_vars(U)
         assert_field("q", down(q), qo)
@@ -149,7 +149,7 @@ def test_small_kernels_parity_tiny(tiny):
 def _gpu_stages(plan, Ug, iters):
     """Stage-by-stage GPU driver through the individual entry points."""
     n = plan.n
-    q, dq, qlim, work, R = plan.field(4), plan.field(8), plan.field(8), plan.field(8), plan.field(4)
+    q, dq, qlim, work, R = plan.field(4), plan.field(8), plan.field(8), plan.field(16), plan.field(4)
     dt = plan.field(1)
     norm = torch.zeros(1, dtype=torch.float64, device="cuda")
     for it in range(iters):
@@ -331,7 +331,7 @@ def test_degenerate_stencil_sets_status():
     o = oracle_of(c, p)
     U = o.init_state()
     U[0, 3] *= 1.1
-    q, dq, qlim, work, R = plan.field(4), plan.field(8), plan.field(8), plan.field(8), plan.field(4)
+    q, dq, qlim, work, R = plan.field(4), plan.field(8), plan.field(8), plan.field(16), plan.field(4)
     L.lskum_q_vars(plan, up(U), q)
     L.lskum_q_derivs(plan, q, dq, qlim, work)
     L.lskum_flux_residual(plan, q, dq, qlim, R)
