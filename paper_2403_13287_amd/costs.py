@@ -10,12 +10,14 @@ counts 2).  Every FP64 operation the kernel executes belongs to that
 formulation (the only wasted work is the n+ split flux evaluated with zero
 weight at wall points, 0.1 % of the edges of the 1M cloud), so the count is
 taken from the hardware: SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes of one launch
-on the 1M cloud divided by its edges (1.7866e10 / 29,967,646).  Per edge the
+on the 1M cloud divided by its edges (1.6775e10 / 29,967,646).  Per edge the
 formulation holds 4 erf, 6 exp, 3 Newton-refined rsqrt, 8 Newton-refined
-divides and about 200 multiply/add/FMA operations; the per-call costs of the
-elementary functions measured by the calibration kernels on arguments in
-the sweep's ranges are listed in ELEMENTARY_FLOPS (erf on wave-coherent
-arguments; on scattered ones it costs 99).
+divides and about 190 multiply/add/FMA operations; the half-plane
+least-squares weights are computed once with the plan (geometry only) and
+read per point.  The per-call costs of the elementary functions measured by
+the calibration kernels on arguments in the sweep's ranges are listed in
+ELEMENTARY_FLOPS (erf on wave-coherent arguments; on scattered ones it costs
+99).
 """
 from __future__ import annotations
 
@@ -25,7 +27,7 @@ import os
 # measured FP64 operations per call (FMA = 2), calibration kernels, gfx950
 ELEMENTARY_FLOPS = {"exp": 27, "erf": 54.4, "log": 79, "sqrt": 17, "rsqrt": 9, "div": 14}
 
-EDGE_FLOPS = 596.2  # flux kernel, FP64 operations per (point, neighbour) pair
+EDGE_FLOPS = 559.8  # flux kernel, FP64 operations per (point, neighbour) pair
 
 
 def flux_flops(n_points: int, n_edges: int) -> float:
@@ -38,17 +40,19 @@ def conn_bytes(k_pad: int) -> int:
 
 def flux_bytes(n_points: int, k_pad: int) -> float:
     """Flux pass: x, y, nx, ny, kind (33), q (32), dq (64), qlim (64),
-    connectivity; writes R (32)."""
-    return float(n_points) * (33 + 32 + 64 + 64 + 32 + conn_bytes(k_pad))
+    half-plane weights (64), connectivity; writes R (32)."""
+    return float(n_points) * (33 + 32 + 64 + 64 + 64 + 32 + conn_bytes(k_pad))
 
 
 def stage_bytes(n_points: int, k_pad: int, n_inner: int) -> float:
     """One RK stage: q-variables (64), first-order pass (16 + 32 + 64 + 64
-    + C), each inner sweep (16 + 32 + 64 + 64 + C), flux pass, stage update
-    (Un, U, R, dt, kind in; U out: 137), plus the per-iteration time step
-    and U^n copy amortised over 4 stages ((16 + 32 + 8 + C + 64)/4)."""
+    + C), each inner sweep (16 + previous derivatives 64 + first-order
+    derivatives 64 + new derivatives 64 + C), flux pass, stage update (Un,
+    U, R, dt, kind in; U out: 137), plus the per-iteration time step and U^n
+    copy amortised over 4 stages ((16 + 32 + 8 + C + 64)/4)."""
     c = conn_bytes(k_pad)
-    per = 64 + (176 + c) + n_inner * (176 + c) + (225 + c) + 137 + (120 + c) / 4.0
+    flux = flux_bytes(1, k_pad)
+    per = 64 + (176 + c) + n_inner * (208 + c) + flux + 137 + (120 + c) / 4.0
     return float(n_points) * per
 
 
