@@ -24,6 +24,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -217,6 +218,176 @@ __global__ void __launch_bounds__(BLK) k_deriv_inner(Geo G, const double *__rest
     xj = xn;
     gj = gn;
     j_next = j_after;
+  }
+  const double det = sxx * syy - sxy * sxy;
+  const F8 d0 = ld8(dq0, i);
+  F8 g;
+  for (int m = 0; m < 4; ++m) {
+    g.v[m] = d0.v[m] + 0.5 * g0.v[m] - 0.5 * ((syy * ax[m] - sxy * ay[m]) / det);
+    g.v[4 + m] = d0.v[4 + m] + 0.5 * g0.v[4 + m] - 0.5 * ((sxx * ay[m] - sxy * ax[m]) / det);
+  }
+  st8(dqn, i, g);
+}
+
+// ---------------------------------------------------------------------------
+// derivative passes on LDS tables (tile maps)
+//
+// Block b stages in LDS the records of its BLK points and of their
+// out-of-tile neighbours (the tile's halo, a few hundred points for a
+// Hilbert-ordered cloud), loaded by all threads at once with no dependent
+// round trips; each row is stored as table slots (uint16), so the gather
+// loop reads LDS only.  Same arithmetic, in the same order, as k_deriv_first
+// and k_deriv_inner, which remain the path for clouds whose halos do not fit.
+
+// Reader of point i's row of table slots; entries past the count return
+// the point's own slot (prefetching ahead never leaves the row).
+struct SlotRow {
+  const uint16_t *col;  // &lcol[i], stride n
+  int n, c, own;
+  __device__ __forceinline__ int operator()(int k) const {
+    const int kk = k < c ? k : c - 1;
+    const int sl = col[(size_t)kk * n];
+    return k < c ? sl : own;
+  }
+};
+
+template <int BLK, bool ARG>
+__global__ void __launch_bounds__(BLK) k_deriv_first_t(Geo G, Tiles T,
+                                                          const double *__restrict__ q,
+                                                          double *__restrict__ dq,
+                                                          double *__restrict__ qlim,
+                                                          int8_t *__restrict__ argext) {
+  extern __shared__ __align__(64) unsigned char smem[];
+  const int n = G.n;
+  const int tile = block_id(G.xcd);
+  const int lo = tile * BLK;
+  if (lo >= n) return;  // blocks past the last tile (the grid is a multiple of 8)
+  const int cap = BLK + T.hmax;
+  double2 *s_xy = reinterpret_cast<double2 *>(smem);
+  F4 *s_q = reinterpret_cast<F4 *>(smem + 16 * (size_t)cap);
+  const int h0 = T.hoff[tile];
+  const int slots = BLK + (T.hoff[tile + 1] - h0);
+  for (int sl = threadIdx.x; sl < slots; sl += BLK) {
+    const int pnt = sl < BLK ? lo + sl : T.hids[h0 + sl - BLK];
+    if (pnt < n) {
+      s_xy[sl] = G.xy[pnt];
+      s_q[sl] = ld4(q, pnt);
+    }
+  }
+  __syncthreads();
+  const int i = lo + threadIdx.x;
+  if (i >= n) return;
+  const double2 xi = s_xy[threadIdx.x];
+  const F4 q0 = s_q[threadIdx.x];
+  double qmax[4], qmin[4], sxq[4], syq[4];
+  int amax[4], amin[4];
+  for (int m = 0; m < 4; ++m) {
+    qmax[m] = qmin[m] = q0.v[m];
+    sxq[m] = syq[m] = 0.0;
+    amax[m] = amin[m] = -1;
+  }
+  double sxx = 0.0, sxy = 0.0, syy = 0.0;
+  const int c = G.cnt[i];
+  const SlotRow row{T.lcol + i, n, c, (int)threadIdx.x};
+  int s_next = row(1);
+  int s_cur = row(0);
+  for (int k = 0; k < c; ++k) {
+    const int s_after = row(k + 2);
+    const double2 xj = s_xy[s_cur];
+    const F4 qj = s_q[s_cur];
+    const double dx = xj.x - xi.x, dy = xj.y - xi.y;
+    sxx += dx * dx;
+    sxy += dx * dy;
+    syy += dy * dy;
+    for (int m = 0; m < 4; ++m) {
+      const double d = qj.v[m] - q0.v[m];
+      sxq[m] += dx * d;
+      syq[m] += dy * d;
+      if (ARG) {
+        if (qj.v[m] > qmax[m]) {
+          qmax[m] = qj.v[m];
+          amax[m] = k;
+        }
+        if (qj.v[m] < qmin[m]) {
+          qmin[m] = qj.v[m];
+          amin[m] = k;
+        }
+      } else {
+        qmax[m] = fmax(qmax[m], qj.v[m]);
+        qmin[m] = fmin(qmin[m], qj.v[m]);
+      }
+    }
+    s_cur = s_next;
+    s_next = s_after;
+  }
+  const double det = sxx * syy - sxy * sxy;
+  F8 g, lim;
+  for (int m = 0; m < 4; ++m) {
+    g.v[m] = (syy * sxq[m] - sxy * syq[m]) / det;
+    g.v[4 + m] = (sxx * syq[m] - sxy * sxq[m]) / det;
+    lim.v[m] = qmax[m];
+    lim.v[4 + m] = qmin[m];
+  }
+  st8(dq, i, g);
+  st8(qlim, i, lim);
+  if (ARG) {
+    uint64_t packed = 0;
+    for (int m = 0; m < 4; ++m) {
+      packed |= (uint64_t)(uint8_t)(int8_t)amax[m] << (8 * m);
+      packed |= (uint64_t)(uint8_t)(int8_t)amin[m] << (8 * (4 + m));
+    }
+    reinterpret_cast<uint64_t *>(argext)[i] = packed;
+  }
+}
+
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_deriv_inner_t(Geo G, Tiles T,
+                                                          const double *__restrict__ dq0,
+                                                          const double *__restrict__ dqp,
+                                                          double *__restrict__ dqn) {
+  extern __shared__ __align__(64) unsigned char smem[];
+  const int n = G.n;
+  const int tile = block_id(G.xcd);
+  const int lo = tile * BLK;
+  if (lo >= n) return;
+  const int cap = BLK + T.hmax;
+  double2 *s_xy = reinterpret_cast<double2 *>(smem);
+  F8 *s_g = reinterpret_cast<F8 *>(smem + 16 * (size_t)cap);
+  const int h0 = T.hoff[tile];
+  const int slots = BLK + (T.hoff[tile + 1] - h0);
+  for (int sl = threadIdx.x; sl < slots; sl += BLK) {
+    const int pnt = sl < BLK ? lo + sl : T.hids[h0 + sl - BLK];
+    if (pnt < n) {
+      s_xy[sl] = G.xy[pnt];
+      s_g[sl] = ld8(dqp, pnt);
+    }
+  }
+  __syncthreads();
+  const int i = lo + threadIdx.x;
+  if (i >= n) return;
+  const double2 xi = s_xy[threadIdx.x];
+  const F8 g0 = s_g[threadIdx.x];
+  double ax[4] = {0, 0, 0, 0}, ay[4] = {0, 0, 0, 0};
+  double sxx = 0.0, sxy = 0.0, syy = 0.0;
+  const int c = G.cnt[i];
+  const SlotRow row{T.lcol + i, n, c, (int)threadIdx.x};
+  int s_next = row(1);
+  int s_cur = row(0);
+  for (int k = 0; k < c; ++k) {
+    const int s_after = row(k + 2);
+    const double2 xj = s_xy[s_cur];
+    const F8 gj = s_g[s_cur];
+    const double dx = xj.x - xi.x, dy = xj.y - xi.y;
+    sxx += dx * dx;
+    sxy += dx * dy;
+    syy += dy * dy;
+    for (int m = 0; m < 4; ++m) {
+      const double t = dx * gj.v[m] + dy * gj.v[4 + m];
+      ax[m] += dx * t;
+      ay[m] += dy * t;
+    }
+    s_cur = s_next;
+    s_next = s_after;
   }
   const double det = sxx * syy - sxy * sxy;
   const F8 d0 = ld8(dq0, i);
@@ -611,6 +782,73 @@ struct lskum_graph_s {
 
 namespace lskum_impl {
 
+namespace {
+
+// Tile map of tile size blk from the host connectivity (column-major, pads =
+// own id): per tile, the sorted out-of-tile neighbour ids, and every row
+// entry's slot in the tile's table (own points 0..blk-1, halo after).
+int build_tile_map(lskum_plan_s *p, int blk, const int32_t *nbr, const int32_t *cnt) {
+  TileMap &m = p->maps[tile_index(blk)];
+  if (m.blk == blk) return LSKUM_OK;
+  const int32_t n = p->n, kp = p->k_pad;
+  const int32_t nt = (n + blk - 1) / blk;
+  std::vector<uint16_t> lcol;
+  std::vector<int32_t> hoff, hids, ext;
+  int hmax = 0;
+  try {
+    lcol.resize((size_t)kp * n);
+    hoff.assign((size_t)nt + 1, 0);
+    hids.reserve((size_t)n);
+    for (int32_t t = 0; t < nt; ++t) {
+      const int32_t lo = t * blk, hi = std::min(n, lo + blk);
+      ext.clear();
+      for (int32_t i = lo; i < hi; ++i)
+        for (int32_t s = 0; s < cnt[i]; ++s) {
+          const int32_t j = nbr[(size_t)s * n + i];
+          if (j < lo || j >= hi) ext.push_back(j);
+        }
+      std::sort(ext.begin(), ext.end());
+      ext.erase(std::unique(ext.begin(), ext.end()), ext.end());
+      if ((int64_t)blk + (int64_t)ext.size() > 65535) return LSKUM_ERR_INVALID_ARG;
+      hmax = std::max(hmax, (int)ext.size());
+      hoff[(size_t)t + 1] = hoff[(size_t)t] + (int32_t)ext.size();
+      hids.insert(hids.end(), ext.begin(), ext.end());
+      for (int32_t i = lo; i < hi; ++i)
+        for (int32_t s = 0; s < kp; ++s) {
+          const int32_t j = nbr[(size_t)s * n + i];
+          const int32_t sl = (j >= lo && j < hi)
+                                 ? j - lo
+                                 : blk + (int32_t)(std::lower_bound(ext.begin(), ext.end(), j) -
+                                                   ext.begin());
+          lcol[(size_t)s * n + i] = (uint16_t)sl;
+        }
+    }
+  } catch (const std::bad_alloc &) {
+    return LSKUM_ERR_NO_MEMORY;
+  }
+  int rc;
+  if ((rc = upload(&m.lcol, lcol.data(), lcol.size())) ||
+      (rc = upload(&m.hoff, hoff.data(), hoff.size())) ||
+      (rc = upload(&m.hids, hids.data(), hids.size())))
+    return rc;
+  m.hmax = (hmax + 3) / 4 * 4;
+  m.blk = blk;
+  return LSKUM_OK;
+}
+
+}  // namespace
+
+int ensure_tile_map(lskum_plan_s *p) {
+  if (p->maps[tile_index(p->block)].blk == p->block) return LSKUM_OK;
+  std::vector<int32_t> nbr((size_t)p->n * p->k_pad), cnt((size_t)p->n);
+  if (hipMemcpy(nbr.data(), p->nbr, nbr.size() * sizeof(int32_t), hipMemcpyDeviceToHost) !=
+          hipSuccess ||
+      hipMemcpy(cnt.data(), p->cnt, cnt.size() * sizeof(int32_t), hipMemcpyDeviceToHost) !=
+          hipSuccess)
+    return LSKUM_ERR_HIP;
+  return build_tile_map(p, p->block, nbr.data(), cnt.data());
+}
+
 int q_vars_launch(lskum_plan_s *p, const double *U, double *q, void *stream) {
   const Flow f = flow(p);
   k_q_vars<<<grid_for(p->n), kBlock, 0, S(stream)>>>(p->n, p->xcd, f.gamma, f.inv_gm1, U, q,
@@ -623,6 +861,26 @@ int deriv_first_launch(lskum_plan_s *p, const double *q, double *dq, double *qli
   const Geo g = geo(p);
   const int gr = grid_for(p->n, p->block);
   hipStream_t st = S(stream);
+  const TileMap &m = p->maps[tile_index(p->block)];
+  const size_t lds = (size_t)(p->block + m.hmax) * 48;
+  if (m.blk == p->block && lds <= kTileLdsBytes) {
+    const Tiles t = tiles(m);
+    switch (p->block) {
+      case 128:
+        if (argext) k_deriv_first_t<128, true><<<gr, 128, lds, st>>>(g, t, q, dq, qlim, argext);
+        else k_deriv_first_t<128, false><<<gr, 128, lds, st>>>(g, t, q, dq, qlim, nullptr);
+        break;
+      case 512:
+        if (argext) k_deriv_first_t<512, true><<<gr, 512, lds, st>>>(g, t, q, dq, qlim, argext);
+        else k_deriv_first_t<512, false><<<gr, 512, lds, st>>>(g, t, q, dq, qlim, nullptr);
+        break;
+      default:
+        if (argext) k_deriv_first_t<256, true><<<gr, 256, lds, st>>>(g, t, q, dq, qlim, argext);
+        else k_deriv_first_t<256, false><<<gr, 256, lds, st>>>(g, t, q, dq, qlim, nullptr);
+        break;
+    }
+    return launched();
+  }
   switch (p->block) {
     case 128:
       if (argext) k_deriv_first<128, true><<<gr, 128, 0, st>>>(g, q, dq, qlim, argext);
@@ -642,6 +900,18 @@ int deriv_first_launch(lskum_plan_s *p, const double *q, double *dq, double *qli
 
 int deriv_inner_launch(lskum_plan_s *p, const double *dq0, const double *dqp, double *dqn,
                        void *stream) {
+  const TileMap &m = p->maps[tile_index(p->block)];
+  const size_t lds = (size_t)(p->block + m.hmax) * 80;
+  if (m.blk == p->block && lds <= kTileLdsBytes) {
+    const int gr = grid_for(p->n, p->block);
+    const Tiles t = tiles(m);
+    switch (p->block) {
+      case 128: k_deriv_inner_t<128><<<gr, 128, lds, S(stream)>>>(geo(p), t, dq0, dqp, dqn); break;
+      case 512: k_deriv_inner_t<512><<<gr, 512, lds, S(stream)>>>(geo(p), t, dq0, dqp, dqn); break;
+      default: k_deriv_inner_t<256><<<gr, 256, lds, S(stream)>>>(geo(p), t, dq0, dqp, dqn); break;
+    }
+    return launched();
+  }
   LSKUM_TILED(k_deriv_inner, p, stream, geo(p), dq0, dqp, dqn);
   return launched();
 }
@@ -692,6 +962,11 @@ void release(lskum_plan_s *p) {
                   p->chunk_first, p->partial, p->norm_scratch, p->counter, p->status,
                   p->in_cnt, p->in_ent, p->spw, p->lsg, p->outer, p->ooff};
   for (void *b : bufs) (void)hipFree(b);
+  for (TileMap &m : p->maps) {
+    (void)hipFree(m.lcol);
+    (void)hipFree(m.hoff);
+    (void)hipFree(m.hids);
+  }
   (void)hipSetDevice(cur);
   delete p;
 }
@@ -943,6 +1218,7 @@ int lskum_batch_plan_create(lskum_plan *out, int32_t n_clouds, const lskum_cloud
                          hipMalloc((void **)&p->status, sizeof(unsigned)) != hipSuccess))
     rc = LSKUM_ERR_NO_MEMORY;
   if (rc == LSKUM_OK) rc = upload_uinf(p);
+  if (rc == LSKUM_OK) rc = build_tile_map(p, p->block, nbr.data(), cnt.data());
   if (rc == LSKUM_OK && hipMalloc((void **)&p->spw, (size_t)n * 8 * sizeof(double)) != hipSuccess)
     rc = LSKUM_ERR_NO_MEMORY;
   if (rc == LSKUM_OK) {
@@ -985,7 +1261,7 @@ int lskum_plan_set_tuning(lskum_plan p, const lskum_tuning *tuning) {
   if (!p || !tuning || !tuning_ok(tuning)) return LSKUM_ERR_INVALID_ARG;
   p->block = tuning->block ? tuning->block : 256;
   p->xcd = tuning->xcd_contiguous;
-  return LSKUM_OK;
+  return ensure_tile_map(p);
 }
 
 int32_t lskum_plan_n(lskum_plan p) { return p ? p->n : -1; }

@@ -280,6 +280,25 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
 constexpr int kSlotShift = 25;
 constexpr int32_t kPointMask = (1 << kSlotShift) - 1;
 
+// LDS tables of one tile size: block b stages the BLK points of its tile
+// and their out-of-tile neighbours (the tile's halo) in LDS, and its rows
+// are stored as slots of that table, so the gather loop reads LDS only.
+struct TileMap {
+  int blk = 0;                // tile size; 0 = not built
+  int hmax = 0;               // largest halo, rounded up to a multiple of 4
+  uint16_t *lcol = nullptr;   // [k_pad][n] table slot of every row entry (pads: own slot)
+  int32_t *hoff = nullptr;    // [n_tiles + 1] halo of tile t is hids[hoff[t] .. hoff[t+1])
+  int32_t *hids = nullptr;    // halo point ids, ascending within a tile
+};
+
+// kernel view of a TileMap
+struct Tiles {
+  const uint16_t *lcol;
+  const int32_t *hoff;
+  const int32_t *hids;
+  int hmax;
+};
+
 }  // namespace lskum_impl
 
 // ---------------------------------------------------------------------------
@@ -289,6 +308,7 @@ struct lskum_plan_s {
   int device = 0;
   int32_t n = 0, k_pad = 0, n_clouds = 0, n_wall = 0, n_chunks = 0;
   int block = 256, xcd = 1;
+  lskum_impl::TileMap maps[3];       // tile sizes 128, 256, 512 (built on demand)
   std::vector<lskum_params> params;  // one per cloud
   std::vector<int32_t> offset;       // first point of each cloud (+ total)
   double2 *xy = nullptr, *nrm = nullptr;
@@ -360,6 +380,14 @@ inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
       default: kern<256><<<g_, 256, 0, S(stream)>>>(__VA_ARGS__); break;                     \
     }                                                                                        \
   } while (0)
+
+// tile maps: index of a tile size in lskum_plan_s::maps, kernel view, and
+// the LDS budget of one block's table (two blocks per CU)
+inline int tile_index(int blk) { return blk == 128 ? 0 : (blk == 512 ? 2 : 1); }
+inline Tiles tiles(const TileMap &m) { return Tiles{m.lcol, m.hoff, m.hids, m.hmax}; }
+constexpr size_t kTileLdsBytes = 80 * 1024;
+// builds the tile map of the plan's current tile size if missing (synchronous)
+int ensure_tile_map(lskum_plan_s *p);
 
 // launchers of the forward kernels (lskum.hip), reused by the adjoint
 int q_vars_launch(lskum_plan_s *p, const double *U, double *q, void *stream);

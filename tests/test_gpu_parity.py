@@ -284,6 +284,32 @@ def test_parity_16m_sampled_points():
     assert_field("R 16M", host(R[sidx]).T, Ro[:, pos])
 
 
+@pytest.mark.parametrize("block", [128, 256])
+def test_parity_without_hilbert_order(block):
+    """An airfoil cloud left in its O-grid (layer-by-layer) order: the halos
+    of 256-point tiles span several layers and exceed the LDS tables, so the
+    derivative passes gather directly; with 128-point tiles the first-order
+    pass fits its table and the inner sweeps do not.  Both paths must give
+    the oracle's fields."""
+    from cloudgen import make_airfoil_cloud
+    c = make_airfoil_cloud(200, 40, 25, 21, reorder=False)
+    p = L.Params(0.6, 2.0, n_inner=3)
+    o = oracle_of(c, p)
+    Uo, ho, flags = o.iterate(o.init_state(), 3)
+    assert flags == 0
+    s = Solver(c, p, tuning=L.Tuning(block, 1))
+    hg = s.run(3)
+    np.testing.assert_allclose(host(hg), ho, rtol=HIST_TOL)
+    assert_field("U unordered", down(s.U), Uo)
+    q, dq, qlim, R = s.residual()
+    qo, _ = o.q_vars(Uo)
+    dqo, qlimo = o.q_derivs(qo)
+    Ro, _ = o.flux_residual(qo, dqo, qlimo)
+    assert_field("dq unordered", down(dq), dqo)
+    assert_field("qlim unordered", down(qlim), qlimo)
+    assert_field("R unordered", down(R), Ro)
+
+
 @pytest.mark.parametrize("M,Lr", [(24, 8), (32, 8), (48, 12)])  # 192, 256, 576 points
 def test_small_and_ragged_clouds_with_garbage_padding(M, Lr):
     c = cylinder_cloud(M=M, L=Lr)
