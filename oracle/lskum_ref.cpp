@@ -247,6 +247,25 @@ T venkat_phi(T delta, T dmax, T dmin, T eps2) {
   return T(1.0);
 }
 
+// Min-max limiter factor: the increment is scaled so that the reconstructed
+// value stays within the stencil bounds, phi = min(1, D/delta) with D the
+// room on delta's side (dmax for delta > 0, dmin for delta < 0); phi = 1 for
+// delta = 0.
+template <class T>
+T minmax_phi(T delta, T dmax, T dmin) {
+  T D;
+  if (delta > 0.0) {
+    D = dmax;
+  } else if (delta < 0.0) {
+    D = dmin;
+  } else {
+    return T(1.0);
+  }
+  T phi = D / delta;
+  if (phi < 1.0) return phi;
+  return T(1.0);
+}
+
 bool finite_positive(double v) { return std::isfinite(v) && v > 0.0; }
 
 // ---------------------------------------------------------------------------
@@ -409,10 +428,21 @@ unsigned flux_point(const lskum_ref_cloud &c, const lskum_ref_params &P, int32_t
     T qt_j[4], qt_0[4];
     for (int m = 0; m < 4; ++m) {
       T qj = st.nbr(k, kQ, m), q0 = st.own(kQ, m);
+      if (P.options & LSKUM_REF_FIRST_ORDER) {  // first-order scheme: q itself
+        qt_j[m] = qj;
+        qt_0[m] = q0;
+        continue;
+      }
       T del_j = -0.5 * (dx * st.nbr(k, kG, m) + dy * st.nbr(k, kG, 4 + m));
       T del_0 = -0.5 * (dx * st.own(kG, m) + dy * st.own(kG, 4 + m));
-      T phi_j = venkat_phi(del_j, st.nbr(k, kL, m) - qj, st.nbr(k, kL, 4 + m) - qj, T(eps2));
-      T phi_0 = venkat_phi(del_0, st.own(kL, m) - q0, st.own(kL, 4 + m) - q0, T(eps2));
+      T phi_j, phi_0;
+      if (P.options & LSKUM_REF_MINMAX) {
+        phi_j = minmax_phi(del_j, st.nbr(k, kL, m) - qj, st.nbr(k, kL, 4 + m) - qj);
+        phi_0 = minmax_phi(del_0, st.own(kL, m) - q0, st.own(kL, 4 + m) - q0);
+      } else {
+        phi_j = venkat_phi(del_j, st.nbr(k, kL, m) - qj, st.nbr(k, kL, 4 + m) - qj, T(eps2));
+        phi_0 = venkat_phi(del_0, st.own(kL, m) - q0, st.own(kL, 4 + m) - q0, T(eps2));
+      }
       qt_j[m] = qj + phi_j * del_j;
       qt_0[m] = q0 + phi_0 * del_0;
     }
@@ -590,6 +620,10 @@ void lskum_ref_split_flux(double gamma, int dir, int sign, const double w[4], do
 
 double lskum_ref_venkat_phi(double delta, double dmax, double dmin, double eps2) {
   return venkat_phi(delta, dmax, dmin, eps2);
+}
+
+double lskum_ref_minmax_phi(double delta, double dmax, double dmin) {
+  return minmax_phi(delta, dmax, dmin);
 }
 
 // ---------------------------------------------------------------------------

@@ -46,7 +46,12 @@ typedef struct {
   double cfl;      /* CFL number of the local time step */
   double venkat_k; /* limiter constant K: eps^2 = (K |d|)^3 */
   int32_t n_inner; /* corrective (inner) LS sweeps after the first-order one */
+  int32_t options; /* scheme variant bits (0: the default scheme) */
 } lskum_ref_params;
+
+/* options bits */
+#define LSKUM_REF_FIRST_ORDER 1u /* split fluxes of q itself (no reconstruction) */
+#define LSKUM_REF_MINMAX      2u /* min-max limiter instead of Venkatakrishnan */
 
 /* status bits returned by the sweep routines */
 #define LSKUM_REF_NONPHYSICAL 1u  /* rho, p or beta <= 0, or non-finite */
@@ -63,6 +68,8 @@ void lskum_ref_prim_from_cons(double gamma, const double U[4], double prim[4]);
 void lskum_ref_split_flux(double gamma, int dir, int sign, const double w[4], double G[4]);
 /* limiter factor phi for increment delta with bounds dmax >= 0 >= dmin */
 double lskum_ref_venkat_phi(double delta, double dmax, double dmin, double eps2);
+/* min-max limiter factor: min(1, D/delta), D the bound on delta's side */
+double lskum_ref_minmax_phi(double delta, double dmax, double dmin);
 
 /* sweep routines (one call = one pass over all points) */
 void lskum_ref_init_state(const lskum_ref_cloud *c, const lskum_ref_params *p, double *U);

@@ -28,8 +28,12 @@ class _Cloud(ctypes.Structure):
 class _Params(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("mach", ctypes.c_double),
                 ("aoa_rad", ctypes.c_double), ("cfl", ctypes.c_double),
-                ("venkat_k", ctypes.c_double), ("n_inner", ctypes.c_int32)]
+                ("venkat_k", ctypes.c_double), ("n_inner", ctypes.c_int32),
+                ("options", ctypes.c_int32)]
 
+
+FIRST_ORDER = 1  # options bits
+MINMAX = 2
 
 NONPHYSICAL = 1
 DEGENERATE = 2
@@ -56,6 +60,7 @@ def load(rebuild: bool = False) -> ctypes.CDLL:
         "lskum_ref_prim_from_cons": (None, [ctypes.c_double, vp, vp]),
         "lskum_ref_split_flux": (None, [ctypes.c_double, ctypes.c_int, ctypes.c_int, vp, vp]),
         "lskum_ref_venkat_phi": (ctypes.c_double, [ctypes.c_double] * 4),
+        "lskum_ref_minmax_phi": (ctypes.c_double, [ctypes.c_double] * 3),
         "lskum_ref_init_state": (None, [cp, pp, vp]),
         "lskum_ref_q_vars": (ctypes.c_uint, [cp, pp, vp, vp]),
         "lskum_ref_q_derivs_first": (None, [cp, vp, vp, vp]),
@@ -131,13 +136,18 @@ def venkat_phi(delta, dmax, dmin, eps2):
     return load().lskum_ref_venkat_phi(float(delta), float(dmax), float(dmin), float(eps2))
 
 
+def minmax_phi(delta, dmax, dmin):
+    return load().lskum_ref_minmax_phi(float(delta), float(dmax), float(dmin))
+
+
 # -- cloud-level sweeps ----------------------------------------------------------
 
 class Oracle:
     """The oracle bound to one cloud and one flow condition."""
 
     def __init__(self, cloud, mach: float, aoa_deg: float, *, cfl: float = 0.2,
-                 venkat_k: float = 5.0, n_inner: int = 2, gamma: float = 1.4):
+                 venkat_k: float = 5.0, n_inner: int = 2, gamma: float = 1.4,
+                 options: int = 0):
         self.lib = load()
         self.cloud = cloud
         self.n = int(cloud.x.shape[0])
@@ -157,9 +167,10 @@ class Oracle:
         self._c = _Cloud(self.n, _ptr(a["x"]), _ptr(a["y"]), _ptr(a["nx"]), _ptr(a["ny"]),
                          _ptr(a["kind"]), _ptr(a["row_ptr"]), _ptr(a["col"]),
                          _ptr(a["nbr_count"]), _ptr(a["wall_loop"]), int(a["wall_loop"].size))
-        self._p = _Params(gamma, mach, math.radians(aoa_deg), cfl, venkat_k, n_inner)
+        self._p = _Params(gamma, mach, math.radians(aoa_deg), cfl, venkat_k, n_inner, options)
         self.gamma, self.mach, self.aoa_deg = gamma, mach, aoa_deg
         self.cfl, self.venkat_k, self.n_inner = cfl, venkat_k, n_inner
+        self.options = options
 
     @property
     def params(self):
@@ -274,7 +285,8 @@ class Oracle:
     def with_flow(self, mach: float, aoa_rad: float) -> "Oracle":
         """The same cloud and settings at another free stream (AoA in radians)."""
         o = Oracle(self.cloud, mach, math.degrees(aoa_rad), cfl=self.cfl,
-                   venkat_k=self.venkat_k, n_inner=self.n_inner, gamma=self.gamma)
+                   venkat_k=self.venkat_k, n_inner=self.n_inner, gamma=self.gamma,
+                   options=self.options)
         o._p.aoa_rad = aoa_rad  # exactly, not through degrees
         return o
 
