@@ -292,6 +292,49 @@ def bench_adjoint(args) -> int:
     return 0 if status == L.OK and out["finite"] else 1
 
 
+def bench_ksweep(args) -> int:
+    """Limiter sensitivity: the 9,600-point cloud at the 1M workload's flow
+    (M 0.85, AoA 1 deg, n_inner 2) advanced 2,000 iterations with the
+    Venkatakrishnan limiter at several K and with the min-max limiter;
+    whether each stays physical, how far the residual falls, Cl and Cd."""
+    import numpy as np
+    import torch
+
+    from cloudgen import named_cloud
+    from paper_2403_13287_amd import lskum as L
+    from paper_2403_13287_amd.solver import Solver
+
+    cloud = named_cloud("tiny")
+    torch.cuda.set_device(0)
+    iters = 2000 if args.steps is None else args.steps
+    per = 250 if iters % 250 == 0 else 1
+    rows = []
+    for label, K, opt in ([(f"venkat K={k:g}", k, 0) for k in (0.3, 1.0, 5.0, 15.0, 50.0, 150.0)]
+                          + [("min-max", 5.0, L.MINMAX), ("first-order", 5.0, L.FIRST_ORDER)]):
+        s = Solver(cloud, L.Params(0.85, 1.0, 0.2, K, 2, options=opt))
+        graph, hist = s.capture(per, iters // per)
+        t0 = time.perf_counter()
+        for _ in range(iters // per):
+            graph.launch()
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        h = hist[:, 0].cpu().numpy()
+        st = s.status()
+        cl, cd = (float(v) for v in s.force_coeffs().cpu().numpy())
+        finite = bool(np.all(np.isfinite(h)))
+        row = {"limiter": label, "status": L.strerror(st), "residual_first": float(h[0]),
+               "residual_last": float(h[-1]) if finite else None,
+               "drop": float(h[-1] / h[0]) if finite else None,
+               "Cl": cl if finite else None, "Cd": cd if finite else None, "seconds": sec}
+        log(f"[bench] {label}: {row}")
+        rows.append(row)
+    print(json.dumps({"metric": "limiter sensitivity (stability and residual drop)",
+                      "config": {"workload": "tiny cloud 160 x 60 at M 0.85, AoA 1 deg, n_inner 2, "
+                                             f"CFL 0.2, {iters} iterations"},
+                      "rows": rows}), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -299,6 +342,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="1m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--scheme", default="default", choices=("default", "first-order", "minmax"),
+                    help="scheme variant of the sweep (default: the paper's second-order "
+                         "scheme with the Venkatakrishnan limiter)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of the sweep, run 5 plain device copies of this many bytes "
                          "(calibrates the HBM traffic counters)")
@@ -326,6 +372,8 @@ def main():
         return bench_batch(args)
     if args.workload == "adjoint":
         return bench_adjoint(args)
+    if args.workload == "ksweep":
+        return bench_ksweep(args)
 
     import numpy as np
     import torch
@@ -344,7 +392,8 @@ def main():
     torch.cuda.set_device(0)
     n = cloud.n
     edges = int(cloud.nbr_count.astype(np.int64).sum())
-    p = L.Params(wl.mach, wl.aoa_deg, wl.cfl, wl.venkat_k, wl.n_inner, wl.gamma)
+    options = {"default": 0, "first-order": L.FIRST_ORDER, "minmax": L.MINMAX}[args.scheme]
+    p = L.Params(wl.mach, wl.aoa_deg, wl.cfl, wl.venkat_k, wl.n_inner, wl.gamma, options=options)
     plan = L.Plan(cloud, p)
     U = plan.field(4)
     L.lskum_init_state(plan, U)
@@ -360,7 +409,8 @@ def main():
         Un.copy_(U)
         for s in range(4):
             L.lskum_q_vars(plan, U, q)
-            L.lskum_q_derivs(plan, q, dq, qlim, work)
+            if options != L.FIRST_ORDER:  # the first-order flux reads no derivatives
+                L.lskum_q_derivs(plan, q, dq, qlim, work)
             if timed:
                 ev[4 * (k - warm) + s][0].record()
             L.lskum_flux_residual(plan, q, dq, qlim, R)
@@ -389,8 +439,10 @@ def main():
     flops = costs.flux_flops(n, edges)
     achieved = flops / (flux_ms * 1e-3) / 1e12
     traffic = None
-    if wl.name == "1m":
+    if wl.name == "1m" and args.scheme == "default":
         traffic = costs.stored_flux_traffic(os.path.join(ROOT, "profiles", "k_flux_1m.txt"))
+    if args.scheme != "default":  # the FP64 count per edge is the default scheme's
+        achieved = None
     stage_gb = costs.stage_bytes(n, cloud.k_pad, wl.n_inner) / 1e9
     out = {
         "metric": METRIC,
@@ -407,11 +459,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{wl.name}: NACA 0012 O-type airfoil cloud {wl.W} x {wl.L}, "
                                f"k_max {wl.k_max}, M {wl.mach}, AoA {wl.aoa_deg} deg, "
-                               f"n_inner {wl.n_inner}, CFL {wl.cfl}, Venkatakrishnan K {wl.venkat_k}",
+                               f"n_inner {wl.n_inner}, CFL {wl.cfl}, Venkatakrishnan K {wl.venkat_k}"
+                               + ("" if args.scheme == "default" else f", scheme {args.scheme}"),
                    "points": n, "edges": edges, "k_pad": cloud.k_pad, "iterations": steps,
                    "stages_per_iteration": 4},
         "roofline": {"bound": "alu", "kernel": "k_flux", "achieved": achieved,
-                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": None if achieved is None else achieved / FP64_PEAK_TFLOPS,
                      "traffic": traffic, "flops_per_launch": flops, "avg_launch_ms": flux_ms,
                      "algorithmic_bytes_per_launch": costs.flux_bytes(n, cloud.k_pad)},
         "hbm_compulsory": {"GB_per_stage": stage_gb,

@@ -80,8 +80,18 @@ typedef struct {
   double cfl;       /* CFL number of the local time step                        */
   double venkat_k;  /* limiter constant K, eps^2 = (K |d_i|)^3                  */
   int32_t n_inner;  /* Jacobi inner sweeps after the first-order LS solve, >= 0 */
-  int32_t reserved; /* must be 0                                                */
+  int32_t options;  /* scheme variant bits, 0 = the default scheme (below)      */
 } lskum_params;
+
+/* options bits.  LSKUM_FIRST_ORDER: the split fluxes of q itself (no
+ * reconstruction; the paper's first-order scheme before the defect
+ * correction of eq. (14)), so the flux reads no derivatives and
+ * lskum_iterate skips the derivative passes.  LSKUM_MINMAX: the min-max
+ * limiter phi = min(1, D/delta) (reconstructed values stay within the
+ * stencil bounds) instead of Venkatakrishnan's.  The adjoint entry points
+ * support the default scheme only (LSKUM_ERR_INVALID_ARG otherwise). */
+#define LSKUM_FIRST_ORDER 1
+#define LSKUM_MINMAX 2
 
 /* Launch tuning of a plan: the block size (= points per LDS tile of the
  * gather kernels) and whether blocks are relabelled so that each of the 8

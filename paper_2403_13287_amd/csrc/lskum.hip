@@ -460,7 +460,8 @@ __device__ __forceinline__ unsigned degenerate_splits(const F8 &W, bool interior
 // n-split, weighted by the point's half-plane least-squares weights.  The
 // point's own records and weights are re-read from LDS at every edge
 // instead of being held in registers through the loop.
-template <int BLK>
+// VAR: 0 the default scheme, 1 first-order flux (q~ = q), 2 min-max limiter
+template <int BLK, int VAR>
 __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__restrict__ spw,
                                                  const double *__restrict__ q,
                                                  const double *__restrict__ dq,
@@ -544,10 +545,20 @@ __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__res
       const F4 q0 = s_q[threadIdx.x];
       const F8 g0 = s_g[threadIdx.x], l0 = s_l[threadIdx.x];
       for (int m = 0; m < 4; ++m) {
+        if (VAR == 1) {
+          qtj[m] = qj.v[m];
+          qt0[m] = q0.v[m];
+          continue;
+        }
         const double dj = half_step(dx, dy, gj.v[m], gj.v[4 + m]);
-        qtj[m] = qj.v[m] + limited(dj, lj8.v[m] - qj.v[m], lj8.v[4 + m] - qj.v[m], eps2);
         const double d0 = half_step(dx, dy, g0.v[m], g0.v[4 + m]);
-        qt0[m] = q0.v[m] + limited(d0, l0.v[m] - q0.v[m], l0.v[4 + m] - q0.v[m], eps2);
+        if (VAR == 2) {
+          qtj[m] = qj.v[m] + limited_minmax(dj, lj8.v[m] - qj.v[m], lj8.v[4 + m] - qj.v[m]);
+          qt0[m] = q0.v[m] + limited_minmax(d0, l0.v[m] - q0.v[m], l0.v[4 + m] - q0.v[m]);
+        } else {
+          qtj[m] = qj.v[m] + limited(dj, lj8.v[m] - qj.v[m], lj8.v[4 + m] - qj.v[m], eps2);
+          qt0[m] = q0.v[m] + limited(d0, l0.v[m] - q0.v[m], l0.v[4 + m] - q0.v[m], eps2);
+        }
       }
     }
     EndState sj, s0;
@@ -924,7 +935,7 @@ bool params_ok(const lskum_params *p) {
   return p && std::isfinite(p->gamma) && p->gamma > 1.0 && std::isfinite(p->mach) &&
          p->mach >= 0.0 && std::isfinite(p->aoa_rad) && std::isfinite(p->cfl) && p->cfl > 0.0 &&
          std::isfinite(p->venkat_k) && p->venkat_k >= 0.0 && p->n_inner >= 0 &&
-         p->n_inner <= 64 && p->reserved == 0;
+         p->n_inner <= 64 && (p->options & ~(LSKUM_FIRST_ORDER | LSKUM_MINMAX)) == 0;
 }
 
 // every cloud valid, and the settings the kernels share equal across clouds
@@ -933,7 +944,7 @@ bool batch_params_ok(int32_t nc, const lskum_params *p) {
   for (int32_t c = 0; c < nc; ++c) {
     if (!params_ok(p + c)) return false;
     if (p[c].gamma != p[0].gamma || p[c].cfl != p[0].cfl || p[c].venkat_k != p[0].venkat_k ||
-        p[c].n_inner != p[0].n_inner)
+        p[c].n_inner != p[0].n_inner || p[c].options != p[0].options)
       return false;
   }
   return true;
@@ -1034,6 +1045,24 @@ int upload_uinf(lskum_plan_s *p) {
   return LSKUM_OK;
 }
 
+// flux launch for the plan's tile size and scheme variant
+#define LSKUM_FLUX(p, stream, ...)                                                           \
+  do {                                                                                       \
+    const int g_ = grid_for((p)->n, (p)->block);                                             \
+    const int v_ = flux_variant(p);                                                          \
+    switch ((p)->block * 4 + v_) {                                                           \
+      case 128 * 4 + 0: k_flux<128, 0><<<g_, 128, 0, S(stream)>>>(__VA_ARGS__); break;       \
+      case 128 * 4 + 1: k_flux<128, 1><<<g_, 128, 0, S(stream)>>>(__VA_ARGS__); break;       \
+      case 128 * 4 + 2: k_flux<128, 2><<<g_, 128, 0, S(stream)>>>(__VA_ARGS__); break;       \
+      case 512 * 4 + 0: k_flux<512, 0><<<g_, 512, 0, S(stream)>>>(__VA_ARGS__); break;       \
+      case 512 * 4 + 1: k_flux<512, 1><<<g_, 512, 0, S(stream)>>>(__VA_ARGS__); break;       \
+      case 512 * 4 + 2: k_flux<512, 2><<<g_, 512, 0, S(stream)>>>(__VA_ARGS__); break;       \
+      case 256 * 4 + 1: k_flux<256, 1><<<g_, 256, 0, S(stream)>>>(__VA_ARGS__); break;       \
+      case 256 * 4 + 2: k_flux<256, 2><<<g_, 256, 0, S(stream)>>>(__VA_ARGS__); break;       \
+      default: k_flux<256, 0><<<g_, 256, 0, S(stream)>>>(__VA_ARGS__); break;                \
+    }                                                                                        \
+  } while (0)
+
 int norm_launch(lskum_plan_s *p, const double *R, double *out, const int32_t *counter,
                 int capacity, void *stream) {
   k_norm_partial<<<p->n_chunks, kBlock, 0, S(stream)>>>(p->chunks, p->kind, R, p->partial);
@@ -1085,8 +1114,9 @@ int run_iterations(lskum_plan_s *p, int32_t iters, double *U, double *hist, int3
     k_copy<<<copy_grid, kBlock, 0, S(stream)>>>(4 * n, U, Un);
     for (int s = 0; s < 4; ++s) {
       if ((rc = q_vars_launch(p, U, q, stream))) return rc;
-      if ((rc = q_derivs_launch(p, q, dq, qlim, work, stream))) return rc;
-      LSKUM_TILED(k_flux, p, stream, g, f, p->spw, q, dq, qlim, R, p->status);
+      // the first-order flux reads no derivatives
+      if (flux_variant(p) != 1 && (rc = q_derivs_launch(p, q, dq, qlim, work, stream))) return rc;
+      LSKUM_FLUX(p, stream, g, f, p->spw, q, dq, qlim, R, p->status);
       if (s == 0) {
         if (counter)
           rc = norm_launch(p, R, hist ? hist : p->norm_scratch, counter, hist ? hist_rows : 1,
@@ -1300,7 +1330,7 @@ int lskum_q_derivs(lskum_plan p, const double *q, double *dq, double *qlim, doub
 int lskum_flux_residual(lskum_plan p, const double *q, const double *dq, const double *qlim,
                         double *R, void *stream) {
   if (!p || !a32(q) || !a64(dq) || !a64(qlim) || !a32(R)) return LSKUM_ERR_INVALID_ARG;
-  LSKUM_TILED(k_flux, p, stream, geo(p), flow(p), p->spw, q, dq, qlim, R, p->status);
+  LSKUM_FLUX(p, stream, geo(p), flow(p), p->spw, q, dq, qlim, R, p->status);
   return launched();
 }
 

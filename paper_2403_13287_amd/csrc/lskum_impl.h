@@ -166,6 +166,15 @@ __device__ __forceinline__ double limited(double delta, double room_max, double 
   return phi * delta;
 }
 
+// Min-max-limited increment: phi = min(1, D/delta) with D the room on
+// delta's side, so the reconstructed value stays within the stencil bounds.
+__device__ __forceinline__ double limited_minmax(double delta, double room_max,
+                                                 double room_min) {
+  const double D = delta > 0.0 ? room_max : room_min;
+  const double phi = delta == 0.0 ? 1.0 : fmin(1.0, lk_div(D, delta));
+  return phi * delta;
+}
+
 // Limiter constant of an edge: eps^2 = (K |d|)^3.
 __device__ __forceinline__ double edge_eps2(double K, double dx, double dy) {
   const double d2 = dx * dx + dy * dy;
@@ -351,6 +360,12 @@ inline Flow flow(const lskum_plan_s *p) {
   f.venkat_k = q.venkat_k;
   f.gamma_is_14 = q.gamma == 1.4;
   return f;
+}
+
+// scheme variant of the flux kernel: 0 default, 1 first-order flux, 2 min-max limiter
+inline int flux_variant(const lskum_plan_s *p) {
+  const int o = p->params[0].options;
+  return (o & LSKUM_FIRST_ORDER) ? 1 : ((o & LSKUM_MINMAX) ? 2 : 0);
 }
 
 inline int launched() { return hipGetLastError() == hipSuccess ? LSKUM_OK : LSKUM_ERR_HIP; }

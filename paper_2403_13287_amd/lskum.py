@@ -27,6 +27,9 @@ ERR_NONPHYSICAL = -4
 ERR_NO_MEMORY = -5
 ERR_DEGENERATE = -6
 
+FIRST_ORDER = 1  # Params.options bits
+MINMAX = 2
+
 
 class LskumError(RuntimeError):
     def __init__(self, code: int, where: str):
@@ -47,7 +50,7 @@ class _Params(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("mach", ctypes.c_double),
                 ("aoa_rad", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("venkat_k", ctypes.c_double), ("n_inner", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("options", ctypes.c_int32)]
 
 
 class _Tuning(ctypes.Structure):
@@ -140,13 +143,14 @@ class Params:
     n_inner: int = 2
     gamma: float = 1.4
     aoa_rad: float | None = None  # if set, the angle in radians (aoa_deg ignored)
+    options: int = 0              # FIRST_ORDER | MINMAX bits (0: the default scheme)
 
     def alpha(self) -> float:
         return float(self.aoa_rad) if self.aoa_rad is not None else math.radians(self.aoa_deg)
 
     def c(self) -> _Params:
         return _Params(self.gamma, self.mach, self.alpha(), self.cfl,
-                       self.venkat_k, int(self.n_inner), 0)
+                       self.venkat_k, int(self.n_inner), int(self.options))
 
 
 @dataclass
