@@ -776,6 +776,42 @@ void lskum_ref_rk_stage(const lskum_ref_cloud *c, const lskum_ref_params *p, int
   }
 }
 
+// One stage of the classical fourth-order Runge-Kutta scheme with the same
+// local time step and L(U) = -R(U) (k_s = L of stage s's input):
+//   U1 = Un + dt/2 k_0,  U2 = Un + dt/2 k_1,  U3 = Un + dt k_2,
+//   U4 = Un + dt/6 (k_0 + 2 k_1 + 2 k_2 + k_3).
+// Rs holds R(U0) .. R(U_stage) as consecutive [4][n] fields.  The boundary
+// conditions follow every stage as in lskum_ref_rk_stage.
+void lskum_ref_rk4_stage(const lskum_ref_cloud *c, const lskum_ref_params *p, int stage,
+                         const double *Un, const double *Rs, const double *dt, double *U) {
+  const int32_t n = c->n;
+  const size_t F = 4 * (size_t)n;
+  double Uinf[4];
+  lskum_ref_free_stream(p, Uinf);
+  for (int32_t i = 0; i < n; ++i) {
+    if (c->kind[i] == 2) {
+      for (int m = 0; m < 4; ++m) fld(U, m, n, i) = Uinf[m];
+      continue;
+    }
+    for (int m = 0; m < 4; ++m) {
+      auto k = [&](int s) { return -fld(Rs + (size_t)s * F, m, n, i); };
+      double v;
+      if (stage < 2)
+        v = fld(Un, m, n, i) + 0.5 * dt[i] * k(stage);
+      else if (stage == 2)
+        v = fld(Un, m, n, i) + dt[i] * k(2);
+      else
+        v = fld(Un, m, n, i) + dt[i] / 6.0 * (k(0) + 2.0 * k(1) + 2.0 * k(2) + k(3));
+      fld(U, m, n, i) = v;
+    }
+    if (c->kind[i] == 1) {
+      double mn = fld(U, 1, n, i) * c->nx[i] + fld(U, 2, n, i) * c->ny[i];
+      fld(U, 1, n, i) = fld(U, 1, n, i) - mn * c->nx[i];
+      fld(U, 2, n, i) = fld(U, 2, n, i) - mn * c->ny[i];
+    }
+  }
+}
+
 // L2 norm of the density residual over interior and wall points.
 double lskum_ref_residual_norm(const lskum_ref_cloud *c, const double *R) {
   std::vector<double> v;
@@ -796,17 +832,23 @@ void lskum_ref_force_coeffs(const lskum_ref_cloud *c, const lskum_ref_params *p,
 unsigned lskum_ref_iterate(const lskum_ref_cloud *c, const lskum_ref_params *p, int32_t iters,
                            double *U, double *hist) {
   const size_t n = (size_t)c->n;
-  std::vector<double> Un(4 * n), q(4 * n), dq(8 * n), qlim(8 * n), R(4 * n), dt(n);
+  // Rs keeps the residual of every stage (the classical RK4 update needs all four)
+  std::vector<double> Un(4 * n), q(4 * n), dq(8 * n), qlim(8 * n), Rs(16 * n), dt(n);
+  const bool rk4 = (p->options & LSKUM_REF_RK4) != 0;
   unsigned flags = 0;
   for (int32_t it = 0; it < iters; ++it) {
     lskum_ref_local_dt(c, p, U, dt.data());
     for (size_t k = 0; k < 4 * n; ++k) Un[k] = U[k];
     for (int s = 0; s < 4; ++s) {
+      double *R = Rs.data() + (size_t)s * 4 * n;
       flags |= lskum_ref_q_vars(c, p, U, q.data());
       lskum_ref_q_derivs(c, p, q.data(), dq.data(), qlim.data());
-      flags |= lskum_ref_flux_residual(c, p, q.data(), dq.data(), qlim.data(), R.data());
-      if (s == 0 && hist) hist[it] = lskum_ref_residual_norm(c, R.data());
-      lskum_ref_rk_stage(c, p, s, Un.data(), R.data(), dt.data(), U);
+      flags |= lskum_ref_flux_residual(c, p, q.data(), dq.data(), qlim.data(), R);
+      if (s == 0 && hist) hist[it] = lskum_ref_residual_norm(c, R);
+      if (rk4)
+        lskum_ref_rk4_stage(c, p, s, Un.data(), Rs.data(), dt.data(), U);
+      else
+        lskum_ref_rk_stage(c, p, s, Un.data(), R, dt.data(), U);
     }
   }
   return flags;

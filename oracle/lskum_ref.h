@@ -52,6 +52,7 @@ typedef struct {
 /* options bits */
 #define LSKUM_REF_FIRST_ORDER 1u /* split fluxes of q itself (no reconstruction) */
 #define LSKUM_REF_MINMAX      2u /* min-max limiter instead of Venkatakrishnan */
+#define LSKUM_REF_RK4         4u /* classical four-stage Runge-Kutta time stepping */
 
 /* status bits returned by the sweep routines */
 #define LSKUM_REF_NONPHYSICAL 1u  /* rho, p or beta <= 0, or non-finite */
@@ -89,6 +90,10 @@ void lskum_ref_local_dt(const lskum_ref_cloud *c, const lskum_ref_params *p,
                         const double *U, double *dt);
 void lskum_ref_rk_stage(const lskum_ref_cloud *c, const lskum_ref_params *p, int stage,
                         const double *Un, const double *R, const double *dt, double *U);
+/* classical RK4 stage: Rs holds the residuals of stages 0..stage as
+ * consecutive [4][n] fields; U receives stage `stage`'s output */
+void lskum_ref_rk4_stage(const lskum_ref_cloud *c, const lskum_ref_params *p, int stage,
+                         const double *Un, const double *Rs, const double *dt, double *U);
 double lskum_ref_residual_norm(const lskum_ref_cloud *c, const double *R);
 void lskum_ref_force_coeffs(const lskum_ref_cloud *c, const lskum_ref_params *p,
                             const double *U, double clcd[2]);

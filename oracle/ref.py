@@ -34,6 +34,7 @@ class _Params(ctypes.Structure):
 
 FIRST_ORDER = 1  # options bits
 MINMAX = 2
+RK4 = 4
 
 NONPHYSICAL = 1
 DEGENERATE = 2
@@ -69,6 +70,7 @@ def load(rebuild: bool = False) -> ctypes.CDLL:
         "lskum_ref_flux_residual": (ctypes.c_uint, [cp, pp, vp, vp, vp, vp]),
         "lskum_ref_local_dt": (None, [cp, pp, vp, vp]),
         "lskum_ref_rk_stage": (None, [cp, pp, ctypes.c_int, vp, vp, vp, vp]),
+        "lskum_ref_rk4_stage": (None, [cp, pp, ctypes.c_int, vp, vp, vp, vp]),
         "lskum_ref_residual_norm": (ctypes.c_double, [cp, vp]),
         "lskum_ref_force_coeffs": (None, [cp, pp, vp, vp]),
         "lskum_ref_iterate": (ctypes.c_uint, [cp, pp, ctypes.c_int32, vp, vp]),
@@ -249,6 +251,16 @@ class Oracle:
                                     _ptr(Un), _ptr(R), _ptr(dt), _ptr(out))
         return out
 
+    def rk4_stage(self, stage: int, Un, Rs, dt, U):
+        """Classical RK4 stage `stage`; Rs = [R of stage 0, ..., R of stage `stage`]."""
+        Un = self._field(Un, 4)
+        Rall = np.ascontiguousarray(np.stack([self._field(R, 4) for R in Rs[:stage + 1]]))
+        dt = _f64(dt, (self.n,))
+        out = self._field(U, 4).copy()
+        self.lib.lskum_ref_rk4_stage(ctypes.byref(self._c), ctypes.byref(self._p), int(stage),
+                                     _ptr(Un), _ptr(Rall), _ptr(dt), _ptr(out))
+        return out
+
     def residual_norm(self, R):
         R = self._field(R, 4)
         return float(self.lib.lskum_ref_residual_norm(ctypes.byref(self._c), _ptr(R)))
@@ -306,11 +318,16 @@ class Oracle:
         for it in range(iters):
             dt = self.local_dt(U)
             Un = U.copy()
+            Rs = []
             for s in range(4):
                 q, f1 = self.q_vars(U)
                 dq, qlim = self.q_derivs(q)
                 R, f2 = self.flux_residual(q, dq, qlim)
+                Rs.append(R)
                 norm = self.residual_norm(R) if s == 0 else None
-                U = self.rk_stage(s, Un, R, dt, U)
+                if self.options & RK4:
+                    U = self.rk4_stage(s, Un, Rs, dt, U)
+                else:
+                    U = self.rk_stage(s, Un, R, dt, U)
                 yield dict(it=it, stage=s, q=q, dq=dq, qlim=qlim, R=R, dt=dt, U=U.copy(),
                            norm=norm, flags=f1 | f2)

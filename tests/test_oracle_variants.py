@@ -1,12 +1,12 @@
-"""Pins of the oracle's scheme options (CPU): the min-max limiter and the
+"""Pins of the oracle's scheme options (CPU): the min-max limiter, the
 first-order flux (split fluxes of q itself, the paper's first-order scheme
-before the defect correction of eq. (14))."""
+before the defect correction of eq. (14)) and classical RK4 time stepping."""
 import numpy as np
 import pytest
 
-from cloudgen.shapes import square_cloud
+from cloudgen.shapes import from_lists, square_cloud
 from oracle import ref
-from oracle.ref import FIRST_ORDER, MINMAX, Oracle
+from oracle.ref import FIRST_ORDER, MINMAX, RK4, Oracle
 
 from test_oracle_sweep import euler_divergence, prim_to_U, smooth_prims
 
@@ -79,3 +79,88 @@ def test_minmax_limiter_error_lies_between_unlimited_and_first_order():
     first-order scheme's."""
     e_mm = _mms(81, MINMAX)
     assert _mms(81, 0) < e_mm < _mms(81, FIRST_ORDER)
+
+
+def _chain(n):
+    """n interior points on a line, each linked to the next: the stage
+    updates are pointwise, so the residuals can be set directly."""
+    return from_lists(np.arange(n, dtype=float), np.zeros(n), np.zeros(n), np.ones(n), [0] * n,
+                      [[(i + 1) % n] for i in range(n)])
+
+
+def _rk4_step(o, U0, dt, rhs):
+    """One classical RK4 step through the oracle's stage routine with
+    R = rhs(U) re-evaluated at every stage input."""
+    U, Rs = U0.copy(), []
+    for s in range(4):
+        Rs.append(rhs(U))
+        U = o.rk4_stage(s, U0, Rs, dt, U)
+    return U
+
+
+def test_rk4_stages_reproduce_the_rk4_stability_polynomial():
+    """On L(U) = z U the four stages give the degree-4 Taylor polynomial of
+    exp(z) (classical RK4), not SSPRK(4,3)'s z^4/48 term."""
+    n = 5
+    o = Oracle(_chain(n), 0.5, 0.0, options=RK4)
+    z = np.array([-0.3, -1.0, -2.0, -2.7, 0.1])
+    U0 = np.ones((4, n)) * np.array([1.0, 0.5, -0.25, 3.0])[:, None]
+    U = _rk4_step(o, U0, np.ones(n), lambda V: -z[None, :] * V)
+    P = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+    np.testing.assert_allclose(U, U0 * P[None, :], rtol=1e-14, atol=1e-15)
+
+
+def test_rk4_is_fourth_order_on_a_nonlinear_ode():
+    """U' = -U^2 (R = U^2) from U(0) = u0 has U(t) = u0/(1 + u0 t): the
+    one-step error of RK4 falls 32-fold per halving of dt (local order 5),
+    that of SSPRK(4,3) 16-fold (a wrong stage weight drops the order)."""
+    n = 4
+    o = Oracle(_chain(n), 0.5, 0.0, options=RK4)
+    u0 = np.array([1.0, 0.7, 1.3, 0.4])
+    U0 = np.repeat(u0[None, :], 4, axis=0)
+    errs, errs_ssp = [], []
+    for h in (0.04, 0.02, 0.01):
+        dt = np.full(n, h)
+        exact = u0 / (1 + u0 * h)
+        errs.append(np.max(np.abs(_rk4_step(o, U0, dt, lambda V: V * V)[0] - exact)))
+        U = U0.copy()
+        for s in range(4):
+            U = o.rk_stage(s, U0, U * U, dt, U)
+        errs_ssp.append(np.max(np.abs(U[0] - exact)))
+    for e in (errs, errs_ssp):
+        assert e[0] > e[1] > e[2] > 0
+    r = [errs[0] / errs[1], errs[1] / errs[2]]
+    r_ssp = [errs_ssp[0] / errs_ssp[1], errs_ssp[1] / errs_ssp[2]]
+    assert all(27 < x < 37 for x in r), r
+    assert all(13.5 < x < 18 for x in r_ssp), r_ssp
+
+
+def test_rk4_stage_boundary_conditions(tiny_cloud):
+    c = tiny_cloud
+    o = Oracle(c, 0.63, 2.0, options=RK4)
+    rng = np.random.Generator(np.random.PCG64(16))
+    U = o.init_state() * (1 + 0.01 * rng.normal(size=(4, c.n)))
+    Rs = [rng.normal(size=(4, c.n)) for _ in range(4)]
+    dt = np.full(c.n, 1e-3)
+    wall, outer = c.kind == 1, c.kind == 2
+    for s in range(4):
+        U1 = o.rk4_stage(s, U, Rs, dt, U)
+        mn = U1[1] * c.nx + U1[2] * c.ny
+        assert np.max(np.abs(mn[wall])) < 1e-15
+        np.testing.assert_array_equal(U1[:, outer],
+                                      np.repeat(o.free_stream()[:, None], outer.sum(), 1))
+
+
+def test_rk4_iterate_matches_the_stage_composition(tiny_cloud):
+    """The oracle's whole-iteration routine with the RK4 bit is the stage
+    routine applied to each stage's residual, and differs from SSPRK(4,3)."""
+    o = Oracle(tiny_cloud, 0.63, 2.0, n_inner=1, options=RK4)
+    U0 = o.init_state()
+    U, h, flags = o.iterate(U0, 2)
+    assert flags == 0
+    st = list(o.stages(U0, 2))
+    np.testing.assert_array_equal(U, st[-1]["U"])
+    np.testing.assert_array_equal(h, [st[0]["norm"], st[4]["norm"]])
+    Us, hs, _ = Oracle(tiny_cloud, 0.63, 2.0, n_inner=1).iterate(U0, 2)
+    assert h[0] == hs[0]  # same first residual, different update
+    assert np.max(np.abs(U - Us)) > 1e-8
