@@ -40,27 +40,39 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cloud, wl, U_host, min_seconds: float = 10.0):
-    """The oracle, as it stands, on whole RK stages of the workload: repeated
-    until at least `min_seconds` of single-thread CPU work (one stage over
-    the 1M cloud takes about 4 s)."""
-    from oracle.ref import Oracle
+def cpu_baseline(cloud, wl, U_host, options: int = 0, n_inner=None, min_seconds: float = 10.0):
+    """The oracle, as it stands, on whole RK stages of the workload (same
+    scheme options and inner sweeps as the GPU run): repeated until at least
+    `min_seconds` of single-thread CPU work (one stage over the 1M cloud
+    takes about 4 s)."""
+    import numpy as np
+    from oracle.ref import FIRST_ORDER, RK4, Oracle
 
+    n_inner = wl.n_inner if n_inner is None else n_inner
     o = Oracle(cloud, wl.mach, wl.aoa_deg, cfl=wl.cfl, venkat_k=wl.venkat_k,
-               n_inner=wl.n_inner, gamma=wl.gamma)
+               n_inner=n_inner, gamma=wl.gamma, options=options)
     U = U_host.copy()
     Un = U_host.copy()
     dt = None
+    Rs = []
     stages = 0
     t0 = time.perf_counter()
     while True:
         if stages % 4 == 0:
             dt = o.local_dt(U)
             Un = U.copy()
+            Rs = []
         q, _ = o.q_vars(U)
-        dq, qlim = o.q_derivs(q)
+        if options & FIRST_ORDER:
+            dq, qlim = np.zeros((8, cloud.n)), np.zeros((8, cloud.n))
+        else:
+            dq, qlim = o.q_derivs(q)
         R, _ = o.flux_residual(q, dq, qlim)
-        U = o.rk_stage(stages % 4, Un, R, dt, U)
+        Rs.append(R)
+        if options & RK4:
+            U = o.rk4_stage(stages % 4, Un, Rs, dt, U)
+        else:
+            U = o.rk_stage(stages % 4, Un, R, dt, U)
         stages += 1
         sec = time.perf_counter() - t0
         if sec >= min_seconds:
@@ -68,9 +80,10 @@ def cpu_baseline(cloud, wl, U_host, min_seconds: float = 10.0):
     return {"value": cloud.n * stages / sec, "unit": "point-stage updates/s", "cores": 1,
             "kind": "oracle",
             "sample": f"{stages} RK stages (local time step per 4 stages, q-variables, first-order "
-                      f"+ {wl.n_inner} inner LS sweeps, flux residual, stage update) over all "
-                      f"{cloud.n} points of the {wl.name} cloud from the initial state, single "
-                      f"thread, {sec:.1f} s"}
+                      f"+ {n_inner} inner LS sweeps, flux residual, stage update) over all "
+                      f"{cloud.n} points of the {wl.name} cloud from the initial state"
+                      + (f", options {options}" if options else "")
+                      + f", single thread, {sec:.1f} s"}
 
 
 ELEMENTARY_RANGES = {
@@ -344,9 +357,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-inner", type=int, default=None,
                     help="inner least-squares sweeps (default: the workload's)")
-    ap.add_argument("--scheme", default="default", choices=("default", "first-order", "minmax"),
+    ap.add_argument("--scheme", default="default",
+                    choices=("default", "first-order", "minmax", "rk4"),
                     help="scheme variant of the sweep (default: the paper's second-order "
-                         "scheme with the Venkatakrishnan limiter)")
+                         "scheme with the Venkatakrishnan limiter and SSPRK(4,3); rk4: the "
+                         "same residual with classical RK4 stages)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of the sweep, run 5 plain device copies of this many bytes "
                          "(calibrates the HBM traffic counters)")
@@ -394,7 +409,8 @@ def main():
     torch.cuda.set_device(0)
     n = cloud.n
     edges = int(cloud.nbr_count.astype(np.int64).sum())
-    options = {"default": 0, "first-order": L.FIRST_ORDER, "minmax": L.MINMAX}[args.scheme]
+    options = {"default": 0, "first-order": L.FIRST_ORDER, "minmax": L.MINMAX,
+               "rk4": L.RK4}[args.scheme]
     n_inner = wl.n_inner if args.n_inner is None else args.n_inner
     p = L.Params(wl.mach, wl.aoa_deg, wl.cfl, wl.venkat_k, n_inner, wl.gamma, options=options)
     plan = L.Plan(cloud, p)
@@ -402,7 +418,7 @@ def main():
     L.lskum_init_state(plan, U)
     U0_host = U.cpu().numpy().T.copy()  # oracle layout (4, n)
     Un, q, dq, qlim, work, R = (plan.field(c) for c in (4, 4, 8, 8, 16, 4))
-    dt = plan.field(1)
+    dt, acc = plan.field(1), plan.field(4)
     hist = torch.zeros(max(steps + warm, 1), dtype=torch.float64, device="cuda")
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(4 * steps)]
@@ -412,7 +428,7 @@ def main():
         Un.copy_(U)
         for s in range(4):
             L.lskum_q_vars(plan, U, q)
-            if options != L.FIRST_ORDER:  # the first-order flux reads no derivatives
+            if not options & L.FIRST_ORDER:  # the first-order flux reads no derivatives
                 L.lskum_q_derivs(plan, q, dq, qlim, work)
             if timed:
                 ev[4 * (k - warm) + s][0].record()
@@ -421,7 +437,10 @@ def main():
                 ev[4 * (k - warm) + s][1].record()
             if s == 0:
                 L.lskum_residual_norm(plan, R, hist[k:k + 1])
-            L.lskum_rk_stage(plan, s, Un, R, dt, U)
+            if options & L.RK4:
+                L.lskum_rk4_stage(plan, s, Un, R, dt, acc, U)
+            else:
+                L.lskum_rk_stage(plan, s, Un, R, dt, U)
 
     log(f"[bench] n={n} edges={edges} warmup={warm} steps={steps}")
     for k in range(warm):
@@ -442,9 +461,10 @@ def main():
     flops = costs.flux_flops(n, edges)
     achieved = flops / (flux_ms * 1e-3) / 1e12
     traffic = None
-    if wl.name == "1m" and args.scheme == "default":
+    same_flux = args.scheme in ("default", "rk4")  # rk4 changes only the stage update
+    if wl.name == "1m" and same_flux:
         traffic = costs.stored_flux_traffic(os.path.join(ROOT, "profiles", "k_flux_1m.txt"))
-    if args.scheme != "default":  # the FP64 count per edge is the default scheme's
+    if not same_flux:  # the FP64 count per edge is the default scheme's
         achieved = None
     stage_gb = costs.stage_bytes(n, cloud.k_pad, n_inner) / 1e9
     out = {
@@ -479,7 +499,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on one stage")
-        out["cpu_baseline"] = cpu_baseline(cloud, wl, U0_host)
+        out["cpu_baseline"] = cpu_baseline(cloud, wl, U0_host, options, n_inner)
     print(json.dumps(out), flush=True)
     return 0 if status == L.OK and np.all(np.isfinite(h[:warm + steps])) else 1
 

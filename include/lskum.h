@@ -89,9 +89,13 @@ typedef struct {
  * lskum_iterate skips the derivative passes.  LSKUM_MINMAX: the min-max
  * limiter phi = min(1, D/delta) (reconstructed values stay within the
  * stencil bounds) instead of Venkatakrishnan's.  The adjoint entry points
- * support the default scheme only (LSKUM_ERR_INVALID_ARG otherwise). */
+ * support the default residual only (LSKUM_ERR_INVALID_ARG for either bit). */
 #define LSKUM_FIRST_ORDER 1
 #define LSKUM_MINMAX 2
+/* LSKUM_RK4: lskum_iterate advances each iteration with the classical
+ * fourth-order Runge-Kutta scheme (lskum_rk4_stage) in place of the SSP
+ * Runge-Kutta (4,3) stages; the residual and its adjoints are unchanged. */
+#define LSKUM_RK4 4
 
 /* Launch tuning of a plan: the block size (= points per LDS tile of the
  * gather kernels) and whether blocks are relabelled so that each of the 8
@@ -166,6 +170,17 @@ int lskum_local_dt(lskum_plan plan, const double *U, double *dt, void *stream);
  * free stream.  U holds the previous stage on entry. */
 int lskum_rk_stage(lskum_plan plan, int stage, const double *Un, const double *R,
                    const double *dt, double *U, void *stream);
+
+/* Stage `stage` (0..3) of the classical fourth-order Runge-Kutta scheme
+ * with L = -R and the same local time step: stages 0..2 write
+ * U = Un - c dt R with c = 1/2, 1/2, 1 and the last writes
+ * U = Un - dt/6 (R0 + 2 R1 + 2 R2 + R3), where R_s is the residual of stage
+ * s's input.  acc ([n][4], caller-owned, 32-byte aligned) carries
+ * R0 + 2 R1 + 2 R2 between the calls of one step: stage 0 overwrites it,
+ * stages 1 and 2 update it, stage 3 only reads it.  Boundary conditions as
+ * in lskum_rk_stage. */
+int lskum_rk4_stage(lskum_plan plan, int stage, const double *Un, const double *R,
+                    const double *dt, double *acc, double *U, void *stream);
 
 /* Deterministic L2 norm of the density residual over interior and wall
  * points, per cloud: out[c] (device, n_clouds doubles). */

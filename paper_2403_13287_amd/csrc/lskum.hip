@@ -672,6 +672,45 @@ __global__ void __launch_bounds__(kBlock) k_rk_stage(Geo G, Flow P, int stage,
   st4(U, i, Ui);
 }
 
+// Classical RK4 stage with L = -R: the stage inputs are Un - dt/2 R0,
+// Un - dt/2 R1, Un - dt R2 and the step ends at Un - dt/6 (R0 + 2 R1 + 2 R2 + R3).
+// acc carries the partial weighted sum of the stage residuals.
+__global__ void __launch_bounds__(kBlock) k_rk4_stage(Geo G, Flow P, int stage,
+                                                      const double *__restrict__ Un,
+                                                      const double *__restrict__ R,
+                                                      const double *__restrict__ dt,
+                                                      double *__restrict__ acc,
+                                                      double *__restrict__ U) {
+  const int n = G.n;
+  const int i = point_index<kBlock>(G.xcd);
+  if (i >= n) return;
+  const int kind = G.kind[i];
+  F4 Ui;
+  if (kind == 2) {
+    Ui = ld4(G.uinf, G.cloud[i]);
+  } else {
+    const F4 U0 = ld4(Un, i), Ri = ld4(R, i);
+    F4 A;
+    if (stage == 0) {
+      A = Ri;
+    } else {
+      A = ld4(acc, i);
+      for (int m = 0; m < 4; ++m) A.v[m] = A.v[m] + (stage == 3 ? 1.0 : 2.0) * Ri.v[m];
+    }
+    if (stage < 3) st4(acc, i, A);
+    const double h = stage < 2 ? 0.5 * dt[i] : (stage == 2 ? dt[i] : dt[i] / 6.0);
+    const F4 &D = stage < 3 ? Ri : A;
+    for (int m = 0; m < 4; ++m) Ui.v[m] = U0.v[m] - h * D.v[m];
+    if (kind == 1) {
+      const double2 nv = G.nrm[i];
+      const double mn = Ui.v[1] * nv.x + Ui.v[2] * nv.y;
+      Ui.v[1] = Ui.v[1] - mn * nv.x;
+      Ui.v[2] = Ui.v[2] - mn * nv.y;
+    }
+  }
+  st4(U, i, Ui);
+}
+
 __global__ void __launch_bounds__(kBlock) k_init_state(Geo G, double *__restrict__ U) {
   const int n = G.n;
   const int i = point_index<kBlock>(G.xcd);
@@ -935,7 +974,8 @@ bool params_ok(const lskum_params *p) {
   return p && std::isfinite(p->gamma) && p->gamma > 1.0 && std::isfinite(p->mach) &&
          p->mach >= 0.0 && std::isfinite(p->aoa_rad) && std::isfinite(p->cfl) && p->cfl > 0.0 &&
          std::isfinite(p->venkat_k) && p->venkat_k >= 0.0 && p->n_inner >= 0 &&
-         p->n_inner <= 64 && (p->options & ~(LSKUM_FIRST_ORDER | LSKUM_MINMAX)) == 0;
+         p->n_inner <= 64 &&
+         (p->options & ~(LSKUM_FIRST_ORDER | LSKUM_MINMAX | LSKUM_RK4)) == 0;
 }
 
 // every cloud valid, and the settings the kernels share equal across clouds
@@ -982,7 +1022,7 @@ void release(lskum_plan_s *p) {
   delete p;
 }
 
-constexpr size_t kNumWorkFields = 4 + 4 + 8 + 8 + 16 + 4 + 1;  // Un q dq qlim work R dt
+constexpr size_t kNumWorkFields = 4 + 4 + 8 + 8 + 16 + 4 + 1 + 4;  // Un q dq qlim work R dt acc
 
 // Validate one cloud and append it (point ids shifted by base) to the
 // concatenated host arrays.
@@ -1104,6 +1144,8 @@ int run_iterations(lskum_plan_s *p, int32_t iters, double *U, double *hist, int3
   double *work = reinterpret_cast<double *>(base + 24 * f1);
   double *R = reinterpret_cast<double *>(base + 40 * f1);
   double *dt = reinterpret_cast<double *>(base + 44 * f1);
+  double *acc = reinterpret_cast<double *>(base + 45 * f1);
+  const bool rk4 = (p->params[0].options & LSKUM_RK4) != 0;
   const Geo g = geo(p);
   const Flow f = flow(p);
   const int grid = grid_for(p->n);
@@ -1126,7 +1168,10 @@ int run_iterations(lskum_plan_s *p, int32_t iters, double *U, double *hist, int3
                            nullptr, 1, stream);
         if (rc) return rc;
       }
-      k_rk_stage<<<grid, kBlock, 0, S(stream)>>>(g, f, s, Un, R, dt, U);
+      if (rk4)
+        k_rk4_stage<<<grid, kBlock, 0, S(stream)>>>(g, f, s, Un, R, dt, acc, U);
+      else
+        k_rk_stage<<<grid, kBlock, 0, S(stream)>>>(g, f, s, Un, R, dt, U);
     }
     if (counter) k_tick<<<1, 64, 0, S(stream)>>>(counter);
   }
@@ -1345,6 +1390,15 @@ int lskum_rk_stage(lskum_plan p, int stage, const double *Un, const double *R, c
   if (!p || !a32(Un) || !a32(R) || !dt || !a32(U) || stage < 0 || stage > 3)
     return LSKUM_ERR_INVALID_ARG;
   k_rk_stage<<<grid_for(p->n), kBlock, 0, S(stream)>>>(geo(p), flow(p), stage, Un, R, dt, U);
+  return launched();
+}
+
+int lskum_rk4_stage(lskum_plan p, int stage, const double *Un, const double *R, const double *dt,
+                    double *acc, double *U, void *stream) {
+  if (!p || !a32(Un) || !a32(R) || !dt || !a32(acc) || !a32(U) || stage < 0 || stage > 3)
+    return LSKUM_ERR_INVALID_ARG;
+  k_rk4_stage<<<grid_for(p->n), kBlock, 0, S(stream)>>>(geo(p), flow(p), stage, Un, R, dt, acc,
+                                                        U);
   return launched();
 }
 

@@ -893,7 +893,8 @@ void adjoint_reset(lskum_plan_s *p) {
   } while (0)
 
 int prepare_checked(lskum_plan_s *p, void *stream) {
-  if (p->params[0].options != 0) return LSKUM_ERR_INVALID_ARG;  // default scheme only
+  if (p->params[0].options & (LSKUM_FIRST_ORDER | LSKUM_MINMAX))  // the default residual only
+    return LSKUM_ERR_INVALID_ARG;
   const int rc = adjoint_prepare(p, stream);
   if (rc) adjoint_reset(p);
   return rc;

@@ -29,6 +29,7 @@ ERR_DEGENERATE = -6
 
 FIRST_ORDER = 1  # Params.options bits
 MINMAX = 2
+RK4 = 4
 
 
 class LskumError(RuntimeError):
@@ -73,6 +74,7 @@ _SIGS = {
     "lskum_flux_residual": (ctypes.c_int, "vvvvvv"),
     "lskum_local_dt": (ctypes.c_int, "vvvv"),
     "lskum_rk_stage": (ctypes.c_int, "vivvvvv"),
+    "lskum_rk4_stage": (ctypes.c_int, "vivvvvvv"),
     "lskum_residual_norm": (ctypes.c_int, "vvvv"),
     "lskum_force_coeffs": (ctypes.c_int, "vvvv"),
     "lskum_workspace_bytes": (ctypes.c_size_t, "v"),
@@ -143,7 +145,7 @@ class Params:
     n_inner: int = 2
     gamma: float = 1.4
     aoa_rad: float | None = None  # if set, the angle in radians (aoa_deg ignored)
-    options: int = 0              # FIRST_ORDER | MINMAX bits (0: the default scheme)
+    options: int = 0              # FIRST_ORDER | MINMAX | RK4 bits (0: the default scheme)
 
     def alpha(self) -> float:
         return float(self.aoa_rad) if self.aoa_rad is not None else math.radians(self.aoa_deg)
@@ -287,6 +289,13 @@ def lskum_rk_stage(plan: Plan, stage: int, Un, R, dt, U, stream=None):
     _check(plan.lib.lskum_rk_stage(plan.handle, int(stage), plan._arg(Un, 4, "Un"),
                                    plan._arg(R, 4, "R"), plan._arg(dt, 1, "dt"),
                                    plan._arg(U, 4, "U"), _stream(stream)), "lskum_rk_stage")
+
+
+def lskum_rk4_stage(plan: Plan, stage: int, Un, R, dt, acc, U, stream=None):
+    _check(plan.lib.lskum_rk4_stage(plan.handle, int(stage), plan._arg(Un, 4, "Un"),
+                                    plan._arg(R, 4, "R"), plan._arg(dt, 1, "dt"),
+                                    plan._arg(acc, 4, "acc"), plan._arg(U, 4, "U"),
+                                    _stream(stream)), "lskum_rk4_stage")
 
 
 def _scalar_out(plan: Plan, t, count: int, name: str) -> int:

@@ -1,7 +1,8 @@
-"""Scheme options on the GPU against the oracle: the first-order flux and
-the min-max limiter, on the 9,600-point cloud at the workload's flow and on
-the supersonic case (3 iterations; fields normwise 1e-10, histories 1e-8).
-The adjoint entry points refuse them."""
+"""Scheme options on the GPU against the oracle: the first-order flux, the
+min-max limiter and classical RK4 time stepping, on the 9,600-point cloud at
+the workload's flow and on the supersonic case (3 iterations; fields
+normwise 1e-10, histories 1e-8).  The adjoint entry points refuse the two
+residual options."""
 import sys
 
 import numpy as np
@@ -9,7 +10,7 @@ import pytest
 import torch
 
 from cloudgen import named_cloud
-from oracle.ref import Oracle
+from oracle.ref import RK4, Oracle
 from paper_2403_13287_amd import lskum as L
 from paper_2403_13287_amd.solver import Solver
 
@@ -32,7 +33,8 @@ def tiny():
     return named_cloud("tiny")
 
 
-@pytest.mark.parametrize("options", [L.FIRST_ORDER, L.MINMAX, L.FIRST_ORDER | L.MINMAX])
+@pytest.mark.parametrize("options", [L.FIRST_ORDER, L.MINMAX, L.FIRST_ORDER | L.MINMAX, L.RK4,
+                                     L.RK4 | L.MINMAX])
 @pytest.mark.parametrize("mach,aoa", [(0.63, 2.0), (1.2, 0.0)])
 def test_variant_parity(tiny, options, mach, aoa):
     c = tiny
@@ -59,3 +61,71 @@ def test_adjoint_refuses_variants(tiny):
     tb = torch.empty(2, dtype=torch.float64, device="cuda")
     with pytest.raises(L.LskumError):
         L.lskum_flux_residual_vjp(plan, U, U.clone(), plan.field(4), tb, L.vjp_workspace(plan))
+
+
+def test_rk4_stage_entry_point(tiny):
+    """lskum_rk4_stage called stage by stage with arbitrary residuals (the
+    accumulator carried between calls) against the oracle's textbook
+    stages, which keep every stage residual."""
+    assert L.RK4 == RK4
+    c = tiny
+    o = Oracle(c, 0.63, 2.0, options=RK4)
+    plan = L.Plan(c, L.Params(0.63, 2.0, options=L.RK4))
+    rng = np.random.Generator(np.random.PCG64(21))
+    Un = o.init_state() * (1 + 0.01 * rng.normal(size=(4, c.n)))
+    Rs = [rng.normal(size=(4, c.n)) for _ in range(4)]
+    dt = np.full(c.n, 1e-3) * (1 + rng.random(c.n))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a.T)).cuda()  # noqa: E731
+    Ung, dtg = dev(Un), torch.from_numpy(dt).cuda()
+    Ug, acc = Ung.clone(), plan.field(4)
+    Uo = Un.copy()
+    for s in range(4):
+        L.lskum_rk4_stage(plan, s, Ung, dev(Rs[s]), dtg, acc, Ug)
+        Uo = o.rk4_stage(s, Un, Rs, dt, Uo)
+        torch.cuda.synchronize()
+        e = normwise(Ug.cpu().numpy().T, Uo)
+        say("rk4 stage", s, e)
+        assert e <= 1e-14
+
+
+def test_rk4_graph_replays(tiny):
+    """Graph-captured RK4 iterations (two replays of two) against the oracle's
+    four iterations."""
+    c = tiny
+    o = Oracle(c, 0.63, 2.0, n_inner=2, options=RK4)
+    Uo, ho, flags = o.iterate(o.init_state(), 4)
+    assert flags == 0
+    s = Solver(c, L.Params(0.63, 2.0, n_inner=2, options=L.RK4))
+    graph, hist = s.capture(2, 2)
+    for _ in range(2):
+        graph.launch()
+        torch.cuda.synchronize()
+    assert s.status() == L.OK
+    np.testing.assert_allclose(hist[:, 0].cpu().numpy(), ho, rtol=1e-8)
+    e = normwise(s.U.cpu().numpy().T, Uo)
+    say("rk4 graph: U", e)
+    assert e <= 1e-10
+
+
+def test_rk4_adjoint_accepted(tiny):
+    """RK4 changes the time stepping only: the residual VJP of an RK4 plan
+    equals that of the default plan."""
+    pa = L.Plan(tiny, L.Params(0.63, 2.0, options=L.RK4))
+    pb = L.Plan(tiny, L.Params(0.63, 2.0))
+    U = pa.field(4)
+    L.lskum_init_state(pa, U)
+    U = U * (1 + 0.01 * torch.randn(U.shape, dtype=torch.float64, device=U.device,
+                                    generator=torch.Generator(device=U.device).manual_seed(5)))
+    L.lskum_set_far_field(pa, U)
+    Rb = torch.randn(U.shape, dtype=torch.float64, device=U.device,
+                     generator=torch.Generator(device=U.device).manual_seed(6))
+    out = []
+    for p in (pa, pb):
+        Ub, tb = p.field(4), torch.empty(2, dtype=torch.float64, device=U.device)
+        L.lskum_flux_residual_vjp(p, U, Rb, Ub, tb, L.vjp_workspace(p))
+        out.append((Ub, tb))
+    torch.cuda.synchronize()
+    eU = (out[0][0] - out[1][0]).abs().max() / out[1][0].abs().max()
+    et = (out[0][1] - out[1][1]).abs().max() / out[1][1].abs().max()
+    say("rk4 vjp vs default:", float(eU), float(et))
+    assert eU <= 1e-14 and et <= 1e-14
