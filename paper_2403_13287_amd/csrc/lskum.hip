@@ -251,7 +251,58 @@ struct SlotRow {
   }
 };
 
-template <int BLK, bool ARG>
+// Point i's whole row of table slots in registers, loaded before the
+// staging barrier so that these loads overlap the staging and the gather
+// loop reads LDS only (rows of at most KMAX entries).  Entries past the
+// count hold the point's own slot; their loads re-read entry 0.
+template <int KMAX>
+struct SlotRegs {
+  int s[KMAX];
+  __device__ __forceinline__ void load(const uint16_t *col, int n, int c, int own) {
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const int sl = col[(size_t)(k < c ? k : 0) * n];
+      s[k] = k < c ? sl : own;
+    }
+  }
+};
+
+// Stage the records of tile `tile` (its BLK points, then its halo) into LDS
+// slots: every thread issues all of its loads before it stores any.  get(p)
+// loads point p's records, put(slot, rec) stores them.
+template <int BLK, class Rec, class Get, class Put>
+__device__ __forceinline__ void stage_tile(const Tiles &T, int tile, int lo, int n, Get get,
+                                           Put put) {
+  const int h0 = T.hoff[tile];
+  const int nh = T.hoff[tile + 1] - h0;
+  const int own = lo + threadIdx.x;
+  Rec r0{};
+  if (own < n) r0 = get(own);
+  for (int b = 0; b < nh; b += 2 * BLK) {
+    const int a0 = b + threadIdx.x, a1 = a0 + BLK;
+    const int p0 = a0 < nh ? T.hids[h0 + a0] : -1;
+    const int p1 = a1 < nh ? T.hids[h0 + a1] : -1;
+    Rec r1{}, r2{};
+    if (p0 >= 0) r1 = get(p0);
+    if (p1 >= 0) r2 = get(p1);
+    if (b == 0 && own < n) put(threadIdx.x, r0);
+    if (p0 >= 0) put(BLK + a0, r1);
+    if (p1 >= 0) put(BLK + a1, r2);
+  }
+  if (nh == 0 && own < n) put(threadIdx.x, r0);
+}
+
+struct XyQ {
+  double2 xy;
+  F4 q;
+};
+struct XyG {
+  double2 xy;
+  F8 g;
+};
+
+// KMAX: rows of at most KMAX entries (slots in registers), 0: any row length
+template <int BLK, bool ARG, int KMAX>
 __global__ void __launch_bounds__(BLK) k_deriv_first_t(Geo G, Tiles T,
                                                           const double *__restrict__ q,
                                                           double *__restrict__ dq,
@@ -265,17 +316,17 @@ __global__ void __launch_bounds__(BLK) k_deriv_first_t(Geo G, Tiles T,
   const int cap = BLK + T.hmax;
   double2 *s_xy = reinterpret_cast<double2 *>(smem);
   F4 *s_q = reinterpret_cast<F4 *>(smem + 16 * (size_t)cap);
-  const int h0 = T.hoff[tile];
-  const int slots = BLK + (T.hoff[tile + 1] - h0);
-  for (int sl = threadIdx.x; sl < slots; sl += BLK) {
-    const int pnt = sl < BLK ? lo + sl : T.hids[h0 + sl - BLK];
-    if (pnt < n) {
-      s_xy[sl] = G.xy[pnt];
-      s_q[sl] = ld4(q, pnt);
-    }
-  }
-  __syncthreads();
   const int i = lo + threadIdx.x;
+  const int c = i < n ? G.cnt[i] : 0;
+  SlotRegs<KMAX ? KMAX : 1> sr;
+  if (KMAX && i < n) sr.load(T.lcol + i, n, c, threadIdx.x);
+  stage_tile<BLK, XyQ>(
+      T, tile, lo, n, [&](int p) { return XyQ{G.xy[p], ld4(q, p)}; },
+      [&](int sl, const XyQ &r) {
+        s_xy[sl] = r.xy;
+        s_q[sl] = r.q;
+      });
+  __syncthreads();
   if (i >= n) return;
   const double2 xi = s_xy[threadIdx.x];
   const F4 q0 = s_q[threadIdx.x];
@@ -287,14 +338,9 @@ __global__ void __launch_bounds__(BLK) k_deriv_first_t(Geo G, Tiles T,
     amax[m] = amin[m] = -1;
   }
   double sxx = 0.0, sxy = 0.0, syy = 0.0;
-  const int c = G.cnt[i];
-  const SlotRow row{T.lcol + i, n, c, (int)threadIdx.x};
-  int s_next = row(1);
-  int s_cur = row(0);
-  for (int k = 0; k < c; ++k) {
-    const int s_after = row(k + 2);
-    const double2 xj = s_xy[s_cur];
-    const F4 qj = s_q[s_cur];
+  auto edge = [&](int k, int sl) {
+    const double2 xj = s_xy[sl];
+    const F4 qj = s_q[sl];
     const double dx = xj.x - xi.x, dy = xj.y - xi.y;
     sxx += dx * dx;
     sxy += dx * dy;
@@ -317,8 +363,21 @@ __global__ void __launch_bounds__(BLK) k_deriv_first_t(Geo G, Tiles T,
         qmin[m] = fmin(qmin[m], qj.v[m]);
       }
     }
-    s_cur = s_next;
-    s_next = s_after;
+  };
+  if (KMAX) {
+#pragma unroll
+    for (int k = 0; k < (KMAX ? KMAX : 1); ++k)
+      if (k < c) edge(k, sr.s[k]);
+  } else {
+    const SlotRow row{T.lcol + i, n, c, (int)threadIdx.x};
+    int s_next = row(1);
+    int s_cur = row(0);
+    for (int k = 0; k < c; ++k) {
+      const int s_after = row(k + 2);
+      edge(k, s_cur);
+      s_cur = s_next;
+      s_next = s_after;
+    }
   }
   const double det = sxx * syy - sxy * sxy;
   F8 g, lim;
@@ -340,7 +399,7 @@ __global__ void __launch_bounds__(BLK) k_deriv_first_t(Geo G, Tiles T,
   }
 }
 
-template <int BLK>
+template <int BLK, int KMAX>
 __global__ void __launch_bounds__(BLK) k_deriv_inner_t(Geo G, Tiles T,
                                                           const double *__restrict__ dq0,
                                                           const double *__restrict__ dqp,
@@ -353,30 +412,25 @@ __global__ void __launch_bounds__(BLK) k_deriv_inner_t(Geo G, Tiles T,
   const int cap = BLK + T.hmax;
   double2 *s_xy = reinterpret_cast<double2 *>(smem);
   F8 *s_g = reinterpret_cast<F8 *>(smem + 16 * (size_t)cap);
-  const int h0 = T.hoff[tile];
-  const int slots = BLK + (T.hoff[tile + 1] - h0);
-  for (int sl = threadIdx.x; sl < slots; sl += BLK) {
-    const int pnt = sl < BLK ? lo + sl : T.hids[h0 + sl - BLK];
-    if (pnt < n) {
-      s_xy[sl] = G.xy[pnt];
-      s_g[sl] = ld8(dqp, pnt);
-    }
-  }
-  __syncthreads();
   const int i = lo + threadIdx.x;
+  const int c = i < n ? G.cnt[i] : 0;
+  SlotRegs<KMAX ? KMAX : 1> sr;
+  if (KMAX && i < n) sr.load(T.lcol + i, n, c, threadIdx.x);
+  stage_tile<BLK, XyG>(
+      T, tile, lo, n, [&](int p) { return XyG{G.xy[p], ld8(dqp, p)}; },
+      [&](int sl, const XyG &r) {
+        s_xy[sl] = r.xy;
+        s_g[sl] = r.g;
+      });
+  __syncthreads();
   if (i >= n) return;
   const double2 xi = s_xy[threadIdx.x];
   const F8 g0 = s_g[threadIdx.x];
   double ax[4] = {0, 0, 0, 0}, ay[4] = {0, 0, 0, 0};
   double sxx = 0.0, sxy = 0.0, syy = 0.0;
-  const int c = G.cnt[i];
-  const SlotRow row{T.lcol + i, n, c, (int)threadIdx.x};
-  int s_next = row(1);
-  int s_cur = row(0);
-  for (int k = 0; k < c; ++k) {
-    const int s_after = row(k + 2);
-    const double2 xj = s_xy[s_cur];
-    const F8 gj = s_g[s_cur];
+  auto edge = [&](int sl) {
+    const double2 xj = s_xy[sl];
+    const F8 gj = s_g[sl];
     const double dx = xj.x - xi.x, dy = xj.y - xi.y;
     sxx += dx * dx;
     sxy += dx * dy;
@@ -386,8 +440,21 @@ __global__ void __launch_bounds__(BLK) k_deriv_inner_t(Geo G, Tiles T,
       ax[m] += dx * t;
       ay[m] += dy * t;
     }
-    s_cur = s_next;
-    s_next = s_after;
+  };
+  if (KMAX) {
+#pragma unroll
+    for (int k = 0; k < (KMAX ? KMAX : 1); ++k)
+      if (k < c) edge(sr.s[k]);
+  } else {
+    const SlotRow row{T.lcol + i, n, c, (int)threadIdx.x};
+    int s_next = row(1);
+    int s_cur = row(0);
+    for (int k = 0; k < c; ++k) {
+      const int s_after = row(k + 2);
+      edge(s_cur);
+      s_cur = s_next;
+      s_next = s_after;
+    }
   }
   const double det = sxx * syy - sxy * sxy;
   const F8 d0 = ld8(dq0, i);
@@ -906,6 +973,13 @@ int q_vars_launch(lskum_plan_s *p, const double *U, double *q, void *stream) {
   return launched();
 }
 
+// tiled derivative launches: slot rows in registers for rows of <= 32 entries
+#define LSKUM_DERIV_T(kern, blk, kmax_ok, ...)                                        \
+  do {                                                                                \
+    if (kmax_ok) kern<__VA_ARGS__, 32><<<gr, blk, lds, st>>>(g, t, ARGS_);            \
+    else kern<__VA_ARGS__, 0><<<gr, blk, lds, st>>>(g, t, ARGS_);                     \
+  } while (0)
+
 int deriv_first_launch(lskum_plan_s *p, const double *q, double *dq, double *qlim,
                        int8_t *argext, void *stream) {
   const Geo g = geo(p);
@@ -915,20 +989,23 @@ int deriv_first_launch(lskum_plan_s *p, const double *q, double *dq, double *qli
   const size_t lds = (size_t)(p->block + m.hmax) * 48;
   if (m.blk == p->block && lds <= kTileLdsBytes) {
     const Tiles t = tiles(m);
+    const bool k32 = p->k_pad <= 32;
+#define ARGS_ q, dq, qlim, argext
     switch (p->block) {
       case 128:
-        if (argext) k_deriv_first_t<128, true><<<gr, 128, lds, st>>>(g, t, q, dq, qlim, argext);
-        else k_deriv_first_t<128, false><<<gr, 128, lds, st>>>(g, t, q, dq, qlim, nullptr);
+        if (argext) LSKUM_DERIV_T(k_deriv_first_t, 128, k32, 128, true);
+        else LSKUM_DERIV_T(k_deriv_first_t, 128, k32, 128, false);
         break;
       case 512:
-        if (argext) k_deriv_first_t<512, true><<<gr, 512, lds, st>>>(g, t, q, dq, qlim, argext);
-        else k_deriv_first_t<512, false><<<gr, 512, lds, st>>>(g, t, q, dq, qlim, nullptr);
+        if (argext) LSKUM_DERIV_T(k_deriv_first_t, 512, k32, 512, true);
+        else LSKUM_DERIV_T(k_deriv_first_t, 512, k32, 512, false);
         break;
       default:
-        if (argext) k_deriv_first_t<256, true><<<gr, 256, lds, st>>>(g, t, q, dq, qlim, argext);
-        else k_deriv_first_t<256, false><<<gr, 256, lds, st>>>(g, t, q, dq, qlim, nullptr);
+        if (argext) LSKUM_DERIV_T(k_deriv_first_t, 256, k32, 256, true);
+        else LSKUM_DERIV_T(k_deriv_first_t, 256, k32, 256, false);
         break;
     }
+#undef ARGS_
     return launched();
   }
   switch (p->block) {
@@ -955,11 +1032,16 @@ int deriv_inner_launch(lskum_plan_s *p, const double *dq0, const double *dqp, do
   if (m.blk == p->block && lds <= kTileLdsBytes) {
     const int gr = grid_for(p->n, p->block);
     const Tiles t = tiles(m);
+    const Geo g = geo(p);
+    hipStream_t st = S(stream);
+    const bool k32 = p->k_pad <= 32;
+#define ARGS_ dq0, dqp, dqn
     switch (p->block) {
-      case 128: k_deriv_inner_t<128><<<gr, 128, lds, S(stream)>>>(geo(p), t, dq0, dqp, dqn); break;
-      case 512: k_deriv_inner_t<512><<<gr, 512, lds, S(stream)>>>(geo(p), t, dq0, dqp, dqn); break;
-      default: k_deriv_inner_t<256><<<gr, 256, lds, S(stream)>>>(geo(p), t, dq0, dqp, dqn); break;
+      case 128: LSKUM_DERIV_T(k_deriv_inner_t, 128, k32, 128); break;
+      case 512: LSKUM_DERIV_T(k_deriv_inner_t, 512, k32, 512); break;
+      default: LSKUM_DERIV_T(k_deriv_inner_t, 256, k32, 256); break;
     }
+#undef ARGS_
     return launched();
   }
   LSKUM_TILED(k_deriv_inner, p, stream, geo(p), dq0, dqp, dqn);
