@@ -707,6 +707,62 @@ __global__ void __launch_bounds__(kBlock) k_local_dt(Geo G, Flow P, const double
   dt[i] = P.cfl * best;
 }
 
+// Local time step on LDS tables: each staged slot carries 1/speed^2 of its
+// point, so an edge costs |d|^2 / speed_j^2 and one square root per point
+// ends the minimum: dt_i = CFL sqrt(min_j |d_ij|^2 / speed_j^2).
+struct XyW {
+  double2 xy;
+  double w;
+};
+
+template <int BLK, int KMAX>
+__global__ void __launch_bounds__(BLK) k_local_dt_t(Geo G, Flow P, Tiles T,
+                                                       const double *__restrict__ U,
+                                                       double *__restrict__ dt) {
+  extern __shared__ __align__(64) unsigned char smem[];
+  const int n = G.n;
+  const int tile = block_id(G.xcd);
+  const int lo = tile * BLK;
+  if (lo >= n) return;
+  const int cap = BLK + T.hmax;
+  double2 *s_xy = reinterpret_cast<double2 *>(smem);
+  double *s_w = reinterpret_cast<double *>(smem + 16 * (size_t)cap);
+  const int i = lo + threadIdx.x;
+  const int c = i < n ? G.cnt[i] : 0;
+  SlotRegs<KMAX ? KMAX : 1> sr;
+  if (KMAX && i < n) sr.load(T.lcol + i, n, c, threadIdx.x);
+  stage_tile<BLK, XyW>(
+      T, tile, lo, n,
+      [&](int p) {
+        double rho, u, v, pr;
+        prim_from_cons(P.gamma, ld4(U, p), rho, u, v, pr);
+        const double speed = sqrt(u * u + v * v) + 3.0 * sqrt(pr / rho);
+        return XyW{G.xy[p], 1.0 / (speed * speed)};
+      },
+      [&](int sl, const XyW &r) {
+        s_xy[sl] = r.xy;
+        s_w[sl] = r.w;
+      });
+  __syncthreads();
+  if (i >= n) return;
+  const double2 xi = s_xy[threadIdx.x];
+  double best = INFINITY;
+  auto edge = [&](int sl) {
+    const double2 xj = s_xy[sl];
+    const double dx = xj.x - xi.x, dy = xj.y - xi.y;
+    best = fmin(best, (dx * dx + dy * dy) * s_w[sl]);
+  };
+  if (KMAX) {
+#pragma unroll
+    for (int k = 0; k < (KMAX ? KMAX : 1); ++k)
+      if (k < c) edge(sr.s[k]);
+  } else {
+    const SlotRow row{T.lcol + i, n, c, (int)threadIdx.x};
+    for (int k = 0; k < c; ++k) edge(row(k));
+  }
+  dt[i] = P.cfl * sqrt(best);
+}
+
 __global__ void __launch_bounds__(kBlock) k_rk_stage(Geo G, Flow P, int stage,
                                                      const double *__restrict__ Un,
                                                      const double *__restrict__ R,
@@ -1048,6 +1104,33 @@ int deriv_inner_launch(lskum_plan_s *p, const double *dq0, const double *dqp, do
   return launched();
 }
 
+int local_dt_launch(lskum_plan_s *p, const double *U, double *dt, void *stream) {
+  const TileMap &m = p->maps[tile_index(p->block)];
+  const size_t lds = (size_t)(p->block + m.hmax) * 24;
+  const Geo g = geo(p);
+  const Flow f = flow(p);
+  hipStream_t st = S(stream);
+  if (m.blk == p->block && lds <= kTileLdsBytes) {
+    const int gr = grid_for(p->n, p->block);
+    const Tiles t = tiles(m);
+    const bool k32 = p->k_pad <= 32;
+#define LSKUM_DT_T(blk)                                                                  \
+  do {                                                                                   \
+    if (k32) k_local_dt_t<blk, 32><<<gr, blk, lds, st>>>(g, f, t, U, dt);                \
+    else k_local_dt_t<blk, 0><<<gr, blk, lds, st>>>(g, f, t, U, dt);                     \
+  } while (0)
+    switch (p->block) {
+      case 128: LSKUM_DT_T(128); break;
+      case 512: LSKUM_DT_T(512); break;
+      default: LSKUM_DT_T(256); break;
+    }
+#undef LSKUM_DT_T
+    return launched();
+  }
+  k_local_dt<<<grid_for(p->n), kBlock, 0, st>>>(g, f, U, dt);
+  return launched();
+}
+
 }  // namespace lskum_impl
 
 namespace {
@@ -1234,7 +1317,7 @@ int run_iterations(lskum_plan_s *p, int32_t iters, double *U, double *hist, int3
   const int copy_grid = grid_for((int)std::min<size_t>(4 * n, (size_t)1 << 24));
   int rc;
   for (int32_t it = 0; it < iters; ++it) {
-    k_local_dt<<<grid, kBlock, 0, S(stream)>>>(g, f, U, dt);
+    if ((rc = local_dt_launch(p, U, dt, stream))) return rc;
     k_copy<<<copy_grid, kBlock, 0, S(stream)>>>(4 * n, U, Un);
     for (int s = 0; s < 4; ++s) {
       if ((rc = q_vars_launch(p, U, q, stream))) return rc;
@@ -1463,8 +1546,7 @@ int lskum_flux_residual(lskum_plan p, const double *q, const double *dq, const d
 
 int lskum_local_dt(lskum_plan p, const double *U, double *dt, void *stream) {
   if (!p || !a32(U) || !dt) return LSKUM_ERR_INVALID_ARG;
-  k_local_dt<<<grid_for(p->n), kBlock, 0, S(stream)>>>(geo(p), flow(p), U, dt);
-  return launched();
+  return local_dt_launch(p, U, dt, stream);
 }
 
 int lskum_rk_stage(lskum_plan p, int stage, const double *Un, const double *R, const double *dt,
