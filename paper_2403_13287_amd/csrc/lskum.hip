@@ -314,8 +314,14 @@ __global__ void __launch_bounds__(BLK) k_deriv_first_t(Geo G, Tiles T,
   const int lo = tile * BLK;
   if (lo >= n) return;  // blocks past the last tile (the grid is a multiple of 8)
   const int cap = BLK + T.hmax;
+  // 16-byte planes (coordinates, q0 q1, q2 q3): random-slot reads spread
+  // over all LDS banks, where whole 32-byte records would share few
   double2 *s_xy = reinterpret_cast<double2 *>(smem);
-  F4 *s_q = reinterpret_cast<F4 *>(smem + 16 * (size_t)cap);
+  double2 *s_q = s_xy + cap;
+  auto rd_q = [&](int sl) {
+    const double2 a = s_q[sl], b = s_q[cap + sl];
+    return F4{{a.x, a.y, b.x, b.y}};
+  };
   const int i = lo + threadIdx.x;
   const int c = i < n ? G.cnt[i] : 0;
   SlotRegs<KMAX ? KMAX : 1> sr;
@@ -324,12 +330,13 @@ __global__ void __launch_bounds__(BLK) k_deriv_first_t(Geo G, Tiles T,
       T, tile, lo, n, [&](int p) { return XyQ{G.xy[p], ld4(q, p)}; },
       [&](int sl, const XyQ &r) {
         s_xy[sl] = r.xy;
-        s_q[sl] = r.q;
+        s_q[sl] = make_double2(r.q.v[0], r.q.v[1]);
+        s_q[cap + sl] = make_double2(r.q.v[2], r.q.v[3]);
       });
   __syncthreads();
   if (i >= n) return;
   const double2 xi = s_xy[threadIdx.x];
-  const F4 q0 = s_q[threadIdx.x];
+  const F4 q0 = rd_q(threadIdx.x);
   double qmax[4], qmin[4], sxq[4], syq[4];
   int amax[4], amin[4];
   for (int m = 0; m < 4; ++m) {
@@ -340,7 +347,7 @@ __global__ void __launch_bounds__(BLK) k_deriv_first_t(Geo G, Tiles T,
   double sxx = 0.0, sxy = 0.0, syy = 0.0;
   auto edge = [&](int k, int sl) {
     const double2 xj = s_xy[sl];
-    const F4 qj = s_q[sl];
+    const F4 qj = rd_q(sl);
     const double dx = xj.x - xi.x, dy = xj.y - xi.y;
     sxx += dx * dx;
     sxy += dx * dy;
@@ -410,8 +417,18 @@ __global__ void __launch_bounds__(BLK) k_deriv_inner_t(Geo G, Tiles T,
   const int lo = tile * BLK;
   if (lo >= n) return;
   const int cap = BLK + T.hmax;
+  // 16-byte planes (coordinates, then the derivative record in four pairs)
   double2 *s_xy = reinterpret_cast<double2 *>(smem);
-  F8 *s_g = reinterpret_cast<F8 *>(smem + 16 * (size_t)cap);
+  double2 *s_g = s_xy + cap;
+  auto rd_g = [&](int sl) {
+    F8 g;
+    for (int h = 0; h < 4; ++h) {
+      const double2 a = s_g[h * cap + sl];
+      g.v[2 * h] = a.x;
+      g.v[2 * h + 1] = a.y;
+    }
+    return g;
+  };
   const int i = lo + threadIdx.x;
   const int c = i < n ? G.cnt[i] : 0;
   SlotRegs<KMAX ? KMAX : 1> sr;
@@ -420,17 +437,17 @@ __global__ void __launch_bounds__(BLK) k_deriv_inner_t(Geo G, Tiles T,
       T, tile, lo, n, [&](int p) { return XyG{G.xy[p], ld8(dqp, p)}; },
       [&](int sl, const XyG &r) {
         s_xy[sl] = r.xy;
-        s_g[sl] = r.g;
+        for (int h = 0; h < 4; ++h) s_g[h * cap + sl] = make_double2(r.g.v[2 * h], r.g.v[2 * h + 1]);
       });
   __syncthreads();
   if (i >= n) return;
   const double2 xi = s_xy[threadIdx.x];
-  const F8 g0 = s_g[threadIdx.x];
+  const F8 g0 = rd_g(threadIdx.x);
   double ax[4] = {0, 0, 0, 0}, ay[4] = {0, 0, 0, 0};
   double sxx = 0.0, sxy = 0.0, syy = 0.0;
   auto edge = [&](int sl) {
     const double2 xj = s_xy[sl];
-    const F8 gj = s_g[sl];
+    const F8 gj = rd_g(sl);
     const double dx = xj.x - xi.x, dy = xj.y - xi.y;
     sxx += dx * dx;
     sxy += dx * dy;
@@ -534,11 +551,26 @@ __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__res
                                                  const double *__restrict__ dq,
                                                  const double *__restrict__ qlim,
                                                  double *__restrict__ R, unsigned *status) {
+  // the tile's records as 16-byte planes: q in 2, dq, qlim and the split
+  // weights in 4 each (whole records would put lanes on few LDS banks)
   __shared__ double2 s_xy[BLK];
-  __shared__ F4 s_q[BLK];
-  __shared__ F8 s_g[BLK];
-  __shared__ F8 s_l[BLK];
-  __shared__ F8 s_w[BLK];
+  __shared__ double2 s_q[2][BLK];
+  __shared__ double2 s_g[4][BLK];
+  __shared__ double2 s_l[4][BLK];
+  __shared__ double2 s_w[4][BLK];
+  auto rd4 = [](const double2 (*pl)[BLK], int sl) {
+    const double2 a = pl[0][sl], b = pl[1][sl];
+    return F4{{a.x, a.y, b.x, b.y}};
+  };
+  auto rd8 = [](const double2 (*pl)[BLK], int sl) {
+    F8 r;
+    for (int h = 0; h < 4; ++h) {
+      const double2 a = pl[h][sl];
+      r.v[2 * h] = a.x;
+      r.v[2 * h + 1] = a.y;
+    }
+    return r;
+  };
   const int n = G.n;
   const int lo = tile_lo<BLK>(G.xcd);
   const int i = lo + threadIdx.x;
@@ -554,11 +586,14 @@ __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__res
       l0 = ld8(qlim, i);
       w0 = ld8(spw, i);
     }
-    s_xy[threadIdx.x] = xi;
-    s_q[threadIdx.x] = q0;
-    s_g[threadIdx.x] = g0;
-    s_l[threadIdx.x] = l0;
-    s_w[threadIdx.x] = w0;
+    const int t = threadIdx.x;
+    s_xy[t] = xi;
+    for (int h = 0; h < 2; ++h) s_q[h][t] = make_double2(q0.v[2 * h], q0.v[2 * h + 1]);
+    for (int h = 0; h < 4; ++h) {
+      s_g[h][t] = make_double2(g0.v[2 * h], g0.v[2 * h + 1]);
+      s_l[h][t] = make_double2(l0.v[2 * h], l0.v[2 * h + 1]);
+      s_w[h][t] = make_double2(w0.v[2 * h], w0.v[2 * h + 1]);
+    }
   }
   __syncthreads();
   if (!active) return;
@@ -577,7 +612,7 @@ __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__res
     int lj;
     return in_tile<BLK>(j, lo, lj) ? s_xy[lj] : G.xy[j];
   };
-  unsigned f = degenerate_splits(s_w[threadIdx.x], interior);
+  unsigned f = degenerate_splits(rd8(s_w, threadIdx.x), interior);
   const double K = P.venkat_k;
   double acc[4] = {0, 0, 0, 0};  // (mass, s-momentum, n-momentum, energy)
 
@@ -593,9 +628,9 @@ __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__res
     F4 qj;
     F8 gj, lj8;
     if (in_tile<BLK>(j_cur, lo, lj)) {
-      qj = s_q[lj];
-      gj = s_g[lj];
-      lj8 = s_l[lj];
+      qj = rd4(s_q, lj);
+      gj = rd8(s_g, lj);
+      lj8 = rd8(s_l, lj);
     } else {
       qj = ld4(q, j_cur);
       gj = ld8(dq, j_cur);
@@ -609,8 +644,8 @@ __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__res
     {
       // keeps the compiler from hoisting the own-record reads out of the loop
       asm volatile("" ::: "memory");
-      const F4 q0 = s_q[threadIdx.x];
-      const F8 g0 = s_g[threadIdx.x], l0 = s_l[threadIdx.x];
+      const F4 q0 = rd4(s_q, threadIdx.x);
+      const F8 g0 = rd8(s_g, threadIdx.x), l0 = rd8(s_l, threadIdx.x);
       for (int m = 0; m < 4; ++m) {
         if (VAR == 1) {
           qtj[m] = qj.v[m];
@@ -631,7 +666,7 @@ __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__res
     EndState sj, s0;
     f |= end_state(qtj, P, tx, ty, nx, ny, sj);
     f |= end_state(qt0, P, tx, ty, nx, ny, s0);
-    const F8 W = s_w[threadIdx.x];
+    const F8 W = rd8(s_w, threadIdx.x);
 
     // s-direction split: ds < 0 -> G_s^+, ds > 0 -> G_s^-
     {
