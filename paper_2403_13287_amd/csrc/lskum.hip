@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(BLK) k_deriv_first(Geo G, const double *__rest
                                                         double *__restrict__ qlim,
                                                         int8_t *__restrict__ argext) {
   __shared__ double2 s_xy[BLK];
-  __shared__ F4 s_q[BLK];
+  __shared__ double2 s_q[2][BLK];  // 16-byte planes
   const int n = G.n;
   const int lo = tile_lo<BLK>(G.xcd);
   const int i = lo + threadIdx.x;
@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(BLK) k_deriv_first(Geo G, const double *__rest
     q0 = ld4(q, i);
   }
   s_xy[threadIdx.x] = xi;
-  s_q[threadIdx.x] = q0;
+  pl_wr4<BLK>(s_q, threadIdx.x, q0);
   __syncthreads();
   if (!active) return;
   double qmax[4], qmin[4], sxq[4], syq[4];
@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(BLK) k_deriv_first(Geo G, const double *__rest
     int lj;
     if (in_tile<BLK>(j, lo, lj)) {
       xj = s_xy[lj];
-      qj = s_q[lj];
+      qj = pl_rd4<BLK>(s_q, lj);
     } else {
       xj = G.xy[j];
       qj = ld4(q, j);
@@ -168,7 +168,7 @@ __global__ void __launch_bounds__(BLK) k_deriv_inner(Geo G, const double *__rest
                                                         const double *__restrict__ dqp,
                                                         double *__restrict__ dqn) {
   __shared__ double2 s_xy[BLK];
-  __shared__ F8 s_g[BLK];
+  __shared__ double2 s_g[4][BLK];  // 16-byte planes
   const int n = G.n;
   const int lo = tile_lo<BLK>(G.xcd);
   const int i = lo + threadIdx.x;
@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(BLK) k_deriv_inner(Geo G, const double *__rest
     g0 = ld8(dqp, i);
   }
   s_xy[threadIdx.x] = xi;
-  s_g[threadIdx.x] = g0;
+  pl_wr8<BLK>(s_g, threadIdx.x, g0);
   __syncthreads();
   if (!active) return;
   double ax[4] = {0, 0, 0, 0}, ay[4] = {0, 0, 0, 0};
@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(BLK) k_deriv_inner(Geo G, const double *__rest
     int lj;
     if (in_tile<BLK>(j, lo, lj)) {
       xj = s_xy[lj];
-      gj = s_g[lj];
+      gj = pl_rd8<BLK>(s_g, lj);
     } else {
       xj = G.xy[j];
       gj = ld8(dqp, j);
@@ -558,19 +558,8 @@ __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__res
   __shared__ double2 s_g[4][BLK];
   __shared__ double2 s_l[4][BLK];
   __shared__ double2 s_w[4][BLK];
-  auto rd4 = [](const double2 (*pl)[BLK], int sl) {
-    const double2 a = pl[0][sl], b = pl[1][sl];
-    return F4{{a.x, a.y, b.x, b.y}};
-  };
-  auto rd8 = [](const double2 (*pl)[BLK], int sl) {
-    F8 r;
-    for (int h = 0; h < 4; ++h) {
-      const double2 a = pl[h][sl];
-      r.v[2 * h] = a.x;
-      r.v[2 * h + 1] = a.y;
-    }
-    return r;
-  };
+  const auto rd4 = pl_rd4<BLK>;
+  const auto rd8 = pl_rd8<BLK>;
   const int n = G.n;
   const int lo = tile_lo<BLK>(G.xcd);
   const int i = lo + threadIdx.x;
@@ -588,12 +577,10 @@ __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__res
     }
     const int t = threadIdx.x;
     s_xy[t] = xi;
-    for (int h = 0; h < 2; ++h) s_q[h][t] = make_double2(q0.v[2 * h], q0.v[2 * h + 1]);
-    for (int h = 0; h < 4; ++h) {
-      s_g[h][t] = make_double2(g0.v[2 * h], g0.v[2 * h + 1]);
-      s_l[h][t] = make_double2(l0.v[2 * h], l0.v[2 * h + 1]);
-      s_w[h][t] = make_double2(w0.v[2 * h], w0.v[2 * h + 1]);
-    }
+    pl_wr4<BLK>(s_q, t, q0);
+    pl_wr8<BLK>(s_g, t, g0);
+    pl_wr8<BLK>(s_l, t, l0);
+    pl_wr8<BLK>(s_w, t, w0);
   }
   __syncthreads();
   if (!active) return;

@@ -240,9 +240,9 @@ k_flux_rev_own(Geo G, Flow P, const double *__restrict__ spw, const double *__re
                const double *__restrict__ Rb, double *__restrict__ qbar,
                double *__restrict__ gbar, double *__restrict__ lbar, unsigned *status) {
   __shared__ double2 s_xy[BLK];
-  __shared__ F4 s_q[BLK];
-  __shared__ F8 s_g[BLK];
-  __shared__ F8 s_l[BLK];
+  __shared__ double2 s_q[2][BLK];  // 16-byte planes
+  __shared__ double2 s_g[4][BLK];
+  __shared__ double2 s_l[4][BLK];
   const int n = G.n;
   const int lo = tile_lo<BLK>(G.xcd);
   const int i = lo + threadIdx.x;
@@ -258,9 +258,9 @@ k_flux_rev_own(Geo G, Flow P, const double *__restrict__ spw, const double *__re
       l0 = ld8(qlim, i);
     }
     s_xy[threadIdx.x] = xi;
-    s_q[threadIdx.x] = q0;
-    s_g[threadIdx.x] = g0;
-    s_l[threadIdx.x] = l0;
+    pl_wr4<BLK>(s_q, threadIdx.x, q0);
+    pl_wr8<BLK>(s_g, threadIdx.x, g0);
+    pl_wr8<BLK>(s_l, threadIdx.x, l0);
   }
   __syncthreads();
   if (!active) return;
@@ -293,8 +293,8 @@ k_flux_rev_own(Geo G, Flow P, const double *__restrict__ spw, const double *__re
       const EdgeSeed e = edge_seed(dx, dy, tx, ty, nx, ny, interior, W, ab, -1.0);
       // keeps the compiler from hoisting the own-record reads out of the loop
       asm volatile("" ::: "memory");
-      const F4 q0 = s_q[threadIdx.x];
-      const F8 g0 = s_g[threadIdx.x], l0 = s_l[threadIdx.x];
+      const F4 q0 = pl_rd4<BLK>(s_q, threadIdx.x);
+      const F8 g0 = pl_rd8<BLK>(s_g, threadIdx.x), l0 = pl_rd8<BLK>(s_l, threadIdx.x);
       f |= end_reverse(P, q0, g0, l0, dx, dy, edge_eps2(K, dx, dy), tx, ty, nx, ny, e, qb, gb, lb);
       xj = xn;
       j_next = j_after;
@@ -342,11 +342,11 @@ k_flux_gather(Geo G, Flow P, const int32_t *__restrict__ in_cnt,
               double *__restrict__ sbar, double *__restrict__ lbar) {
   __shared__ double2 s_xy[BLK];
   __shared__ double2 s_nrm[BLK];
-  __shared__ F8 s_w[BLK];
-  __shared__ F4 s_rb[BLK];
-  __shared__ F4 s_q[BLK];
-  __shared__ F8 s_g[BLK];
-  __shared__ F8 s_l[BLK];
+  __shared__ double2 s_w[4][BLK];  // 16-byte planes
+  __shared__ double2 s_rb[2][BLK];
+  __shared__ double2 s_q[2][BLK];
+  __shared__ double2 s_g[4][BLK];
+  __shared__ double2 s_l[4][BLK];
   __shared__ int8_t s_kind[BLK];
   const int n = G.n;
   const int lo = tile_lo<BLK>(G.xcd);
@@ -369,11 +369,11 @@ k_flux_gather(Geo G, Flow P, const int32_t *__restrict__ in_cnt,
     }
     s_xy[threadIdx.x] = x;
     s_nrm[threadIdx.x] = nv;
-    s_w[threadIdx.x] = w;
-    s_rb[threadIdx.x] = r;
-    s_q[threadIdx.x] = qq;
-    s_g[threadIdx.x] = g;
-    s_l[threadIdx.x] = l;
+    pl_wr8<BLK>(s_w, threadIdx.x, w);
+    pl_wr4<BLK>(s_rb, threadIdx.x, r);
+    pl_wr4<BLK>(s_q, threadIdx.x, qq);
+    pl_wr8<BLK>(s_g, threadIdx.x, g);
+    pl_wr8<BLK>(s_l, threadIdx.x, l);
     s_kind[threadIdx.x] = kd;
   }
   __syncthreads();
@@ -398,8 +398,8 @@ k_flux_gather(Geo G, Flow P, const int32_t *__restrict__ in_cnt,
       ki = s_kind[li];
       xi = s_xy[li];
       nv = s_nrm[li];
-      W = s_w[li];
-      rb = s_rb[li];
+      W = pl_rd8<BLK>(s_w, li);
+      rb = pl_rd4<BLK>(s_rb, li);
     } else {
       ki = G.kind[i];
       xi = G.xy[i];
@@ -415,8 +415,8 @@ k_flux_gather(Geo G, Flow P, const int32_t *__restrict__ in_cnt,
     const double dx = xj.x - xi.x, dy = xj.y - xi.y;
     const EdgeSeed es = edge_seed(dx, dy, tx, ty, nx, ny, ki == 0, W, ab, 1.0);
     asm volatile("" ::: "memory");
-    const F4 qj = s_q[threadIdx.x];
-    const F8 gj = s_g[threadIdx.x], lj = s_l[threadIdx.x];
+    const F4 qj = pl_rd4<BLK>(s_q, threadIdx.x);
+    const F8 gj = pl_rd8<BLK>(s_g, threadIdx.x), lj = pl_rd8<BLK>(s_l, threadIdx.x);
     end_reverse(P, qj, gj, lj, dx, dy, edge_eps2(K, dx, dy), tx, ty, nx, ny, es, qb, gb, lb);
   }
   const F4 qo = ld4(qbar, j);
@@ -454,7 +454,7 @@ __global__ void __launch_bounds__(BLK) k_inner_rev(Geo G, const int32_t *__restr
                                                       double *__restrict__ qbar,
                                                       double *__restrict__ s_out) {
   __shared__ double2 s_xy[BLK];
-  __shared__ F8 s_s[BLK];
+  __shared__ double2 s_s[4][BLK];  // 16-byte planes
   const int n = G.n;
   const int lo = tile_lo<BLK>(G.xcd);
   const int j = lo + threadIdx.x;
@@ -466,14 +466,14 @@ __global__ void __launch_bounds__(BLK) k_inner_rev(Geo G, const int32_t *__restr
     sj = ld8(s_in, j);
   }
   s_xy[threadIdx.x] = xj;
-  s_s[threadIdx.x] = sj;
+  pl_wr8<BLK>(s_s, threadIdx.x, sj);
   __syncthreads();
   if (!active) return;
   auto fetch = [&](int i, double2 &x, F8 &sv) {
     int li;
     if (in_tile<BLK>(i, lo, li)) {
       x = s_xy[li];
-      sv = s_s[li];
+      sv = pl_rd8<BLK>(s_s, li);
     } else {
       x = G.xy[i];
       sv = ld8(s_in, i);
@@ -528,7 +528,7 @@ __global__ void __launch_bounds__(BLK) k_first_rev(Geo G, Flow P,
                                                       const double *__restrict__ qbar,
                                                       double *__restrict__ Ubar) {
   __shared__ double2 s_xy[BLK];
-  __shared__ F8 s_s[BLK];
+  __shared__ double2 s_s[4][BLK];  // 16-byte planes
   __shared__ uint64_t s_a[BLK];
   const uint64_t *arg = reinterpret_cast<const uint64_t *>(argext);
   const int n = G.n;
@@ -544,7 +544,7 @@ __global__ void __launch_bounds__(BLK) k_first_rev(Geo G, Flow P,
     aj = arg[j];
   }
   s_xy[threadIdx.x] = xj;
-  s_s[threadIdx.x] = sj;
+  pl_wr8<BLK>(s_s, threadIdx.x, sj);
   s_a[threadIdx.x] = aj;
   __syncthreads();
   if (!active) return;
@@ -562,7 +562,7 @@ __global__ void __launch_bounds__(BLK) k_first_rev(Geo G, Flow P,
     int li;
     if (in_tile<BLK>(i, lo, li)) {
       x = s_xy[li];
-      sv = s_s[li];
+      sv = pl_rd8<BLK>(s_s, li);
       a = s_a[li];
     } else {
       x = G.xy[i];

@@ -68,6 +68,34 @@ __device__ __forceinline__ void st4_at(double *f, size_t i, const F4 &v) {
   reinterpret_cast<F4 *>(f)[i] = v;
 }
 
+// A tile's records in LDS as 16-byte planes: plane h holds doubles 2h and
+// 2h+1 of every slot.  A wave reading 16 bytes per lane at consecutive or
+// random slots then spreads over all LDS banks; whole 32- or 64-byte
+// records would put its lanes on a quarter or an eighth of them.
+template <int BLK>
+__device__ __forceinline__ F4 pl_rd4(const double2 (*pl)[BLK], int sl) {
+  const double2 a = pl[0][sl], b = pl[1][sl];
+  return F4{{a.x, a.y, b.x, b.y}};
+}
+template <int BLK>
+__device__ __forceinline__ F8 pl_rd8(const double2 (*pl)[BLK], int sl) {
+  F8 r;
+  for (int h = 0; h < 4; ++h) {
+    const double2 a = pl[h][sl];
+    r.v[2 * h] = a.x;
+    r.v[2 * h + 1] = a.y;
+  }
+  return r;
+}
+template <int BLK>
+__device__ __forceinline__ void pl_wr4(double2 (*pl)[BLK], int sl, const F4 &v) {
+  for (int h = 0; h < 2; ++h) pl[h][sl] = make_double2(v.v[2 * h], v.v[2 * h + 1]);
+}
+template <int BLK>
+__device__ __forceinline__ void pl_wr8(double2 (*pl)[BLK], int sl, const F8 &v) {
+  for (int h = 0; h < 4; ++h) pl[h][sl] = make_double2(v.v[2 * h], v.v[2 * h + 1]);
+}
+
 // ---------------------------------------------------------------------------
 // launch helpers
 
