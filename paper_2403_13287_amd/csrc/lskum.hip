@@ -251,56 +251,6 @@ struct SlotRow {
   }
 };
 
-// Point i's whole row of table slots in registers, loaded before the
-// staging barrier so that these loads overlap the staging and the gather
-// loop reads LDS only (rows of at most KMAX entries).  Entries past the
-// count hold the point's own slot; their loads re-read entry 0.
-template <int KMAX>
-struct SlotRegs {
-  int s[KMAX];
-  __device__ __forceinline__ void load(const uint16_t *col, int n, int c, int own) {
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-      const int sl = col[(size_t)(k < c ? k : 0) * n];
-      s[k] = k < c ? sl : own;
-    }
-  }
-};
-
-// Stage the records of tile `tile` (its BLK points, then its halo) into LDS
-// slots: every thread issues all of its loads before it stores any.  get(p)
-// loads point p's records, put(slot, rec) stores them.
-template <int BLK, class Rec, class Get, class Put>
-__device__ __forceinline__ void stage_tile(const Tiles &T, int tile, int lo, int n, Get get,
-                                           Put put) {
-  const int h0 = T.hoff[tile];
-  const int nh = T.hoff[tile + 1] - h0;
-  const int own = lo + threadIdx.x;
-  Rec r0{};
-  if (own < n) r0 = get(own);
-  for (int b = 0; b < nh; b += 2 * BLK) {
-    const int a0 = b + threadIdx.x, a1 = a0 + BLK;
-    const int p0 = a0 < nh ? T.hids[h0 + a0] : -1;
-    const int p1 = a1 < nh ? T.hids[h0 + a1] : -1;
-    Rec r1{}, r2{};
-    if (p0 >= 0) r1 = get(p0);
-    if (p1 >= 0) r2 = get(p1);
-    if (b == 0 && own < n) put(threadIdx.x, r0);
-    if (p0 >= 0) put(BLK + a0, r1);
-    if (p1 >= 0) put(BLK + a1, r2);
-  }
-  if (nh == 0 && own < n) put(threadIdx.x, r0);
-}
-
-struct XyQ {
-  double2 xy;
-  F4 q;
-};
-struct XyG {
-  double2 xy;
-  F8 g;
-};
-
 // KMAX: rows of at most KMAX entries (slots in registers), 0: any row length
 template <int BLK, bool ARG, int KMAX>
 __global__ void __launch_bounds__(BLK) k_deriv_first_t(Geo G, Tiles T,
@@ -977,29 +927,23 @@ struct lskum_graph_s {
 
 namespace lskum_impl {
 
-namespace {
-
-// Tile map of tile size blk from the host connectivity (column-major, pads =
-// own id): per tile, the sorted out-of-tile neighbour ids, and every row
-// entry's slot in the tile's table (own points 0..blk-1, halo after).
-int build_tile_map(lskum_plan_s *p, int blk, const int32_t *nbr, const int32_t *cnt) {
-  TileMap &m = p->maps[tile_index(blk)];
-  if (m.blk == blk) return LSKUM_OK;
-  const int32_t n = p->n, kp = p->k_pad;
+int tile_slots(int32_t n, int32_t width, int blk, const int32_t *ids, const int32_t *cnt,
+               std::vector<int32_t> &slots, std::vector<int32_t> &hoff,
+               std::vector<int32_t> &hids, int &hmax) {
   const int32_t nt = (n + blk - 1) / blk;
-  std::vector<uint16_t> lcol;
-  std::vector<int32_t> hoff, hids, ext;
-  int hmax = 0;
+  std::vector<int32_t> ext;
+  hmax = 0;
   try {
-    lcol.resize((size_t)kp * n);
+    slots.resize((size_t)width * n);
     hoff.assign((size_t)nt + 1, 0);
+    hids.clear();
     hids.reserve((size_t)n);
     for (int32_t t = 0; t < nt; ++t) {
       const int32_t lo = t * blk, hi = std::min(n, lo + blk);
       ext.clear();
       for (int32_t i = lo; i < hi; ++i)
         for (int32_t s = 0; s < cnt[i]; ++s) {
-          const int32_t j = nbr[(size_t)s * n + i];
+          const int32_t j = ids[(size_t)s * n + i];
           if (j < lo || j >= hi) ext.push_back(j);
         }
       std::sort(ext.begin(), ext.end());
@@ -1009,19 +953,37 @@ int build_tile_map(lskum_plan_s *p, int blk, const int32_t *nbr, const int32_t *
       hoff[(size_t)t + 1] = hoff[(size_t)t] + (int32_t)ext.size();
       hids.insert(hids.end(), ext.begin(), ext.end());
       for (int32_t i = lo; i < hi; ++i)
-        for (int32_t s = 0; s < kp; ++s) {
-          const int32_t j = nbr[(size_t)s * n + i];
-          const int32_t sl = (j >= lo && j < hi)
-                                 ? j - lo
-                                 : blk + (int32_t)(std::lower_bound(ext.begin(), ext.end(), j) -
-                                                   ext.begin());
-          lcol[(size_t)s * n + i] = (uint16_t)sl;
+        for (int32_t s = 0; s < width; ++s) {
+          const int32_t j = s < cnt[i] ? ids[(size_t)s * n + i] : i;
+          slots[(size_t)s * n + i] =
+              (j >= lo && j < hi)
+                  ? j - lo
+                  : blk + (int32_t)(std::lower_bound(ext.begin(), ext.end(), j) - ext.begin());
         }
     }
   } catch (const std::bad_alloc &) {
     return LSKUM_ERR_NO_MEMORY;
   }
-  int rc;
+  return LSKUM_OK;
+}
+
+namespace {
+
+// Tile map of tile size blk from the host connectivity (column-major, pads =
+// own id): every row entry's LDS slot as uint16, and each tile's halo.
+int build_tile_map(lskum_plan_s *p, int blk, const int32_t *nbr, const int32_t *cnt) {
+  TileMap &m = p->maps[tile_index(blk)];
+  if (m.blk == blk) return LSKUM_OK;
+  std::vector<int32_t> slots, hoff, hids;
+  std::vector<uint16_t> lcol;
+  int hmax = 0;
+  int rc = tile_slots(p->n, p->k_pad, blk, nbr, cnt, slots, hoff, hids, hmax);
+  if (rc) return rc;
+  try {
+    lcol.assign(slots.begin(), slots.end());
+  } catch (const std::bad_alloc &) {
+    return LSKUM_ERR_NO_MEMORY;
+  }
   if ((rc = upload(&m.lcol, lcol.data(), lcol.size())) ||
       (rc = upload(&m.hoff, hoff.data(), hoff.size())) ||
       (rc = upload(&m.hids, hids.data(), hids.size())))

@@ -446,6 +446,25 @@ k_flux_gather(Geo G, Flow P, const int32_t *__restrict__ in_cnt,
 //   gbar_prev_i += M_i s_i / 2 = gbar_i / 2    (inner sweeps)
 // so the next seed is s_prev_j = s_j/2 - M_j^-1 sum_i d_ij (d_ij . s_i) / 2.
 
+// Point j's part of an inner-sweep reverse, from its in-edge sums
+// aq = sum d.s_i, (ax, ay) = sum d (d.s_i) and its own seed sj.
+__device__ __forceinline__ void inner_rev_tail(int j, const F8 &sj, const double aq[4],
+                                               const double ax[4], const double ay[4],
+                                               const double *__restrict__ lsg,
+                                               double *__restrict__ qbar,
+                                               double *__restrict__ s_out) {
+  const F8 L = ld8(lsg, j);
+  F4 qb = ld4(qbar, j);
+  F8 so;
+  for (int m = 0; m < 4; ++m) {
+    qb.v[m] += aq[m] - (L.v[3] * sj.v[m] + L.v[4] * sj.v[4 + m]);
+    so.v[m] = 0.5 * sj.v[m] - 0.5 * (L.v[0] * ax[m] + L.v[1] * ay[m]);
+    so.v[4 + m] = 0.5 * sj.v[4 + m] - 0.5 * (L.v[1] * ax[m] + L.v[2] * ay[m]);
+  }
+  st4(qbar, j, qb);
+  st8(s_out, j, so);
+}
+
 template <int BLK>
 __global__ void __launch_bounds__(BLK) k_inner_rev(Geo G, const int32_t *__restrict__ in_cnt,
                                                       const int32_t *__restrict__ in_ent,
@@ -502,16 +521,38 @@ __global__ void __launch_bounds__(BLK) k_inner_rev(Geo G, const int32_t *__restr
     si = sn;
     ent_next = ent_after;
   }
+  inner_rev_tail(j, sj, aq, ax, ay, lsg, qbar, s_out);
+}
+
+// Point j's part of the first-order reverse and of eq. (13) reverse, from
+// the accumulated q cotangent qb (in-edges and bounds) and its own seed sj:
+// writes the cotangent of U_j.
+__device__ __forceinline__ void first_rev_tail(const Flow &P, int j, const F8 &sj, double qb[4],
+                                               const double *__restrict__ lsg,
+                                               const double *__restrict__ U,
+                                               double *__restrict__ Ubar) {
   const F8 L = ld8(lsg, j);
-  F4 qb = ld4(qbar, j);
-  F8 so;
-  for (int m = 0; m < 4; ++m) {
-    qb.v[m] += aq[m] - (L.v[3] * sj.v[m] + L.v[4] * sj.v[4 + m]);
-    so.v[m] = 0.5 * sj.v[m] - 0.5 * (L.v[0] * ax[m] + L.v[1] * ay[m]);
-    so.v[4 + m] = 0.5 * sj.v[4 + m] - 0.5 * (L.v[1] * ax[m] + L.v[2] * ay[m]);
-  }
-  st4(qbar, j, qb);
-  st8(s_out, j, so);
+  for (int m = 0; m < 4; ++m) qb[m] -= L.v[3] * sj.v[m] + L.v[4] * sj.v[4 + m];
+
+  // eq. (13) reverse: q = (ln rho + a ln beta - beta uu, 2 beta u, 2 beta v,
+  // -2 beta), beta = rho/(2p), p = (gamma-1)(E - rho uu/2)
+  const double g = P.gamma, a = P.inv_gm1;
+  double rho, u, v, p;
+  prim_from_cons(g, ld4(U, j), rho, u, v, p);
+  const double beta = 0.5 * rho / p;
+  const double uu = u * u + v * v;
+  const double betab = qb[0] * (a / beta - uu) + 2.0 * u * qb[1] + 2.0 * v * qb[2] - 2.0 * qb[3];
+  const double rhob = qb[0] / rho + betab / (2.0 * p);
+  const double pb = -betab * beta / p;
+  const double ub = -2.0 * beta * u * qb[0] + 2.0 * beta * qb[1];
+  const double vb = -2.0 * beta * v * qb[0] + 2.0 * beta * qb[2];
+  const double gm1 = g - 1.0;
+  F4 o;
+  o.v[0] = rhob + pb * gm1 * 0.5 * uu - (ub * u + vb * v) / rho;
+  o.v[1] = ub / rho - pb * gm1 * u;
+  o.v[2] = vb / rho - pb * gm1 * v;
+  o.v[3] = pb * gm1;
+  st4(Ubar, j, o);
 }
 
 // First-order pass, reverse, then eq. (13) reverse: the cotangent of U.
@@ -602,28 +643,176 @@ __global__ void __launch_bounds__(BLK) k_first_rev(Geo G, Flow P,
     ent = ent_next;
     ent_next = ent_after;
   }
-  const F8 L = ld8(lsg, j);
-  for (int m = 0; m < 4; ++m) qb[m] -= L.v[3] * sj.v[m] + L.v[4] * sj.v[4 + m];
+  first_rev_tail(P, j, sj, qb, lsg, U, Ubar);
+}
 
-  // eq. (13) reverse: q = (ln rho + a ln beta - beta uu, 2 beta u, 2 beta v,
-  // -2 beta), beta = rho/(2p), p = (gamma-1)(E - rho uu/2)
-  const double g = P.gamma, a = P.inv_gm1;
-  double rho, u, v, p;
-  prim_from_cons(g, ld4(U, j), rho, u, v, p);
-  const double beta = 0.5 * rho / p;
-  const double uu = u * u + v * v;
-  const double betab = qb[0] * (a / beta - uu) + 2.0 * u * qb[1] + 2.0 * v * qb[2] - 2.0 * qb[3];
-  const double rhob = qb[0] / rho + betab / (2.0 * p);
-  const double pb = -betab * beta / p;
-  const double ub = -2.0 * beta * u * qb[0] + 2.0 * beta * qb[1];
-  const double vb = -2.0 * beta * v * qb[0] + 2.0 * beta * qb[2];
-  const double gm1 = g - 1.0;
-  F4 o;
-  o.v[0] = rhob + pb * gm1 * 0.5 * uu - (ub * u + vb * v) / rho;
-  o.v[1] = ub / rho - pb * gm1 * u;
-  o.v[2] = vb / rho - pb * gm1 * v;
-  o.v[3] = pb * gm1;
-  st4(Ubar, j, o);
+// The two reverse gathers above on tile tables of the in-edge rows: the
+// coordinates and seeds (and bound slots) of a tile's points and of the
+// sources outside it are staged in LDS as 16-byte planes, and each point's
+// in-edge entries are held in registers (rows of at most KMAX entries; 0:
+// any length, entries read as the loop goes).  Same arithmetic in the same
+// order as k_inner_rev and k_first_rev.
+struct XyS {
+  double2 xy;
+  F8 s;
+};
+struct XySA {  // plain members: a 64-byte aligned F8 member kept this record on the stack
+  double2 xy;
+  double s[8];
+  uint64_t a;
+};
+
+template <int BLK, int KMAX>
+__global__ void __launch_bounds__(BLK) k_inner_rev_t(Geo G, Tiles T,
+                                                        const uint32_t *__restrict__ lent,
+                                                        const int32_t *__restrict__ in_cnt,
+                                                        const double *__restrict__ lsg,
+                                                        const double *__restrict__ s_in,
+                                                        double *__restrict__ qbar,
+                                                        double *__restrict__ s_out) {
+  extern __shared__ __align__(64) unsigned char smem[];
+  const int n = G.n;
+  const int tile = block_id(G.xcd);
+  const int lo = tile * BLK;
+  if (lo >= n) return;
+  const int cap = BLK + T.hmax;
+  double2 *s_xy = reinterpret_cast<double2 *>(smem);
+  double2 *s_s = s_xy + cap;  // 4 planes
+  auto rd_s = [&](int sl) {
+    F8 r;
+    for (int h = 0; h < 4; ++h) {
+      const double2 v = s_s[h * cap + sl];
+      r.v[2 * h] = v.x;
+      r.v[2 * h + 1] = v.y;
+    }
+    return r;
+  };
+  const int j = lo + threadIdx.x;
+  const int c = j < n ? in_cnt[j] : 0;
+  SlotRegs<KMAX ? KMAX : 1, uint32_t> sr;
+  if (KMAX && j < n) sr.load(lent + j, n, c, threadIdx.x);
+  stage_tile<BLK, XyS>(
+      T, tile, lo, n, [&](int p) { return XyS{G.xy[p], ld8(s_in, p)}; },
+      [&](int sl, const XyS &r) {
+        s_xy[sl] = r.xy;
+        for (int h = 0; h < 4; ++h) s_s[h * cap + sl] = make_double2(r.s.v[2 * h], r.s.v[2 * h + 1]);
+      });
+  __syncthreads();
+  if (j >= n) return;
+  const double2 xj = s_xy[threadIdx.x];
+  const F8 sj = rd_s(threadIdx.x);
+  double aq[4] = {0, 0, 0, 0}, ax[4] = {0, 0, 0, 0}, ay[4] = {0, 0, 0, 0};
+  auto edge = [&](uint32_t ent) {
+    const int sl = (int)(ent & 0xffffu);
+    const double2 xi = s_xy[sl];
+    const F8 si = rd_s(sl);
+    const double dx = xj.x - xi.x, dy = xj.y - xi.y;
+    for (int m = 0; m < 4; ++m) {
+      const double t = dx * si.v[m] + dy * si.v[4 + m];
+      aq[m] += t;
+      ax[m] += dx * t;
+      ay[m] += dy * t;
+    }
+  };
+  if (KMAX) {
+#pragma unroll
+    for (int e = 0; e < (KMAX ? KMAX : 1); ++e)
+      if (e < c) edge((uint32_t)sr.s[e]);
+  } else {
+    for (int e = 0; e < c; ++e) edge(lent[(size_t)e * n + j]);
+  }
+  inner_rev_tail(j, sj, aq, ax, ay, lsg, qbar, s_out);
+}
+
+template <int BLK, int KMAX>
+__global__ void __launch_bounds__(BLK) k_first_rev_t(Geo G, Flow P, Tiles T,
+                                                        const uint32_t *__restrict__ lent,
+                                                        const int32_t *__restrict__ in_cnt,
+                                                        const double *__restrict__ lsg,
+                                                        const double *__restrict__ s0,
+                                                        const int8_t *__restrict__ argext,
+                                                        const double *__restrict__ lbar,
+                                                        const double *__restrict__ U,
+                                                        const double *__restrict__ qbar,
+                                                        double *__restrict__ Ubar) {
+  extern __shared__ __align__(64) unsigned char smem[];
+  const uint64_t *arg = reinterpret_cast<const uint64_t *>(argext);
+  const int n = G.n;
+  const int tile = block_id(G.xcd);
+  const int lo = tile * BLK;
+  if (lo >= n) return;
+  const int cap = BLK + T.hmax;
+  double2 *s_xy = reinterpret_cast<double2 *>(smem);
+  double2 *s_s = s_xy + cap;                                // 4 planes
+  uint64_t *s_a = reinterpret_cast<uint64_t *>(s_s + 4 * cap);
+  auto rd_s = [&](int sl) {
+    F8 r;
+    for (int h = 0; h < 4; ++h) {
+      const double2 v = s_s[h * cap + sl];
+      r.v[2 * h] = v.x;
+      r.v[2 * h + 1] = v.y;
+    }
+    return r;
+  };
+  const int j = lo + threadIdx.x;
+  const int c = j < n ? in_cnt[j] : 0;
+  SlotRegs<KMAX ? KMAX : 1, uint32_t> sr;
+  if (KMAX && j < n) sr.load(lent + j, n, c, threadIdx.x);
+  stage_tile<BLK, XySA>(
+      T, tile, lo, n,
+      [&](int p) {
+        const F8 s = ld8(s0, p);
+        return XySA{G.xy[p], {s.v[0], s.v[1], s.v[2], s.v[3], s.v[4], s.v[5], s.v[6], s.v[7]},
+                    arg[p]};
+      },
+      [&](int sl, const XySA &r) {
+        s_xy[sl] = r.xy;
+        for (int h = 0; h < 4; ++h) s_s[h * cap + sl] = make_double2(r.s[2 * h], r.s[2 * h + 1]);
+        s_a[sl] = r.a;
+      });
+  __syncthreads();
+  if (j >= n) return;
+  const double2 xj = s_xy[threadIdx.x];
+  const F8 sj = rd_s(threadIdx.x);
+  const uint64_t aj = s_a[threadIdx.x];
+  double qb[4];
+  {
+    const F4 o = ld4(qbar, j);
+    const F8 lo8 = ld8(lbar, j);
+    for (int m = 0; m < 4; ++m) {
+      qb[m] = o.v[m];
+      if ((int8_t)(aj >> (8 * m)) == -1) qb[m] += lo8.v[m];
+      if ((int8_t)(aj >> (8 * (4 + m))) == -1) qb[m] += lo8.v[4 + m];
+    }
+  }
+  const int h0 = T.hoff[tile];
+  auto edge = [&](uint32_t ent) {
+    const int sl = (int)(ent & 0xffffu);
+    const int slot = (int)(ent >> 16);
+    const double2 xi = s_xy[sl];
+    const F8 si = rd_s(sl);
+    const uint64_t ai = s_a[sl];
+    const double dx = xj.x - xi.x, dy = xj.y - xi.y;
+    for (int m = 0; m < 4; ++m) qb[m] += dx * si.v[m] + dy * si.v[4 + m];
+    bool hit = false;
+    for (int h = 0; h < 8; ++h) hit |= (int8_t)(ai >> (8 * h)) == slot;
+    if (hit) {
+      const int i = sl < BLK ? lo + sl : T.hids[h0 + sl - BLK];
+      const F8 li8 = ld8(lbar, i);
+      for (int m = 0; m < 4; ++m) {
+        if ((int8_t)(ai >> (8 * m)) == slot) qb[m] += li8.v[m];
+        if ((int8_t)(ai >> (8 * (4 + m))) == slot) qb[m] += li8.v[4 + m];
+      }
+    }
+  };
+  if (KMAX) {
+#pragma unroll
+    for (int e = 0; e < (KMAX ? KMAX : 1); ++e)
+      if (e < c) edge((uint32_t)sr.s[e]);
+  } else {
+    for (int e = 0; e < c; ++e) edge(lent[(size_t)e * n + j]);
+  }
+  first_rev_tail(P, j, sj, qb, lsg, U, Ubar);
 }
 
 // theta cotangent of cloud c (block c): the outer rows hold U_inf(M, alpha);
@@ -875,11 +1064,57 @@ int adjoint_prepare(lskum_plan_s *p, void *stream) {
 
 // free whatever a failed preparation left
 void adjoint_reset(lskum_plan_s *p) {
-  void *bufs[] = {p->in_cnt, p->in_ent, p->lsg, p->outer, p->ooff};
+  void *bufs[] = {p->in_cnt, p->in_ent, p->lsg, p->outer, p->ooff,
+                  p->in_map.lent, p->in_map.hoff, p->in_map.hids};
   for (void *b : bufs) (void)hipFree(b);
   p->in_cnt = p->in_ent = p->outer = p->ooff = nullptr;
   p->lsg = nullptr;
+  p->in_map = InTileMap{};
   p->adj_ready = false;
+}
+
+// Tile tables of the in-edge rows for the plan's tile size (synchronous;
+// rebuilt when the tile size changes).
+int ensure_in_tiles(lskum_plan_s *p, void *stream) {
+  InTileMap &m = p->in_map;
+  if (m.blk == p->block) return LSKUM_OK;
+  (void)hipFree(m.lent);
+  (void)hipFree(m.hoff);
+  (void)hipFree(m.hids);
+  m = InTileMap{};
+  if (hipStreamSynchronize(S(stream)) != hipSuccess) return LSKUM_ERR_HIP;
+  const int32_t n = p->n, ki = p->k_in;
+  std::vector<int32_t> ent, cnt, ids, slots, hoff, hids;
+  std::vector<uint32_t> lent;
+  int hmax = 0, rc;
+  if ((rc = download(ent, p->in_ent, (size_t)ki * n)) || (rc = download(cnt, p->in_cnt, (size_t)n)))
+    return rc;
+  try {
+    ids.resize(ent.size());
+    for (size_t e = 0; e < ent.size(); ++e) ids[e] = ent[e] & kPointMask;
+  } catch (const std::bad_alloc &) {
+    return LSKUM_ERR_NO_MEMORY;
+  }
+  if ((rc = tile_slots(n, ki, p->block, ids.data(), cnt.data(), slots, hoff, hids, hmax)))
+    return rc;
+  try {
+    lent.resize(slots.size());
+    for (int32_t e = 0; e < ki; ++e)
+      for (int32_t j = 0; j < n; ++j) {
+        const size_t x = (size_t)e * n + j;
+        const uint32_t row_slot = e < cnt[(size_t)j] ? (uint32_t)(ent[x] >> kSlotShift) : 0u;
+        lent[x] = (uint32_t)slots[x] | (row_slot << 16);
+      }
+  } catch (const std::bad_alloc &) {
+    return LSKUM_ERR_NO_MEMORY;
+  }
+  if ((rc = upload(&m.lent, lent.data(), lent.size())) ||
+      (rc = upload(&m.hoff, hoff.data(), hoff.size())) ||
+      (rc = upload(&m.hids, hids.data(), hids.size())))
+    return rc;
+  m.hmax = (hmax + 3) / 4 * 4;
+  m.blk = p->block;
+  return LSKUM_OK;
 }
 
 #define LSKUM_TILED_ADJ(kern, p, stream, ...)                                                \
@@ -895,7 +1130,8 @@ void adjoint_reset(lskum_plan_s *p) {
 int prepare_checked(lskum_plan_s *p, void *stream) {
   if (p->params[0].options & (LSKUM_FIRST_ORDER | LSKUM_MINMAX))  // the default residual only
     return LSKUM_ERR_INVALID_ARG;
-  const int rc = adjoint_prepare(p, stream);
+  int rc = adjoint_prepare(p, stream);
+  if (!rc) rc = ensure_in_tiles(p, stream);
   if (rc) adjoint_reset(p);
   return rc;
 }
@@ -928,15 +1164,49 @@ int reverse_passes(lskum_plan_s *p, const VjpWs &w, const double *U, const doubl
                   w.lbar, p->status);
   LSKUM_TILED_ADJ(k_flux_gather, p, stream, g, f, p->in_cnt, p->in_ent, p->lsg, p->spw, w.q, dqK,
                   w.qlim, Rbar, w.qbar, w.sa, w.lbar);
+  // the derivative reverses on the in-edge tile tables when a block's
+  // table fits the LDS budget
+  const InTileMap &m = p->in_map;
+  const Tiles t{nullptr, m.hoff, m.hids, m.hmax};
+  const size_t cap = (size_t)p->block + m.hmax;
+  const bool tiled = m.blk == p->block && cap * 88 <= kTileLdsBytes;
+  const bool k48 = p->k_in <= 48;
+  const int gr = grid_for(p->n, p->block);
+  hipStream_t st = S(stream);
+#define LSKUM_REV_T(kern, lds, ...)                                                      \
+  do {                                                                                   \
+    switch (p->block) {                                                                  \
+      case 128:                                                                          \
+        if (k48) kern<128, 48><<<gr, 128, lds, st>>>(__VA_ARGS__);                       \
+        else kern<128, 0><<<gr, 128, lds, st>>>(__VA_ARGS__);                            \
+        break;                                                                           \
+      case 512:                                                                          \
+        if (k48) kern<512, 48><<<gr, 512, lds, st>>>(__VA_ARGS__);                       \
+        else kern<512, 0><<<gr, 512, lds, st>>>(__VA_ARGS__);                            \
+        break;                                                                           \
+      default:                                                                           \
+        if (k48) kern<256, 48><<<gr, 256, lds, st>>>(__VA_ARGS__);                       \
+        else kern<256, 0><<<gr, 256, lds, st>>>(__VA_ARGS__);                            \
+        break;                                                                           \
+    }                                                                                    \
+  } while (0)
   double *cur = w.sa, *nxt = w.sb;
   for (int k = K; k >= 1; --k) {
-    LSKUM_TILED_ADJ(k_inner_rev, p, stream, g, p->in_cnt, p->in_ent, p->lsg, cur, w.qbar, nxt);
-    double *t = cur;
+    if (tiled)
+      LSKUM_REV_T(k_inner_rev_t, cap * 80, g, t, m.lent, p->in_cnt, p->lsg, cur, w.qbar, nxt);
+    else
+      LSKUM_TILED_ADJ(k_inner_rev, p, stream, g, p->in_cnt, p->in_ent, p->lsg, cur, w.qbar, nxt);
+    double *tmp = cur;
     cur = nxt;
-    nxt = t;
+    nxt = tmp;
   }
-  LSKUM_TILED_ADJ(k_first_rev, p, stream, g, f, p->in_cnt, p->in_ent, p->lsg, cur, w.argext,
-                  w.lbar, U, w.qbar, Ubar);
+  if (tiled)
+    LSKUM_REV_T(k_first_rev_t, cap * 88, g, f, t, m.lent, p->in_cnt, p->lsg, cur, w.argext,
+                w.lbar, U, w.qbar, Ubar);
+  else
+    LSKUM_TILED_ADJ(k_first_rev, p, stream, g, f, p->in_cnt, p->in_ent, p->lsg, cur, w.argext,
+                    w.lbar, U, w.qbar, Ubar);
+#undef LSKUM_REV_T
   return launched();
 }
 

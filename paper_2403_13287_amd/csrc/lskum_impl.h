@@ -328,6 +328,18 @@ struct TileMap {
   int32_t *hids = nullptr;    // halo point ids, ascending within a tile
 };
 
+// Tile tables of the in-edge rows (the rows that list each point), for the
+// adjoint's transposed gathers: lent [k_in][n] holds, per in-edge entry,
+// the source's LDS slot (low 16 bits) and the slot at which the source's
+// row lists the point (bits 16 and up).
+struct InTileMap {
+  int blk = 0;
+  int hmax = 0;
+  uint32_t *lent = nullptr;
+  int32_t *hoff = nullptr;
+  int32_t *hids = nullptr;
+};
+
 // kernel view of a TileMap
 struct Tiles {
   const uint16_t *lcol;
@@ -365,6 +377,7 @@ struct lskum_plan_s {
   int32_t k_in = 0;               // padded in-edge row width (largest in-degree)
   int32_t *in_cnt = nullptr;      // [n] in-edges of each point
   int32_t *in_ent = nullptr;      // [k_in][n] (slot << kSlotShift) | source point
+  lskum_impl::InTileMap in_map;   // tile tables of the in-edge rows (plan's tile size)
   double *spw = nullptr;          // [n][8] half-plane least-squares weights (with the plan)
   double *lsg = nullptr;          // [n][8] least-squares geometry of each point
   int32_t *outer = nullptr;       // outer points, grouped by cloud
@@ -424,6 +437,56 @@ inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
     }                                                                                        \
   } while (0)
 
+// Point i's whole row of table slots in registers, loaded before the
+// staging barrier so that these loads overlap the staging and the gather
+// loop reads LDS only (rows of at most KMAX entries).  Entries past the
+// count hold the point's own slot; their loads re-read entry 0.
+template <int KMAX, class E = uint16_t>
+struct SlotRegs {
+  int s[KMAX];
+  __device__ __forceinline__ void load(const E *col, int n, int c, int own) {
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const int sl = col[(size_t)(k < c ? k : 0) * n];
+      s[k] = k < c ? sl : own;
+    }
+  }
+};
+
+// Stage the records of tile `tile` (its BLK points, then its halo) into LDS
+// slots: every thread issues all of its loads before it stores any.  get(p)
+// loads point p's records, put(slot, rec) stores them.
+template <int BLK, class Rec, class Get, class Put>
+__device__ __forceinline__ void stage_tile(const Tiles &T, int tile, int lo, int n, Get get,
+                                           Put put) {
+  const int h0 = T.hoff[tile];
+  const int nh = T.hoff[tile + 1] - h0;
+  const int own = lo + threadIdx.x;
+  Rec r0{};
+  if (own < n) r0 = get(own);
+  for (int b = 0; b < nh; b += 2 * BLK) {
+    const int a0 = b + threadIdx.x, a1 = a0 + BLK;
+    const int p0 = a0 < nh ? T.hids[h0 + a0] : -1;
+    const int p1 = a1 < nh ? T.hids[h0 + a1] : -1;
+    Rec r1{}, r2{};
+    if (p0 >= 0) r1 = get(p0);
+    if (p1 >= 0) r2 = get(p1);
+    if (b == 0 && own < n) put(threadIdx.x, r0);
+    if (p0 >= 0) put(BLK + a0, r1);
+    if (p1 >= 0) put(BLK + a1, r2);
+  }
+  if (nh == 0 && own < n) put(threadIdx.x, r0);
+}
+
+struct XyQ {
+  double2 xy;
+  F4 q;
+};
+struct XyG {
+  double2 xy;
+  F8 g;
+};
+
 // tile maps: index of a tile size in lskum_plan_s::maps, kernel view, and
 // the LDS budget of one block's table (two blocks per CU)
 inline int tile_index(int blk) { return blk == 128 ? 0 : (blk == 512 ? 2 : 1); }
@@ -431,6 +494,14 @@ inline Tiles tiles(const TileMap &m) { return Tiles{m.lcol, m.hoff, m.hids, m.hm
 constexpr size_t kTileLdsBytes = 80 * 1024;
 // builds the tile map of the plan's current tile size if missing (synchronous)
 int ensure_tile_map(lskum_plan_s *p);
+// LDS slots of rows of point ids (column-major [width][n]; row i's entries
+// past cnt[i] stand for i itself) on tiles of blk consecutive points: a
+// tile's own points take slots 0..blk-1, the out-of-tile points its rows
+// name (its halo, ascending in hids[hoff[t] .. hoff[t+1])) slots blk + k.
+// LSKUM_ERR_INVALID_ARG when a tile needs more than 65535 slots.
+int tile_slots(int32_t n, int32_t width, int blk, const int32_t *ids, const int32_t *cnt,
+               std::vector<int32_t> &slots, std::vector<int32_t> &hoff,
+               std::vector<int32_t> &hids, int &hmax);
 
 // launchers of the forward kernels (lskum.hip), reused by the adjoint
 int q_vars_launch(lskum_plan_s *p, const double *U, double *q, void *stream);
