@@ -252,3 +252,29 @@ def test_batch_vjp_equals_single_clouds():
         torch.cuda.synchronize()
         assert torch.equal(Ub[sl], u1) and torch.equal(tb[2 * k:2 * k + 2], t1), k
         assert torch.equal(Fb[sl], f1) and torch.equal(fb[2 * k:2 * k + 2], g1), k
+
+
+@pytest.mark.parametrize("block", [128, 256])
+def test_residual_vjp_without_hilbert_order(block):
+    """An airfoil cloud left in its O-grid (layer-by-layer) order: the tile
+    tables of the in-edge rows fit the LDS budget with 128-point tiles (76 KB
+    for the first-order reverse) but not with 256-point tiles (111 KB), where
+    the transposed derivative gathers take their direct-gather path (as do
+    the forward passes of the recompute).  Both must match the oracle."""
+    c = make_airfoil_cloud(200, 40, 25, 21, reorder=False)
+    o = Oracle(c, 0.6, 2.0, n_inner=3)
+    U, _, flags = o.iterate(o.init_state(), 10)
+    assert flags == 0
+    rng = np.random.default_rng(17)
+    Rb = rng.standard_normal((4, c.n))
+    Ub_o, tb_o, flags = o.residual_vjp(U, Rb)
+    assert flags == 0
+    plan = L.Plan(c, L.Params(0.6, 2.0, n_inner=3), tuning=L.Tuning(block, 1))
+    Ub = plan.field(4)
+    tb = torch.empty(2, dtype=torch.float64, device="cuda")
+    L.lskum_flux_residual_vjp(plan, up(U), up(Rb), Ub, tb, L.vjp_workspace(plan))
+    assert L.lskum_status(plan) == L.OK
+    e = normwise(down(Ub), Ub_o)
+    say("unordered", block, "Ubar normwise", e)
+    assert e <= TOL
+    np.testing.assert_allclose(tb.cpu().numpy(), tb_o, rtol=TOL, atol=0)
