@@ -56,16 +56,21 @@ def stage_bytes(n_points: int, k_pad: int, n_inner: int) -> float:
     return float(n_points) * per
 
 
+# the sources the forward sweep kernels (k_flux among them) are compiled from
+FORWARD_SOURCES = ("include/lskum.h", "paper_2403_13287_amd/csrc/lskum.hip",
+                   "paper_2403_13287_amd/csrc/lskum_impl.h",
+                   "paper_2403_13287_amd/csrc/lskum_math.h")
+
+
 def kernel_source_hash() -> str:
-    """sha256 of the kernel sources, to tie stored counter readings to the
-    code they were taken on."""
-    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    """sha256 of the forward kernels' sources, to tie stored counter readings
+    to the code they were taken on (the adjoint's source does not enter)."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     h = hashlib.sha256()
-    for name in sorted(os.listdir(here)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(here, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
+    for rel in FORWARD_SOURCES:
+        with open(os.path.join(root, rel), "rb") as f:
+            h.update(rel.encode())
+            h.update(f.read())
     return h.hexdigest()
 
 

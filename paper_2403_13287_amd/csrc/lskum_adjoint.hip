@@ -1078,11 +1078,12 @@ void adjoint_reset(lskum_plan_s *p) {
 int ensure_in_tiles(lskum_plan_s *p, void *stream) {
   InTileMap &m = p->in_map;
   if (m.blk == p->block) return LSKUM_OK;
+  // earlier VJP calls on this stream may still read the old tables
+  if (hipStreamSynchronize(S(stream)) != hipSuccess) return LSKUM_ERR_HIP;
   (void)hipFree(m.lent);
   (void)hipFree(m.hoff);
   (void)hipFree(m.hids);
   m = InTileMap{};
-  if (hipStreamSynchronize(S(stream)) != hipSuccess) return LSKUM_ERR_HIP;
   const int32_t n = p->n, ki = p->k_in;
   std::vector<int32_t> ent, cnt, ids, slots, hoff, hids;
   std::vector<uint32_t> lent;
