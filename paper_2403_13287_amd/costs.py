@@ -62,10 +62,12 @@ FORWARD_SOURCES = ("include/lskum.h", "paper_2403_13287_amd/csrc/lskum.hip",
                    "paper_2403_13287_amd/csrc/lskum_math.h")
 
 
-def kernel_source_hash() -> str:
-    """sha256 of the forward kernels' sources, to tie stored counter readings
-    to the code they were taken on (the adjoint's source does not enter)."""
-    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+def kernel_source_hash(root: str | None = None) -> str:
+    """sha256 of the forward kernels' sources (under the repository root, or
+    `root`), to tie stored counter readings to the code they were taken on
+    (the adjoint's source does not enter)."""
+    if root is None:
+        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     h = hashlib.sha256()
     for rel in FORWARD_SOURCES:
         with open(os.path.join(root, rel), "rb") as f:
