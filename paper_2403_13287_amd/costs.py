@@ -58,8 +58,11 @@ def stage_bytes(n_points: int, k_pad: int, n_inner: int) -> float:
 
 # the sources the forward sweep kernels (k_flux among them) are compiled from
 FORWARD_SOURCES = ("include/lskum.h", "paper_2403_13287_amd/csrc/lskum.hip",
+                   "paper_2403_13287_amd/csrc/lskum_flux.hip",
+                   "paper_2403_13287_amd/csrc/lskum_deriv.hip",
                    "paper_2403_13287_amd/csrc/lskum_impl.h",
-                   "paper_2403_13287_amd/csrc/lskum_math.h")
+                   "paper_2403_13287_amd/csrc/lskum_math.h",
+                   "paper_2403_13287_amd/_build.py")  # the build recipe picks the schedulers
 
 
 def kernel_source_hash(root: str | None = None) -> str:

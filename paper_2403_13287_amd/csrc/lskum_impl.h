@@ -503,7 +503,8 @@ int tile_slots(int32_t n, int32_t width, int blk, const int32_t *ids, const int3
                std::vector<int32_t> &slots, std::vector<int32_t> &hoff,
                std::vector<int32_t> &hids, int &hmax);
 
-// launchers of the forward kernels (lskum.hip), reused by the adjoint
+// launchers of the forward kernels (lskum.hip, lskum_deriv.hip, lskum_flux.hip),
+// reused by the adjoint
 int q_vars_launch(lskum_plan_s *p, const double *U, double *q, void *stream);
 // argext (nullable): per point and component, the stencil slot that attains
 // qlim (-1: the point itself), rows 0..3 for the max, 4..7 for the min
@@ -512,5 +513,10 @@ int deriv_first_launch(lskum_plan_s *p, const double *q, double *dq, double *qli
 // one inner sweep: dq0 = the first-order solution, dqp = previous iterate
 int deriv_inner_launch(lskum_plan_s *p, const double *dq0, const double *dqp, double *dqn,
                        void *stream);
+// local time step (tile tables when they fit)
+int local_dt_launch(lskum_plan_s *p, const double *U, double *dt, void *stream);
+// flux residual for the plan's tile size and scheme variant
+int flux_launch(lskum_plan_s *p, const double *q, const double *dq, const double *qlim,
+                double *R, void *stream);
 
 }  // namespace lskum_impl
