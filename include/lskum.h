@@ -229,10 +229,10 @@ int lskum_set_far_field(lskum_plan plan, double *U, void *stream);
  * ------------------------------------------------------------------- */
 
 /* Bytes of device workspace lskum_flux_residual_vjp needs:
- * (49 + 8 n_inner) doubles per point for q, every derivative iterate, the
- * bounds and the cotangents, plus 32 bytes per point and in-edge slot for
- * the edge cotangents (in-edge slots: the largest number of rows that list
- * one point). */
+ * (49 + 8 n_inner) doubles per point (each field rounded up to 256 bytes)
+ * for q, every derivative iterate, the bounds, the slots attaining them and
+ * the cotangents.  Nothing is stored per edge: each edge's reverse is
+ * recomputed where its cotangent is consumed. */
 size_t lskum_vjp_workspace_bytes(lskum_plan plan);
 
 /* Ubar = (dR/dU)^T Rbar at interior and wall rows, 0 at outer rows;
@@ -241,9 +241,9 @@ size_t lskum_vjp_workspace_bytes(lskum_plan plan);
  * U, Rbar, Ubar: device [n][4] (Rbar is ignored at outer rows); thetabar:
  * device [n_clouds][2]; ws: device, lskum_vjp_workspace_bytes(plan) bytes,
  * 256-byte aligned.  q and the derivatives are recomputed from U.  The
- * first call on a plan also builds the plan's transposed connectivity
- * (synchronous; LSKUM_ERR_INVALID_ARG beyond 2^25 - 1 points or 64 slots per
- * row). */
+ * first call on a plan also builds the plan's transposed connectivity and
+ * its LDS tile tables (rebuilt when the tile size changes; synchronous;
+ * LSKUM_ERR_INVALID_ARG beyond 2^25 - 1 points or 64 slots per row). */
 int lskum_flux_residual_vjp(lskum_plan plan, const double *U, const double *Rbar, double *Ubar,
                             double *thetabar, void *ws, void *stream);
 

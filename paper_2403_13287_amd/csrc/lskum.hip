@@ -1,4 +1,6 @@
-// lskum.hip -- gfx950 kernels and C ABI of the LSKUM residual sweep.
+// lskum.hip -- gfx950 plans, small kernels (q-variables, stage updates,
+// reductions) and the C ABI of the LSKUM residual sweep; the flux kernel is
+// in lskum_flux.hip, the derivative and time-step gathers in lskum_deriv.hip.
 //
 // Method: arXiv 2403.13287, "Theory of Meshfree LSKUM" (eq. (9)-(16)).
 // One thread per point for every sweep; points are stored in Hilbert order
