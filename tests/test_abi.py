@@ -109,8 +109,18 @@ def test_validation_rejects_bad_clouds(cyl):
 def test_validation_rejects_bad_params(cyl):
     s, keep = _c_cloud(cyl)
     for bad in [L.Params(0.5, 0.0, cfl=0.0), L.Params(0.5, 0.0, n_inner=-1),
-                L.Params(float("nan"), 0.0), L.Params(0.5, 0.0, gamma=1.0)]:
+                L.Params(float("nan"), 0.0), L.Params(0.5, 0.0, gamma=1.0),
+                L.Params(0.5, 0.0, options=8), L.Params(0.5, 0.0, options=-1)]:
         assert _create(s, bad)[0] == L.ERR_INVALID_ARG
+
+
+def test_empty_cloud_is_rejected(cyl):
+    """A cloud of no points is an argument error, found on the host before
+    any device work."""
+    s, keep = _c_cloud(cyl)
+    s.n = 0
+    rc, h = _create(s)
+    assert rc == L.ERR_INVALID_ARG and not h.value
 
 
 def test_null_arguments_are_rejected():
@@ -119,6 +129,7 @@ def test_null_arguments_are_rejected():
     assert lib.lskum_q_vars(None, None, None, None) == L.ERR_INVALID_ARG
     assert lib.lskum_flux_residual(None, None, None, None, None, None) == L.ERR_INVALID_ARG
     assert lib.lskum_rk_stage(None, 0, None, None, None, None, None) == L.ERR_INVALID_ARG
+    assert lib.lskum_rk4_stage(None, 0, None, None, None, None, None, None) == L.ERR_INVALID_ARG
     assert lib.lskum_workspace_bytes(None) == 0
     assert lib.lskum_set_far_field(None, None, None) == L.ERR_INVALID_ARG
     assert lib.lskum_flux_residual_vjp(None, None, None, None, None, None, None) == L.ERR_INVALID_ARG
