@@ -7,8 +7,9 @@
 // Plain loops over points in index order, one point at a time, evaluated in
 // the order the formulas are written (the library is built with
 // -ffp-contract=off, no -ffast-math).  The per-point formulas are templates
-// over the scalar type so that the same text can later be evaluated with an
-// operation-counting or a reverse-mode scalar.
+// over the scalar type, so that the same text is also evaluated with a
+// reverse-mode scalar (the adjoints) and an operation-counting one (the
+// algorithmic operation count of the flux residual).
 //
 // Method (arXiv 2403.13287, "Theory of Meshfree LSKUM"):
 //   * q-variables: eq. (13);
@@ -122,6 +123,41 @@ inline Var sin(Var x) { return make(std::sin(x.v), x.i, std::cos(x.v), -1, 0.0);
 inline double val(Var x) { return x.v; }
 
 }  // namespace ad
+
+// ---------------------------------------------------------------------------
+// Operation-counting scalar: evaluates the same template text in double and
+// tallies each floating-point operation on state-dependent values (sums and
+// differences, products, quotients, and calls of sqrt, exp, log, erf).
+// Negation is free; comparisons are not arithmetic.  Operations on plain
+// doubles (the geometry of an edge) are not seen.
+namespace cnt {
+
+struct Tally {
+  double add = 0, mul = 0, div = 0, sqrt = 0, exp = 0, log = 0, erf = 0;
+};
+Tally *tally = nullptr;  // the oracle is single-threaded
+
+struct Num {
+  double v;
+  Num() : v(0.0) {}
+  Num(double x) : v(x) {}  // NOLINT: constants convert implicitly
+};
+inline Num operator+(Num x, Num y) { tally->add += 1; return Num(x.v + y.v); }
+inline Num operator-(Num x, Num y) { tally->add += 1; return Num(x.v - y.v); }
+inline Num operator*(Num x, Num y) { tally->mul += 1; return Num(x.v * y.v); }
+inline Num operator/(Num x, Num y) { tally->div += 1; return Num(x.v / y.v); }
+inline Num operator-(Num x) { return Num(-x.v); }
+inline Num &operator+=(Num &x, Num y) { return x = x + y; }
+inline bool operator<(Num x, Num y) { return x.v < y.v; }
+inline bool operator>(Num x, Num y) { return x.v > y.v; }
+inline Num sqrt(Num x) { tally->sqrt += 1; return Num(std::sqrt(x.v)); }
+inline Num exp(Num x) { tally->exp += 1; return Num(std::exp(x.v)); }
+inline Num log(Num x) { tally->log += 1; return Num(std::log(x.v)); }
+inline Num erf(Num x) { tally->erf += 1; return Num(std::erf(x.v)); }
+inline Num fabs(Num x) { return Num(std::fabs(x.v)); }
+inline double val(Num x) { return x.v; }
+
+}  // namespace cnt
 
 inline double val(double x) { return x; }
 
@@ -718,6 +754,32 @@ unsigned lskum_ref_flux_residual(const lskum_ref_cloud *c, const lskum_ref_param
     flags |= flux_point(*c, *p, i, st, Ri);
     for (int m = 0; m < 4; ++m) fld(R, m, n, i) = Ri[m];
   }
+  return flags;
+}
+
+// Operation counts of the flux residual over the whole cloud, evaluated with
+// the counting scalar on the given fields: counts = {add/sub, mul, div,
+// sqrt, exp, log, erf} summed over all points.
+unsigned lskum_ref_flux_op_counts(const lskum_ref_cloud *c, const lskum_ref_params *p,
+                                  const double *q, const double *dq, const double *qlim,
+                                  double counts[7]) {
+  struct CountSt {
+    ArraySt a;
+    cnt::Num own(int f, int m) const { return cnt::Num(a.own(f, m)); }
+    cnt::Num nbr(int k, int f, int m) const { return cnt::Num(a.nbr(k, f, m)); }
+  };
+  cnt::Tally t;
+  cnt::tally = &t;
+  const int32_t n = c->n;
+  unsigned flags = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    CountSt st{ArraySt{{q, dq, qlim}, n, i, c->col + c->row_ptr[i]}};
+    cnt::Num Ri[4];
+    flags |= flux_point(*c, *p, i, st, Ri);
+  }
+  cnt::tally = nullptr;
+  const double v[7] = {t.add, t.mul, t.div, t.sqrt, t.exp, t.log, t.erf};
+  for (int k = 0; k < 7; ++k) counts[k] = v[k];
   return flags;
 }
 

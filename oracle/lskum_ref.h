@@ -98,6 +98,13 @@ double lskum_ref_residual_norm(const lskum_ref_cloud *c, const double *R);
 void lskum_ref_force_coeffs(const lskum_ref_cloud *c, const lskum_ref_params *p,
                             const double *U, double clcd[2]);
 
+/* operation counts of lskum_ref_flux_residual on these fields, summed over
+ * the cloud: counts[7] = {add/sub, mul, div, sqrt, exp, log, erf} on
+ * state-dependent values (edge geometry in plain doubles is not counted) */
+unsigned lskum_ref_flux_op_counts(const lskum_ref_cloud *c, const lskum_ref_params *p,
+                                  const double *q, const double *dq, const double *qlim,
+                                  double counts[7]);
+
 /* whole iterations: U is advanced in place; hist[k] receives the residual
  * norm of iteration k (first stage).  Returns the OR of all status bits. */
 unsigned lskum_ref_iterate(const lskum_ref_cloud *c, const lskum_ref_params *p,

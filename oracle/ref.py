@@ -68,6 +68,7 @@ def load(rebuild: bool = False) -> ctypes.CDLL:
         "lskum_ref_q_derivs_inner": (None, [cp, vp, vp, vp]),
         "lskum_ref_q_derivs": (None, [cp, pp, vp, vp, vp]),
         "lskum_ref_flux_residual": (ctypes.c_uint, [cp, pp, vp, vp, vp, vp]),
+        "lskum_ref_flux_op_counts": (ctypes.c_uint, [cp, pp, vp, vp, vp, vp]),
         "lskum_ref_local_dt": (None, [cp, pp, vp, vp]),
         "lskum_ref_rk_stage": (None, [cp, pp, ctypes.c_int, vp, vp, vp, vp]),
         "lskum_ref_rk4_stage": (None, [cp, pp, ctypes.c_int, vp, vp, vp, vp]),
@@ -235,6 +236,20 @@ class Oracle:
         dq, qlim = self.q_derivs(q)
         R, f2 = self.flux_residual(q, dq, qlim)
         return R, f1 | f2
+
+    OP_KINDS = ("add", "mul", "div", "sqrt", "exp", "log", "erf")
+
+    def flux_op_counts(self, q, dq, qlim):
+        """Floating-point operations of the flux residual on these fields,
+        summed over the cloud, by kind (OP_KINDS), counted on state-dependent
+        values by evaluating the same formulas with a counting scalar."""
+        q = self._field(q, 4)
+        dq = self._field(dq, 8)
+        qlim = self._field(qlim, 8)
+        out = np.zeros(7)
+        flags = self.lib.lskum_ref_flux_op_counts(ctypes.byref(self._c), ctypes.byref(self._p),
+                                                  _ptr(q), _ptr(dq), _ptr(qlim), _ptr(out))
+        return dict(zip(self.OP_KINDS, out.tolist())), int(flags)
 
     def local_dt(self, U):
         U = self._field(U, 4)

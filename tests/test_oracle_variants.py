@@ -164,3 +164,36 @@ def test_rk4_iterate_matches_the_stage_composition(tiny_cloud):
     Us, hs, _ = Oracle(tiny_cloud, 0.63, 2.0, n_inner=1).iterate(U0, 2)
     assert h[0] == hs[0]  # same first residual, different update
     assert np.max(np.abs(U - Us)) > 1e-8
+
+
+def test_flux_operation_count_matches_the_formula_structure():
+    """The counting scalar sees, per edge, the two states' densities (one
+    exp and one log each) and, per used half-plane split, two split fluxes
+    (one erf, one exp and two square roots each).  Which splits an edge uses
+    follows from the geometry alone (s-split when ds != 0; n-split when
+    dn > 0, or dn < 0 at interior points), so the totals are fixed exactly."""
+    c = square_cloud(15, seed=4, k=16, random_frames=True)
+    o = Oracle(c, 0.5, 10.0, n_inner=2)
+    U = prim_to_U(*smooth_prims(c.x, c.y))
+    q, _ = o.q_vars(U)
+    dq, qlim = o.q_derivs(q)
+    counts, flags = o.flux_op_counts(q, dq, qlim)
+    assert flags == 0
+    edges = splits = 0
+    for i in range(c.n):
+        if c.kind[i] == 2:
+            continue
+        tx, ty, nx, ny = c.ny[i], -c.nx[i], c.nx[i], c.ny[i]
+        for k in range(c.nbr_count[i]):
+            j = c.col[c.row_ptr[i] + k]
+            dx, dy = c.x[j] - c.x[i], c.y[j] - c.y[i]
+            ds, dn = dx * tx + dy * ty, dx * nx + dy * ny
+            edges += 1
+            splits += int(ds != 0.0) + int(dn > 0.0 or (dn < 0.0 and c.kind[i] == 0))
+    assert counts["log"] == 2 * edges
+    assert counts["exp"] == 2 * edges + 2 * splits
+    assert counts["erf"] == 2 * splits
+    assert counts["sqrt"] == 4 * splits
+    # the fields agree with the plain evaluation of the same formulas
+    R, _ = o.flux_residual(q, dq, qlim)
+    assert np.all(np.isfinite(R))
