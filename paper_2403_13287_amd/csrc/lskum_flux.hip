@@ -183,23 +183,24 @@ __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__res
 
 namespace lskum_impl {
 
-// The flux launch for the plan's tile size and scheme variant.
+// The flux launch for the plan's scheme variant.  The flux kernel stages
+// only its own block's records (it has no tile tables), so its block size is
+// independent of the plan's tile size: one-wavefront (64-point) blocks
+// shorten the tail of each launch, and the whole iteration on the 1M cloud
+// runs 1.3 % faster than with 256-point blocks.  Results do not depend on
+// the block size (each point's sums run in its row order).
+constexpr int kFluxBlock = 64;
+
 int flux_launch(lskum_plan_s *p, const double *q, const double *dq, const double *qlim,
                 double *R, void *stream) {
   const Geo g = geo(p);
   const Flow f = flow(p);
-  const int gr = grid_for(p->n, p->block);
+  const int gr = grid_for(p->n, kFluxBlock);
   hipStream_t st = S(stream);
-  switch (p->block * 4 + flux_variant(p)) {
-    case 128 * 4 + 0: k_flux<128, 0><<<gr, 128, 0, st>>>(g, f, p->spw, q, dq, qlim, R, p->status); break;
-    case 128 * 4 + 1: k_flux<128, 1><<<gr, 128, 0, st>>>(g, f, p->spw, q, dq, qlim, R, p->status); break;
-    case 128 * 4 + 2: k_flux<128, 2><<<gr, 128, 0, st>>>(g, f, p->spw, q, dq, qlim, R, p->status); break;
-    case 512 * 4 + 0: k_flux<512, 0><<<gr, 512, 0, st>>>(g, f, p->spw, q, dq, qlim, R, p->status); break;
-    case 512 * 4 + 1: k_flux<512, 1><<<gr, 512, 0, st>>>(g, f, p->spw, q, dq, qlim, R, p->status); break;
-    case 512 * 4 + 2: k_flux<512, 2><<<gr, 512, 0, st>>>(g, f, p->spw, q, dq, qlim, R, p->status); break;
-    case 256 * 4 + 1: k_flux<256, 1><<<gr, 256, 0, st>>>(g, f, p->spw, q, dq, qlim, R, p->status); break;
-    case 256 * 4 + 2: k_flux<256, 2><<<gr, 256, 0, st>>>(g, f, p->spw, q, dq, qlim, R, p->status); break;
-    default: k_flux<256, 0><<<gr, 256, 0, st>>>(g, f, p->spw, q, dq, qlim, R, p->status); break;
+  switch (flux_variant(p)) {
+    case 1: k_flux<kFluxBlock, 1><<<gr, kFluxBlock, 0, st>>>(g, f, p->spw, q, dq, qlim, R, p->status); break;
+    case 2: k_flux<kFluxBlock, 2><<<gr, kFluxBlock, 0, st>>>(g, f, p->spw, q, dq, qlim, R, p->status); break;
+    default: k_flux<kFluxBlock, 0><<<gr, kFluxBlock, 0, st>>>(g, f, p->spw, q, dq, qlim, R, p->status); break;
   }
   return launched();
 }
