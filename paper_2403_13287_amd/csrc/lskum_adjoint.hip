@@ -1161,10 +1161,15 @@ int reverse_passes(lskum_plan_s *p, const VjpWs &w, const double *U, const doubl
   const double *dqK = w.dq0 + (size_t)K * lev;
   const Geo g = geo(p);
   const Flow f = flow(p);
-  LSKUM_TILED_ADJ(k_flux_rev_own, p, stream, g, f, p->spw, w.q, dqK, w.qlim, Rbar, w.qbar, w.sa,
-                  w.lbar, p->status);
-  LSKUM_TILED_ADJ(k_flux_gather, p, stream, g, f, p->in_cnt, p->in_ent, p->lsg, p->spw, w.q, dqK,
-                  w.qlim, Rbar, w.qbar, w.sa, w.lbar);
+  {
+    // the two flux reverses have no tile tables: one-wavefront blocks
+    // shorten their launch tails, as for the forward flux
+    const int g64 = grid_for(p->n, 64);
+    k_flux_rev_own<64><<<g64, 64, 0, S(stream)>>>(g, f, p->spw, w.q, dqK, w.qlim, Rbar, w.qbar,
+                                                  w.sa, w.lbar, p->status);
+    k_flux_gather<64><<<g64, 64, 0, S(stream)>>>(g, f, p->in_cnt, p->in_ent, p->lsg, p->spw, w.q,
+                                                 dqK, w.qlim, Rbar, w.qbar, w.sa, w.lbar);
+  }
   // the derivative reverses on the in-edge tile tables when a block's
   // table fits the LDS budget
   const InTileMap &m = p->in_map;
