@@ -418,29 +418,39 @@ def main():
     L.lskum_init_state(plan, U)
     U0_host = U.cpu().numpy().T.copy()  # oracle layout (4, n)
     Un, q, dq, qlim, work, R = (plan.field(c) for c in (4, 4, 8, 8, 16, 4))
-    dt, acc = plan.field(1), plan.field(4)
+    dt, acc, q2 = plan.field(1), plan.field(4), plan.field(4)
+    rk4 = bool(options & L.RK4)
     hist = torch.zeros(max(steps + warm, 1), dtype=torch.float64, device="cuda")
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(4 * steps)]
 
+    qs = (q, q2)
+
     def step(k, timed):
+        # SSP stages: the flux launch also applies the stage update and writes
+        # the next stage's q into the other buffer (four stages bring q back
+        # to qs[0]); q_vars runs only before the very first stage.  RK4 keeps
+        # separate q_vars and stage launches.
         L.lskum_local_dt(plan, U, dt)
         Un.copy_(U)
         for s in range(4):
-            L.lskum_q_vars(plan, U, q)
+            qc = q if rk4 else qs[s % 2]
+            if rk4 or (k == 0 and s == 0):
+                L.lskum_q_vars(plan, U, qc)
             if not options & L.FIRST_ORDER:  # the first-order flux reads no derivatives
-                L.lskum_q_derivs(plan, q, dq, qlim, work)
+                L.lskum_q_derivs(plan, qc, dq, qlim, work)
             if timed:
                 ev[4 * (k - warm) + s][0].record()
-            L.lskum_flux_residual(plan, q, dq, qlim, R)
+            if rk4:
+                L.lskum_flux_residual(plan, qc, dq, qlim, R)
+            else:
+                L.lskum_flux_residual_stage(plan, s, qc, dq, qlim, Un, dt, R, U, qs[(s + 1) % 2])
             if timed:
                 ev[4 * (k - warm) + s][1].record()
             if s == 0:
                 L.lskum_residual_norm(plan, R, hist[k:k + 1])
-            if options & L.RK4:
+            if rk4:
                 L.lskum_rk4_stage(plan, s, Un, R, dt, acc, U)
-            else:
-                L.lskum_rk_stage(plan, s, Un, R, dt, U)
 
     log(f"[bench] n={n} edges={edges} warmup={warm} steps={steps}")
     for k in range(warm):
@@ -458,15 +468,16 @@ def main():
         f"hist first {h[0]:.6e} last {h[warm + steps - 1]:.6e}")
 
     value = n * 4.0 * steps / sec
-    flops = costs.flux_flops(n, edges)
+    # the timed launch is the flux with the SSP stage in its epilogue, or
+    # (rk4) the plain flux
+    flops = costs.flux_flops(n, edges, stage=not rk4)
     achieved = flops / (flux_ms * 1e-3) / 1e12
     traffic = None
-    same_flux = args.scheme in ("default", "rk4")  # rk4 changes only the stage update
-    if wl.name == "1m" and same_flux:
+    if wl.name == "1m" and args.scheme == "default":  # the profiled launch
         traffic = costs.stored_flux_traffic(os.path.join(ROOT, "profiles", "k_flux_1m.txt"))
-    if not same_flux:  # the FP64 count per edge is the default scheme's
+    if args.scheme not in ("default", "rk4"):  # the FP64 count per edge is the default scheme's
         achieved = None
-    stage_gb = costs.stage_bytes(n, cloud.k_pad, n_inner) / 1e9
+    stage_gb = costs.stage_bytes(n, cloud.k_pad, n_inner, fused=not rk4) / 1e9
     out = {
         "metric": METRIC,
         "value": value,
@@ -486,11 +497,13 @@ def main():
                                + ("" if args.scheme == "default" else f", scheme {args.scheme}"),
                    "points": n, "edges": edges, "k_pad": cloud.k_pad, "iterations": steps,
                    "stages_per_iteration": 4},
-        "roofline": {"bound": "alu", "kernel": "k_flux", "achieved": achieved,
+        "roofline": {"bound": "alu", "kernel": "k_flux" + ("" if rk4 else " + SSP stage"),
+                     "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": None if achieved is None else achieved / FP64_PEAK_TFLOPS,
                      "traffic": traffic, "flops_per_launch": flops, "avg_launch_ms": flux_ms,
-                     "algorithmic_bytes_per_launch": costs.flux_bytes(n, cloud.k_pad)},
+                     "algorithmic_bytes_per_launch": costs.flux_bytes(n, cloud.k_pad,
+                                                                      stage=not rk4)},
         "hbm_compulsory": {"GB_per_stage": stage_gb,
                            "achieved_GBs": stage_gb * 4 * steps / sec,
                            "frac": stage_gb * 4 * steps / sec / HBM_PEAK_GBS},

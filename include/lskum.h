@@ -161,6 +161,24 @@ int lskum_q_derivs(lskum_plan plan, const double *q, double *dq, double *qlim, d
 int lskum_flux_residual(lskum_plan plan, const double *q, const double *dq, const double *qlim,
                         double *R, void *stream);
 
+/* lskum_flux_residual, then, in the same launch, stage `stage` (0..3) of the
+ * SSP Runge-Kutta (4,3) scheme on U (as lskum_rk_stage, from that residual)
+ * and the q-variables of eq. (13) of the updated state into q_next (as
+ * lskum_q_vars): the stage update and eq. (13) need only the point's own
+ * values, so they run as the flux kernel's epilogue instead of two more
+ * passes over memory.  R, U and q_next equal those of the three separate
+ * calls bit for bit.  Un, U, R and q_next are [n][4] (32-byte aligned), dt
+ * is [n]; all device memory owned by the caller.  U holds the previous
+ * stage on entry and the new one on return; q_next, a buffer other than q
+ * (other points still read q as neighbours), receives the q of the next
+ * stage.  Non-physical new states set the status word as lskum_q_vars
+ * does.  The stage is always SSP: the plan's LSKUM_RK4 bit is not read
+ * here.  Returns LSKUM_ERR_INVALID_ARG for a null or misaligned pointer,
+ * stage outside 0..3 or q_next == q. */
+int lskum_flux_residual_stage(lskum_plan plan, int stage, const double *q, const double *dq,
+                              const double *qlim, const double *Un, const double *dt, double *R,
+                              double *U, double *q_next, void *stream);
+
 /* Local time step: dt_i = CFL * min_j |d_ij| / (|u_j| + 3 sqrt(p_j/rho_j)). */
 int lskum_local_dt(lskum_plan plan, const double *U, double *dt, void *stream);
 
@@ -194,7 +212,8 @@ int lskum_force_coeffs(lskum_plan plan, const double *U, double *clcd, void *str
 size_t lskum_workspace_bytes(lskum_plan plan);
 
 /* Advance U by `iters` iterations (each: local time step from U^n, then four
- * stages of q_vars -> q_derivs -> flux_residual -> rk_stage).
+ * stages of q_vars -> q_derivs -> flux_residual -> rk_stage, the SSP stages
+ * as lskum_flux_residual_stage).
  * hist[k*n_clouds + c] (device, may be NULL) receives the residual norm of
  * iteration k's first stage for cloud c.  `ws` is a device buffer of
  * lskum_workspace_bytes(plan) bytes, 256-byte aligned. */

@@ -10,7 +10,7 @@ counts 2).  Every FP64 operation the kernel executes belongs to that
 formulation (the only wasted work is the n+ split flux evaluated with zero
 weight at wall points, 0.1 % of the edges of the 1M cloud), so the count is
 taken from the hardware: SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes of one launch
-on the 1M cloud divided by its edges (1.6775e10 / 29,967,646).  Per edge the
+on the 1M cloud divided by its edges (1.6755e10 / 29,967,646).  Per edge the
 formulation holds 4 erf, 6 exp, 3 Newton-refined rsqrt, 8 Newton-refined
 divides and about 190 multiply/add/FMA operations; the half-plane
 least-squares weights are computed once with the plan (geometry only) and
@@ -27,32 +27,47 @@ import os
 # measured FP64 operations per call (FMA = 2), calibration kernels, gfx950
 ELEMENTARY_FLOPS = {"exp": 27, "erf": 54.4, "log": 79, "sqrt": 17, "rsqrt": 9, "div": 14}
 
-EDGE_FLOPS = 559.8  # flux kernel, FP64 operations per (point, neighbour) pair
+EDGE_FLOPS = 559.1  # flux kernel, FP64 operations per (point, neighbour) pair
+# the SSP stage update and the q-variables of the new state (eq. (13)) run
+# as the flux launch's epilogue: FP64 operations per point, the difference
+# of the fused and the plain flux launch's SQ_INSTS_VALU_FLOPS_FP64 over the
+# points of the 1M cloud (1.7005e10 - 559.1 x 29,967,646, averaged over the
+# four stages)
+STAGE_FLOPS = 251.2
 
 
-def flux_flops(n_points: int, n_edges: int) -> float:
-    return float(n_edges) * EDGE_FLOPS
+def flux_flops(n_points: int, n_edges: int, stage: bool = False) -> float:
+    """FP64 operations of one flux launch; with `stage`, of the launch that
+    also applies the SSP stage and writes the next q."""
+    return float(n_edges) * EDGE_FLOPS + (float(n_points) * STAGE_FLOPS if stage else 0.0)
 
 
 def conn_bytes(k_pad: int) -> int:
     return 4 * k_pad + 4
 
 
-def flux_bytes(n_points: int, k_pad: int) -> float:
+def flux_bytes(n_points: int, k_pad: int, stage: bool = False) -> float:
     """Flux pass: x, y, nx, ny, kind (33), q (32), dq (64), qlim (64),
-    half-plane weights (64), connectivity; writes R (32)."""
-    return float(n_points) * (33 + 32 + 64 + 64 + 64 + 32 + conn_bytes(k_pad))
+    half-plane weights (64), connectivity; writes R (32).  With the SSP
+    stage in its epilogue also U and dt in, U and the next q out, and U^n
+    at one stage in four (32 + 8 + 32 + 32 + 32/4 = 112)."""
+    return float(n_points) * (33 + 32 + 64 + 64 + 64 + 32 + conn_bytes(k_pad)
+                              + (112 if stage else 0))
 
 
-def stage_bytes(n_points: int, k_pad: int, n_inner: int) -> float:
-    """One RK stage: q-variables (64), first-order pass (16 + 32 + 64 + 64
-    + C), each inner sweep (16 + previous derivatives 64 + first-order
-    derivatives 64 + new derivatives 64 + C), flux pass, stage update (Un,
-    U, R, dt, kind in; U out: 137), plus the per-iteration time step and U^n
-    copy amortised over 4 stages ((16 + 32 + 8 + C + 64)/4)."""
+def stage_bytes(n_points: int, k_pad: int, n_inner: int, fused: bool = True) -> float:
+    """One RK stage: first-order pass (16 + 32 + 64 + 64 + C), each inner
+    sweep (16 + previous derivatives 64 + first-order derivatives 64 + new
+    derivatives 64 + C), the flux pass with the SSP stage in its epilogue,
+    plus the per-iteration time step and U^n copy amortised over 4 stages
+    ((16 + 32 + 8 + C + 64)/4).  Unfused (classical RK4): the plain flux
+    pass, a q-variables pass (64) and a stage update (Un, U, R, dt, kind
+    in; U out: 137) instead."""
     c = conn_bytes(k_pad)
-    flux = flux_bytes(1, k_pad)
-    per = 64 + (176 + c) + n_inner * (208 + c) + flux + 137 + (120 + c) / 4.0
+    flux = flux_bytes(1, k_pad, stage=fused)
+    per = (176 + c) + n_inner * (208 + c) + flux + (120 + c) / 4.0
+    if not fused:
+        per += 64 + 137
     return float(n_points) * per
 
 

@@ -39,21 +39,13 @@
 
 namespace lskum_impl {
 
-__global__ void __launch_bounds__(kBlock) k_q_vars(int n, int xcd, double g, double inv_gm1,
+__global__ void __launch_bounds__(kBlock) k_q_vars(int n, int xcd, Flow P,
                                                    const double *__restrict__ U,
                                                    double *__restrict__ q, unsigned *status) {
   const int i = point_index<kBlock>(xcd);
   if (i >= n) return;
-  double rho, u, v, p;
-  prim_from_cons(g, ld4(U, i), rho, u, v, p);
-  const unsigned f =
-      (!(rho > 0.0) || !(p > 0.0) || !isfinite(rho) || !isfinite(p)) ? kFlagNonPhysical : 0u;
-  const double beta = 0.5 * rho / p;
   F4 o;
-  o.v[0] = log(rho) + log(beta) * inv_gm1 - beta * (u * u + v * v);
-  o.v[1] = 2.0 * beta * u;
-  o.v[2] = 2.0 * beta * v;
-  o.v[3] = -2.0 * beta;
+  const unsigned f = q_of_state(P, ld4(U, i), o);
   st4(q, i, o);
   flag(status, f);
 }
@@ -118,26 +110,8 @@ __global__ void __launch_bounds__(kBlock) k_rk_stage(Geo G, Flow P, int stage,
   const int i = point_index<kBlock>(G.xcd);
   if (i >= n) return;
   const int kind = G.kind[i];
-  F4 Ui;
-  if (kind == 2) {
-    Ui = ld4(G.uinf, G.cloud[i]);
-  } else {
-    const double h = 0.5 * dt[i];
-    const F4 Uc = ld4(U, i), Ri = ld4(R, i);
-    if (stage == 2) {
-      const F4 U0 = ld4(Un, i);
-      for (int m = 0; m < 4; ++m)
-        Ui.v[m] = (2.0 / 3.0) * U0.v[m] + (1.0 / 3.0) * (Uc.v[m] - h * Ri.v[m]);
-    } else {
-      for (int m = 0; m < 4; ++m) Ui.v[m] = Uc.v[m] - h * Ri.v[m];
-    }
-    if (kind == 1) {
-      const double2 nv = G.nrm[i];
-      const double mn = Ui.v[1] * nv.x + Ui.v[2] * nv.y;
-      Ui.v[1] = Ui.v[1] - mn * nv.x;
-      Ui.v[2] = Ui.v[2] - mn * nv.y;
-    }
-  }
+  const F4 Ui = kind == 2 ? ld4(G.uinf, G.cloud[i])
+                          : ssp_stage(G, i, kind, stage, Un, ld4(U, i), ld4(R, i), dt[i]);
   st4(U, i, Ui);
 }
 
@@ -382,8 +356,7 @@ int ensure_tile_map(lskum_plan_s *p) {
 
 int q_vars_launch(lskum_plan_s *p, const double *U, double *q, void *stream) {
   const Flow f = flow(p);
-  k_q_vars<<<grid_for(p->n), kBlock, 0, S(stream)>>>(p->n, p->xcd, f.gamma, f.inv_gm1, U, q,
-                                                     p->status);
+  k_q_vars<<<grid_for(p->n), kBlock, 0, S(stream)>>>(p->n, p->xcd, f, U, q, p->status);
   return launched();
 }
 
@@ -443,7 +416,7 @@ void release(lskum_plan_s *p) {
   delete p;
 }
 
-constexpr size_t kNumWorkFields = 4 + 4 + 8 + 8 + 16 + 4 + 1 + 4;  // Un q dq qlim work R dt acc
+constexpr size_t kNumWorkFields = 4 + 4 + 8 + 8 + 16 + 4 + 1 + 4 + 4;  // Un q dq qlim work R dt acc q2
 
 // Validate one cloud and append it (point ids shifted by base) to the
 // concatenated host arrays.
@@ -548,6 +521,7 @@ int run_iterations(lskum_plan_s *p, int32_t iters, double *U, double *hist, int3
   double *R = reinterpret_cast<double *>(base + 40 * f1);
   double *dt = reinterpret_cast<double *>(base + 44 * f1);
   double *acc = reinterpret_cast<double *>(base + 45 * f1);
+  double *q2 = reinterpret_cast<double *>(base + 49 * f1);
   const bool rk4 = (p->params[0].options & LSKUM_RK4) != 0;
   const Geo g = geo(p);
   const Flow f = flow(p);
@@ -558,10 +532,13 @@ int run_iterations(lskum_plan_s *p, int32_t iters, double *U, double *hist, int3
     if ((rc = local_dt_launch(p, U, dt, stream))) return rc;
     k_copy<<<copy_grid, kBlock, 0, S(stream)>>>(4 * n, U, Un);
     for (int s = 0; s < 4; ++s) {
-      if ((rc = q_vars_launch(p, U, q, stream))) return rc;
+      // SSP stages run fused into the flux launch, which also writes the
+      // next stage's q (ping-pong buffers); q_vars only starts the sequence
+      if ((rk4 || (it == 0 && s == 0)) && (rc = q_vars_launch(p, U, q, stream))) return rc;
       // the first-order flux reads no derivatives
       if (flux_variant(p) != 1 && (rc = q_derivs_launch(p, q, dq, qlim, work, stream))) return rc;
-      if ((rc = flux_launch(p, q, dq, qlim, R, stream))) return rc;
+      const StageArgs sa{s, Un, dt, U, q2};
+      if ((rc = flux_launch(p, q, dq, qlim, R, stream, rk4 ? nullptr : &sa))) return rc;
       if (s == 0) {
         if (counter)
           rc = norm_launch(p, R, hist ? hist : p->norm_scratch, counter, hist ? hist_rows : 1,
@@ -571,10 +548,13 @@ int run_iterations(lskum_plan_s *p, int32_t iters, double *U, double *hist, int3
                            nullptr, 1, stream);
         if (rc) return rc;
       }
-      if (rk4)
+      if (rk4) {
         k_rk4_stage<<<grid, kBlock, 0, S(stream)>>>(g, f, s, Un, R, dt, acc, U);
-      else
-        k_rk_stage<<<grid, kBlock, 0, S(stream)>>>(g, f, s, Un, R, dt, U);
+      } else {
+        double *t = q;
+        q = q2;
+        q2 = t;
+      }
     }
     if (counter) k_tick<<<1, 64, 0, S(stream)>>>(counter);
   }
@@ -779,6 +759,16 @@ int lskum_flux_residual(lskum_plan p, const double *q, const double *dq, const d
                         double *R, void *stream) {
   if (!p || !a32(q) || !a64(dq) || !a64(qlim) || !a32(R)) return LSKUM_ERR_INVALID_ARG;
   return flux_launch(p, q, dq, qlim, R, stream);
+}
+
+int lskum_flux_residual_stage(lskum_plan p, int stage, const double *q, const double *dq,
+                              const double *qlim, const double *Un, const double *dt, double *R,
+                              double *U, double *q_next, void *stream) {
+  if (!p || !a32(q) || !a64(dq) || !a64(qlim) || !a32(R) || !a32(Un) || !dt || !a32(U) ||
+      !a32(q_next) || q_next == q || stage < 0 || stage > 3)
+    return LSKUM_ERR_INVALID_ARG;
+  const StageArgs sa{stage, Un, dt, U, q_next};
+  return flux_launch(p, q, dq, qlim, R, stream, &sa);
 }
 
 int lskum_local_dt(lskum_plan p, const double *U, double *dt, void *stream) {

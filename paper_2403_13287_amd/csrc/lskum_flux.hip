@@ -26,13 +26,17 @@ __device__ __forceinline__ unsigned degenerate_splits(const F8 &W, bool interior
 // n-split, weighted by the point's half-plane least-squares weights.  The
 // point's own records and weights are re-read from LDS at every edge
 // instead of being held in registers through the loop.
-// VAR: 0 the default scheme, 1 first-order flux (q~ = q), 2 min-max limiter
-template <int BLK, int VAR>
+// VAR: 0 the default scheme, 1 first-order flux (q~ = q), 2 min-max limiter.
+// FUSE: then the point's SSP stage update (its residual is all it needs)
+// and the q-variables of its new state, into S.q_next (the next stage's q;
+// the q read here stays unchanged for the other threads' neighbour loads).
+template <int BLK, int VAR, bool FUSE>
 __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__restrict__ spw,
                                                  const double *__restrict__ q,
                                                  const double *__restrict__ dq,
                                                  const double *__restrict__ qlim,
-                                                 double *__restrict__ R, unsigned *status) {
+                                                 double *__restrict__ R, unsigned *status,
+                                                 StageArgs S) {
   // the tile's records as 16-byte planes: q in 2, dq, qlim and the split
   // weights in 4 each (whole records would put lanes on few LDS banks)
   __shared__ double2 s_xy[BLK];
@@ -67,8 +71,20 @@ __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__res
   __syncthreads();
   if (!active) return;
   const int kind = G.kind[i];
+  // the stage update and next q of this point, once its residual r is known
+  auto finish = [&](const F4 &r, unsigned f) {
+    st4(R, i, r);
+    if (FUSE) {
+      const F4 Ui = ssp_stage(G, i, kind, S.stage, S.Un, ld4(S.U, i), r, S.dt[i]);
+      st4(S.U, i, Ui);
+      F4 qn;
+      f |= q_of_state(P, Ui, qn);
+      st4(S.q_next, i, qn);
+    }
+    flag(status, f);
+  };
   if (kind == 2) {
-    st4(R, i, F4{{0.0, 0.0, 0.0, 0.0}});
+    finish(F4{{0.0, 0.0, 0.0, 0.0}}, 0u);
     return;
   }
   const bool interior = kind == 0;
@@ -175,8 +191,7 @@ __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__res
   r.v[1] = acc[1] * tx + acc[2] * nx;
   r.v[2] = acc[1] * ty + acc[2] * ny;
   r.v[3] = acc[3];
-  st4(R, i, r);
-  flag(status, f);
+  finish(r, f);
 }
 
 }  // namespace lskum_impl
@@ -192,16 +207,27 @@ namespace lskum_impl {
 constexpr int kFluxBlock = 64;
 
 int flux_launch(lskum_plan_s *p, const double *q, const double *dq, const double *qlim,
-                double *R, void *stream) {
+                double *R, void *stream, const StageArgs *stage) {
   const Geo g = geo(p);
   const Flow f = flow(p);
   const int gr = grid_for(p->n, kFluxBlock);
   hipStream_t st = S(stream);
+  const StageArgs sa = stage ? *stage : StageArgs{-1, nullptr, nullptr, nullptr, nullptr};
+#define LSKUM_FLUX_V(var)                                                                  \
+  do {                                                                                     \
+    if (stage)                                                                             \
+      k_flux<kFluxBlock, var, true><<<gr, kFluxBlock, 0, st>>>(g, f, p->spw, q, dq, qlim, R, \
+                                                               p->status, sa);             \
+    else                                                                                   \
+      k_flux<kFluxBlock, var, false><<<gr, kFluxBlock, 0, st>>>(g, f, p->spw, q, dq, qlim, R, \
+                                                                p->status, sa);            \
+  } while (0)
   switch (flux_variant(p)) {
-    case 1: k_flux<kFluxBlock, 1><<<gr, kFluxBlock, 0, st>>>(g, f, p->spw, q, dq, qlim, R, p->status); break;
-    case 2: k_flux<kFluxBlock, 2><<<gr, kFluxBlock, 0, st>>>(g, f, p->spw, q, dq, qlim, R, p->status); break;
-    default: k_flux<kFluxBlock, 0><<<gr, kFluxBlock, 0, st>>>(g, f, p->spw, q, dq, qlim, R, p->status); break;
+    case 1: LSKUM_FLUX_V(1); break;
+    case 2: LSKUM_FLUX_V(2); break;
+    default: LSKUM_FLUX_V(0); break;
   }
+#undef LSKUM_FLUX_V
   return launched();
 }
 

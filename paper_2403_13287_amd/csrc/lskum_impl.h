@@ -144,6 +144,58 @@ __device__ __forceinline__ void prim_from_cons(double g, const F4 &U, double &rh
   p = (g - 1.0) * (U.v[3] - 0.5 * rho * (u * u + v * v));
 }
 
+// eq. (13) at one point: the q-variables of the conserved state Ui;
+// returns kFlagNonPhysical for rho or p <= 0 or non-finite.
+__device__ __forceinline__ unsigned q_of_state(const Flow &P, const F4 &Ui, F4 &q) {
+  double rho, u, v, p;
+  prim_from_cons(P.gamma, Ui, rho, u, v, p);
+  const unsigned f =
+      (!(rho > 0.0) || !(p > 0.0) || !isfinite(rho) || !isfinite(p)) ? kFlagNonPhysical : 0u;
+  const double beta = 0.5 * rho / p;
+  q.v[0] = log(rho) + log(beta) * P.inv_gm1 - beta * (u * u + v * v);
+  q.v[1] = 2.0 * beta * u;
+  q.v[2] = 2.0 * beta * v;
+  q.v[3] = -2.0 * beta;
+  return f;
+}
+
+// Stage `stage` of the SSP Runge-Kutta (4,3) scheme at point i of kind
+// `kind`, from its current state Uc, residual Ri and time step dt (U^n read
+// from Un at stage 2 only), with the boundary conditions: outer points take
+// their cloud's free stream, wall points drop the normal momentum.
+__device__ __forceinline__ F4 ssp_stage(const Geo &G, int i, int kind, int stage,
+                                        const double *__restrict__ Un, const F4 &Uc,
+                                        const F4 &Ri, double dt) {
+  F4 Ui;
+  if (kind == 2) return ld4(G.uinf, G.cloud[i]);
+  const double h = 0.5 * dt;
+  if (stage == 2) {
+    const F4 U0 = ld4(Un, i);
+    for (int m = 0; m < 4; ++m)
+      Ui.v[m] = (2.0 / 3.0) * U0.v[m] + (1.0 / 3.0) * (Uc.v[m] - h * Ri.v[m]);
+  } else {
+    for (int m = 0; m < 4; ++m) Ui.v[m] = Uc.v[m] - h * Ri.v[m];
+  }
+  if (kind == 1) {
+    const double2 nv = G.nrm[i];
+    const double mn = Ui.v[1] * nv.x + Ui.v[2] * nv.y;
+    Ui.v[1] = Ui.v[1] - mn * nv.x;
+    Ui.v[2] = Ui.v[2] - mn * nv.y;
+  }
+  return Ui;
+}
+
+// The stage update a flux launch may apply right after a point's residual
+// (stage >= 0): U <- ssp_stage(U), and q_next <- the q-variables of the new
+// state (a buffer other than the q the flux reads).
+struct StageArgs {
+  int stage;
+  const double *Un;
+  const double *dt;
+  double *U;
+  double *q_next;
+};
+
 // ---------------------------------------------------------------------------
 // block tiles
 //
@@ -515,8 +567,9 @@ int deriv_inner_launch(lskum_plan_s *p, const double *dq0, const double *dqp, do
                        void *stream);
 // local time step (tile tables when they fit)
 int local_dt_launch(lskum_plan_s *p, const double *U, double *dt, void *stream);
-// flux residual for the plan's tile size and scheme variant
+// flux residual for the plan's scheme variant; with st (nullable) the launch
+// also applies SSP stage st->stage and writes the new state's q-variables
 int flux_launch(lskum_plan_s *p, const double *q, const double *dq, const double *qlim,
-                double *R, void *stream);
+                double *R, void *stream, const StageArgs *st = nullptr);
 
 }  // namespace lskum_impl

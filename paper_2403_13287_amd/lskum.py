@@ -75,6 +75,7 @@ _SIGS = {
     "lskum_local_dt": (ctypes.c_int, "vvvv"),
     "lskum_rk_stage": (ctypes.c_int, "vivvvvv"),
     "lskum_rk4_stage": (ctypes.c_int, "vivvvvvv"),
+    "lskum_flux_residual_stage": (ctypes.c_int, "vivvvvvvvvv"),
     "lskum_residual_norm": (ctypes.c_int, "vvvv"),
     "lskum_force_coeffs": (ctypes.c_int, "vvvv"),
     "lskum_workspace_bytes": (ctypes.c_size_t, "v"),
@@ -278,6 +279,16 @@ def lskum_flux_residual(plan: Plan, q, dq, qlim, R, stream=None):
     _check(plan.lib.lskum_flux_residual(plan.handle, plan._arg(q, 4, "q"), plan._arg(dq, 8, "dq"),
                                         plan._arg(qlim, 8, "qlim"), plan._arg(R, 4, "R"),
                                         _stream(stream)), "lskum_flux_residual")
+
+
+def lskum_flux_residual_stage(plan: Plan, stage: int, q, dq, qlim, Un, dt, R, U, q_next,
+                              stream=None):
+    """Flux residual, SSP stage `stage` of U and the next stage's q in one launch."""
+    _check(plan.lib.lskum_flux_residual_stage(
+        plan.handle, int(stage), plan._arg(q, 4, "q"), plan._arg(dq, 8, "dq"),
+        plan._arg(qlim, 8, "qlim"), plan._arg(Un, 4, "Un"), plan._arg(dt, 1, "dt"),
+        plan._arg(R, 4, "R"), plan._arg(U, 4, "U"), plan._arg(q_next, 4, "q_next"),
+        _stream(stream)), "lskum_flux_residual_stage")
 
 
 def lskum_local_dt(plan: Plan, U, dt, stream=None):

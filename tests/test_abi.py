@@ -130,6 +130,8 @@ def test_null_arguments_are_rejected():
     assert lib.lskum_flux_residual(None, None, None, None, None, None) == L.ERR_INVALID_ARG
     assert lib.lskum_rk_stage(None, 0, None, None, None, None, None) == L.ERR_INVALID_ARG
     assert lib.lskum_rk4_stage(None, 0, None, None, None, None, None, None) == L.ERR_INVALID_ARG
+    assert lib.lskum_flux_residual_stage(None, 0, None, None, None, None, None, None, None, None,
+                                         None) == L.ERR_INVALID_ARG
     assert lib.lskum_workspace_bytes(None) == 0
     assert lib.lskum_set_far_field(None, None, None) == L.ERR_INVALID_ARG
     assert lib.lskum_flux_residual_vjp(None, None, None, None, None, None, None) == L.ERR_INVALID_ARG

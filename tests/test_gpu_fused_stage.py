@@ -1,0 +1,98 @@
+"""The flux launch with the SSP stage fused into its epilogue
+(lskum_flux_residual_stage) against the three separate launches it replaces
+(flux residual, SSP stage update, q-variables of the new state): residual,
+state and next q equal bit for bit at every stage, for the scheme options
+that share the SSP stages, on a single cloud and on a batch of clouds with
+different free streams.  The whole-iteration driver, which uses the fused
+launch, is checked against the oracle in the parity tests."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from cloudgen import make_airfoil_cloud, named_cloud
+from paper_2403_13287_amd import lskum as L
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _run_both(plan, U0):
+    """Both paths through the four stages of one iteration from U0."""
+    dq, qlim, work = plan.field(8), plan.field(8), plan.field(16)
+    Un, dt = U0.clone(), plan.field(1)
+    L.lskum_local_dt(plan, U0, dt)
+    Ua, Ub = U0.clone(), U0.clone()
+    Ra, Rb = plan.field(4), plan.field(4)
+    qa, qb = plan.field(4), plan.field(4)
+    L.lskum_q_vars(plan, Ua, qa)
+    qb.copy_(qa)
+    qnext = plan.field(4)
+    for s in range(4):
+        # separate launches
+        L.lskum_q_derivs(plan, qa, dq, qlim, work)
+        L.lskum_flux_residual(plan, qa, dq, qlim, Ra)
+        L.lskum_rk_stage(plan, s, Un, Ra, dt, Ua)
+        L.lskum_q_vars(plan, Ua, qa)
+        # fused
+        L.lskum_q_derivs(plan, qb, dq, qlim, work)
+        qnext.fill_(float("nan"))
+        L.lskum_flux_residual_stage(plan, s, qb, dq, qlim, Un, dt, Rb, Ub, qnext)
+        torch.cuda.synchronize()
+        assert torch.equal(Ra, Rb), f"R at stage {s}"
+        assert torch.equal(Ua, Ub), f"U at stage {s}"
+        assert torch.equal(qa, qnext), f"q_next at stage {s}"
+        qb, qnext = qnext, qb
+    assert L.lskum_status(plan) == L.OK
+    return Ua
+
+
+@pytest.mark.parametrize("options", [0, L.FIRST_ORDER, L.MINMAX])
+def test_fused_stage_equals_separate_launches(options):
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    c = named_cloud("tiny")
+    plan = L.Plan(c, L.Params(0.63, 2.0, n_inner=2, options=options))
+    U = plan.field(4)
+    L.lskum_init_state(plan, U)
+    L.lskum_iterate(plan, 3, U, None, L.workspace(plan))  # a state off the free stream
+    say("options", options, "n", plan.n)
+    U1 = _run_both(plan, U)
+    assert not torch.equal(U1, U)
+
+
+def test_fused_stage_on_a_batch():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    clouds = [make_airfoil_cloud(W, Lr, 25, seed) for W, Lr, seed in
+              ((40, 30, 11), (64, 40, 12), (50, 50, 13))]
+    params = [L.Params(m, a, n_inner=2) for m, a in ((0.4, -2.0), (0.7, 3.0), (1.2, 0.0))]
+    for block in (128, 256):
+        plan = L.Plan(clouds, params, tuning=L.Tuning(block, 1))
+        U = plan.field(4)
+        L.lskum_init_state(plan, U)
+        L.lskum_iterate(plan, 2, U, None, L.workspace(plan))
+        say("batch", [c.n for c in clouds], "block", block)
+        _run_both(plan, U)
+
+
+def test_fused_stage_rejects_aliased_q():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    c = named_cloud("tiny")
+    plan = L.Plan(c, L.Params(0.63, 2.0))
+    q, dq, qlim = plan.field(4), plan.field(8), plan.field(8)
+    Un, dt, R, U = plan.field(4), plan.field(1), plan.field(4), plan.field(4)
+    lib = plan.lib
+    args = (q.data_ptr(), dq.data_ptr(), qlim.data_ptr(), Un.data_ptr(), dt.data_ptr(),
+            R.data_ptr(), U.data_ptr())
+    assert lib.lskum_flux_residual_stage(plan.handle, 0, *args, q.data_ptr(), None) == \
+        L.ERR_INVALID_ARG
+    for bad in (-1, 4):
+        assert lib.lskum_flux_residual_stage(plan.handle, bad, *args, R.data_ptr(), None) == \
+            L.ERR_INVALID_ARG
