@@ -213,6 +213,62 @@ def bench_batch(args) -> int:
     return 0 if status == L.OK and loop_status == L.OK else 1
 
 
+def time_adjoint(plan, U, reps: int, warmup: int, force: bool = False) -> dict:
+    """Mean times (ms, HIP events on the current stream) of one forward
+    residual evaluation (q-variables, q-derivatives, flux residual) and of
+    the residual VJP with respect to U and (M, AoA) (q and every derivative
+    iterate recomputed) at the state U, with N(0, 1) cotangents (seed 7);
+    with `force` also of the lift/drag VJP."""
+    import numpy as np
+    import torch
+
+    from paper_2403_13287_amd import lskum as L
+
+    n = plan.n
+    gen = torch.Generator().manual_seed(7)
+    Rb = torch.randn((n, 4), generator=gen, dtype=torch.float64).cuda()
+    Jb = torch.tensor([1.0, 0.0], dtype=torch.float64, device="cuda")
+    q, dq, qlim, work, R = (plan.field(c) for c in (4, 8, 8, 16, 4))
+    Ub, Fb = plan.field(4), plan.field(4)
+    tb = torch.empty(2, dtype=torch.float64, device="cuda")
+    ws = L.vjp_workspace(plan)
+
+    def forward():
+        L.lskum_q_vars(plan, U, q)
+        L.lskum_q_derivs(plan, q, dq, qlim, work)
+        L.lskum_flux_residual(plan, q, dq, qlim, R)
+
+    def vjp():
+        L.lskum_flux_residual_vjp(plan, U, Rb, Ub, tb, ws)
+
+    def force_vjp():
+        L.lskum_force_coeffs_vjp(plan, U, Jb, Fb, tb)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    vjp()  # builds the plan's transposed connectivity once
+    torch.cuda.synchronize()
+    out = {"forward_ms": timed(forward), "vjp_ms": timed(vjp)}
+    out["ratio"] = out["vjp_ms"] / out["forward_ms"]
+    if force:
+        out["force_vjp_ms"] = timed(force_vjp)
+    out["vjp_workspace_bytes"] = L.lskum_vjp_workspace_bytes(plan)
+    torch.cuda.synchronize()
+    out["finite"] = bool(torch.isfinite(Ub).all()) and bool(torch.isfinite(tb).all())
+    return out
+
+
 def bench_adjoint(args) -> int:
     """Cost of the residual VJP (q and every derivative iterate recomputed)
     against one forward residual evaluation (q-variables, q-derivatives,
@@ -236,45 +292,9 @@ def bench_adjoint(args) -> int:
     s.run(state_iters)
     torch.cuda.synchronize()
     plan, U, n = s.plan, s.U, s.n
-    gen = torch.Generator().manual_seed(7)
-    Rb = torch.randn((n, 4), generator=gen, dtype=torch.float64).cuda()
-    Jb = torch.tensor([1.0, 0.0], dtype=torch.float64, device="cuda")
-    q, dq, qlim, work, R = (plan.field(c) for c in (4, 8, 8, 16, 4))
-    Ub, Fb = plan.field(4), plan.field(4)
-    tb = torch.empty(2, dtype=torch.float64, device="cuda")
-    ws = L.vjp_workspace(plan)
-
-    def forward():
-        L.lskum_q_vars(plan, U, q)
-        L.lskum_q_derivs(plan, q, dq, qlim, work)
-        L.lskum_flux_residual(plan, q, dq, qlim, R)
-
-    def vjp():
-        L.lskum_flux_residual_vjp(plan, U, Rb, Ub, tb, ws)
-
-    def force_vjp():
-        L.lskum_force_coeffs_vjp(plan, U, Jb, Fb, tb)
-
-    def timed(fn):
-        for _ in range(args.warmup):
-            fn()
-        torch.cuda.synchronize()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(reps)]
-        for a, b in ev:
-            a.record()
-            fn()
-            b.record()
-        torch.cuda.synchronize()
-        return float(np.mean([a.elapsed_time(b) for a, b in ev]))
-
-    vjp()  # builds the plan's transposed connectivity once
-    torch.cuda.synchronize()
-    t_fwd = timed(forward)
-    t_vjp = timed(vjp)
-    t_force = timed(force_vjp)
+    t = time_adjoint(plan, U, reps, args.warmup, force=True)
+    t_fwd, t_vjp, t_force, ratio = t["forward_ms"], t["vjp_ms"], t["force_vjp_ms"], t["ratio"]
     status = s.status()
-    ratio = t_vjp / t_fwd
     log(f"[bench] forward {t_fwd:.4f} ms, vjp {t_vjp:.4f} ms, ratio {ratio:.3f}, "
         f"force vjp {t_force:.4f} ms, status {status}")
     out = {
@@ -297,9 +317,9 @@ def bench_adjoint(args) -> int:
         "forward_ms": t_fwd,
         "vjp_ms": t_vjp,
         "force_vjp_ms": t_force,
-        "vjp_workspace_bytes": L.lskum_vjp_workspace_bytes(plan),
+        "vjp_workspace_bytes": t["vjp_workspace_bytes"],
         "status": L.strerror(status),
-        "finite": bool(torch.isfinite(Ub).all()),
+        "finite": t["finite"],
     }
     print(json.dumps(out), flush=True)
     return 0 if status == L.OK and out["finite"] else 1
@@ -355,6 +375,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="1m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint/forward ratio in the 1m line")
     ap.add_argument("--n-inner", type=int, default=None,
                     help="inner least-squares sweeps (default: the workload's)")
     ap.add_argument("--scheme", default="default",
@@ -510,6 +532,17 @@ def main():
         "status": L.strerror(status),
         "residual_history": {"first": float(h[0]), "last": float(h[warm + steps - 1])},
     }
+    # the headline's second figure: the residual VJP against the forward
+    # residual, on this plan at the state the timed iterations reached
+    if wl.name == "1m" and not args.no_adjoint and not options & (L.FIRST_ORDER | L.MINMAX):
+        log("[bench] timing the residual VJP against the forward residual")
+        adj = time_adjoint(plan, U, reps=20, warmup=5)
+        adj["state"] = f"the {wl.name} state after the {warm + steps} iterations above"
+        adj["cotangents"] = "N(0, 1), seed 7"
+        adj["status"] = L.strerror(L.lskum_status(plan))
+        out["adjoint"] = adj
+        log(f"[bench] forward {adj['forward_ms']:.4f} ms, vjp {adj['vjp_ms']:.4f} ms, "
+            f"ratio {adj['ratio']:.3f}")
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on one stage")
         out["cpu_baseline"] = cpu_baseline(cloud, wl, U0_host, options, n_inner)

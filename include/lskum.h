@@ -169,12 +169,13 @@ int lskum_flux_residual(lskum_plan plan, const double *q, const double *dq, cons
  * passes over memory.  R, U and q_next equal those of the three separate
  * calls bit for bit.  Un, U, R and q_next are [n][4] (32-byte aligned), dt
  * is [n]; all device memory owned by the caller.  U holds the previous
- * stage on entry and the new one on return; q_next, a buffer other than q
- * (other points still read q as neighbours), receives the q of the next
- * stage.  Non-physical new states set the status word as lskum_q_vars
- * does.  The stage is always SSP: the plan's LSKUM_RK4 bit is not read
- * here.  Returns LSKUM_ERR_INVALID_ARG for a null or misaligned pointer,
- * stage outside 0..3 or q_next == q. */
+ * stage on entry and the new one on return; q_next receives the q of the
+ * next stage.  U and q_next must be distinct buffers other than q, dq and
+ * qlim, which other points still read as neighbours.  Non-physical new
+ * states set the status word as lskum_q_vars does.  The stage is always
+ * SSP: the plan's LSKUM_RK4 bit is not read here.  Returns
+ * LSKUM_ERR_INVALID_ARG for a null or misaligned pointer, stage outside
+ * 0..3 or U or q_next equal to q, dq, qlim or each other. */
 int lskum_flux_residual_stage(lskum_plan plan, int stage, const double *q, const double *dq,
                               const double *qlim, const double *Un, const double *dt, double *R,
                               double *U, double *q_next, void *stream);

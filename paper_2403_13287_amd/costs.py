@@ -32,7 +32,9 @@ EDGE_FLOPS = 559.1  # flux kernel, FP64 operations per (point, neighbour) pair
 # as the flux launch's epilogue: FP64 operations per point, the difference
 # of the fused and the plain flux launch's SQ_INSTS_VALU_FLOPS_FP64 over the
 # points of the 1M cloud (1.7005e10 - 559.1 x 29,967,646, averaged over the
-# four stages)
+# four stages).  The fused total is what the counters fix; the split moves
+# with the state the plain launch is counted on (the RK4 run's), by about
+# 1.5 operations per edge, 45 per point.
 STAGE_FLOPS = 251.2
 
 

@@ -765,8 +765,12 @@ int lskum_flux_residual_stage(lskum_plan p, int stage, const double *q, const do
                               const double *qlim, const double *Un, const double *dt, double *R,
                               double *U, double *q_next, void *stream) {
   if (!p || !a32(q) || !a64(dq) || !a64(qlim) || !a32(R) || !a32(Un) || !dt || !a32(U) ||
-      !a32(q_next) || q_next == q || stage < 0 || stage > 3)
+      !a32(q_next) || stage < 0 || stage > 3)
     return LSKUM_ERR_INVALID_ARG;
+  // other points read q, dq and qlim as neighbours while U and q_next are written
+  for (const double *w : {static_cast<const double *>(U), static_cast<const double *>(q_next)})
+    if (w == q || w == dq || w == qlim) return LSKUM_ERR_INVALID_ARG;
+  if (U == q_next) return LSKUM_ERR_INVALID_ARG;
   const StageArgs sa{stage, Un, dt, U, q_next};
   return flux_launch(p, q, dq, qlim, R, stream, &sa);
 }

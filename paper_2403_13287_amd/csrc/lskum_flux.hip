@@ -27,9 +27,10 @@ __device__ __forceinline__ unsigned degenerate_splits(const F8 &W, bool interior
 // point's own records and weights are re-read from LDS at every edge
 // instead of being held in registers through the loop.
 // VAR: 0 the default scheme, 1 first-order flux (q~ = q), 2 min-max limiter.
-// FUSE: then the point's SSP stage update (its residual is all it needs)
-// and the q-variables of its new state, into S.q_next (the next stage's q;
-// the q read here stays unchanged for the other threads' neighbour loads).
+// FUSE: then the point's SSP stage update, which reads only the point's own
+// residual, state, U^n and dt, and the q-variables of its new state into
+// S.q_next (the next stage's q; the q read here stays unchanged for the
+// other threads' neighbour loads).
 template <int BLK, int VAR, bool FUSE>
 __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__restrict__ spw,
                                                  const double *__restrict__ q,

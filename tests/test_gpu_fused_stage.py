@@ -93,6 +93,14 @@ def test_fused_stage_rejects_aliased_q():
             R.data_ptr(), U.data_ptr())
     assert lib.lskum_flux_residual_stage(plan.handle, 0, *args, q.data_ptr(), None) == \
         L.ERR_INVALID_ARG
+    # U or q_next on a buffer other points read as neighbours, or on each other
+    qn = plan.field(4)
+    for U_bad, qn_bad in ((q, qn), (dq, qn), (qlim, qn), (U, dq), (U, qlim), (U, U)):
+        bad = args[:-1] + (U_bad.data_ptr(),)
+        assert lib.lskum_flux_residual_stage(plan.handle, 0, *bad, qn_bad.data_ptr(), None) == \
+            L.ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    assert L.lskum_status(plan) == L.OK
     for bad in (-1, 4):
         assert lib.lskum_flux_residual_stage(plan.handle, bad, *args, R.data_ptr(), None) == \
             L.ERR_INVALID_ARG
