@@ -26,6 +26,13 @@
 // Points the paper leaves open (limiter, boundary conditions, local time
 // step, frame at walls, residue definition, force coefficients) follow the
 // readings recorded with the design notes; each is restated at its function.
+//
+// The forward point loops carry OpenMP work-sharing pragmas: every point is
+// computed independently into its own output slots, so a build with -fopenmp
+// gives the same results bit for bit on all host cores (the CPU-throughput
+// comparison).  The parity build ignores them and runs single-threaded.  The
+// reverse-mode and operation-counting routines always run single-threaded
+// (their tape and tally are process globals).
 
 #include "lskum_ref.h"
 
@@ -80,7 +87,7 @@ struct Tape {
   }
 };
 
-Tape *tape = nullptr;  // the oracle is single-threaded
+Tape *tape = nullptr;  // used by single-threaded routines only
 
 struct Var {
   double v;
@@ -135,7 +142,7 @@ namespace cnt {
 struct Tally {
   double add = 0, mul = 0, div = 0, sqrt = 0, exp = 0, log = 0, erf = 0;
 };
-Tally *tally = nullptr;  // the oracle is single-threaded
+Tally *tally = nullptr;  // used by single-threaded routines only
 
 struct Num {
   double v;
@@ -671,6 +678,7 @@ void lskum_ref_init_state(const lskum_ref_cloud *c, const lskum_ref_params *p, d
   double Uinf[4];
   lskum_ref_free_stream(p, Uinf);
   const int32_t n = c->n;
+#pragma omp parallel for schedule(static)
   for (int32_t i = 0; i < n; ++i) {
     for (int m = 0; m < 4; ++m) fld(U, m, n, i) = Uinf[m];
     if (c->kind[i] == 1) {
@@ -686,6 +694,7 @@ unsigned lskum_ref_q_vars(const lskum_ref_cloud *c, const lskum_ref_params *p, c
                           double *q) {
   unsigned flags = 0;
   const int32_t n = c->n;
+#pragma omp parallel for schedule(static) reduction(|: flags)
   for (int32_t i = 0; i < n; ++i) {
     double Ui[4], qi[4];
     for (int m = 0; m < 4; ++m) Ui[m] = fld(U, m, n, i);
@@ -698,6 +707,7 @@ unsigned lskum_ref_q_vars(const lskum_ref_cloud *c, const lskum_ref_params *p, c
 void lskum_ref_q_derivs_first(const lskum_ref_cloud *c, const double *q, double *dq,
                               double *qlim) {
   const int32_t n = c->n;
+#pragma omp parallel for schedule(static)
   for (int32_t i = 0; i < n; ++i) {
     ArraySt st{{q, nullptr, nullptr}, n, i, c->col + c->row_ptr[i]};
     double d[8], l[8];
@@ -712,6 +722,7 @@ void lskum_ref_q_derivs_first(const lskum_ref_cloud *c, const double *q, double 
 void lskum_ref_q_derivs_inner(const lskum_ref_cloud *c, const double *q, const double *dq_prev,
                               double *dq_next) {
   const int32_t n = c->n;
+#pragma omp parallel for schedule(static)
   for (int32_t i = 0; i < n; ++i) {
     ArraySt st{{q, dq_prev, nullptr}, n, i, c->col + c->row_ptr[i]};
     double d[8];
@@ -748,6 +759,7 @@ unsigned lskum_ref_flux_residual(const lskum_ref_cloud *c, const lskum_ref_param
                                  double *R) {
   const int32_t n = c->n;
   unsigned flags = 0;
+#pragma omp parallel for schedule(static) reduction(|: flags)
   for (int32_t i = 0; i < n; ++i) {
     ArraySt st{{q, dq, qlim}, n, i, c->col + c->row_ptr[i]};
     double Ri[4];
@@ -788,6 +800,7 @@ unsigned lskum_ref_flux_op_counts(const lskum_ref_cloud *c, const lskum_ref_para
 void lskum_ref_local_dt(const lskum_ref_cloud *c, const lskum_ref_params *p, const double *U,
                         double *dt) {
   const int32_t n = c->n;
+#pragma omp parallel for schedule(static)
   for (int32_t i = 0; i < n; ++i) {
     Row r = row(*c, i);
     double best = std::numeric_limits<double>::infinity();
@@ -821,6 +834,7 @@ void lskum_ref_rk_stage(const lskum_ref_cloud *c, const lskum_ref_params *p, int
   lskum_ref_free_stream(p, Uinf);
   const double a = stage == 2 ? 2.0 / 3.0 : 0.0;
   const double b = stage == 2 ? 1.0 / 3.0 : 1.0;
+#pragma omp parallel for schedule(static)
   for (int32_t i = 0; i < n; ++i) {
     if (c->kind[i] == 2) {
       for (int m = 0; m < 4; ++m) fld(U, m, n, i) = Uinf[m];
@@ -850,6 +864,7 @@ void lskum_ref_rk4_stage(const lskum_ref_cloud *c, const lskum_ref_params *p, in
   const size_t F = 4 * (size_t)n;
   double Uinf[4];
   lskum_ref_free_stream(p, Uinf);
+#pragma omp parallel for schedule(static)
   for (int32_t i = 0; i < n; ++i) {
     if (c->kind[i] == 2) {
       for (int m = 0; m < 4; ++m) fld(U, m, n, i) = Uinf[m];

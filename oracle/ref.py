@@ -12,7 +12,7 @@ import os
 
 import numpy as np
 
-from .build import LIB, build
+from .build import LIB, LIB_OMP, build
 
 _c_dbl_p = ctypes.POINTER(ctypes.c_double)
 
@@ -49,7 +49,20 @@ def load(rebuild: bool = False) -> ctypes.CDLL:
         return _lib
     if rebuild or not os.path.exists(LIB):
         build()
-    lib = ctypes.CDLL(LIB)
+    _lib = bind(LIB)
+    return _lib
+
+
+def load_omp() -> ctypes.CDLL:
+    """The OpenMP build of the same source (all host cores, same results)."""
+    if not os.path.exists(LIB_OMP):
+        build()
+    return bind(LIB_OMP)
+
+
+def bind(path: str) -> ctypes.CDLL:
+    """Load a build of lskum_ref.cpp at `path` and declare its signatures."""
+    lib = ctypes.CDLL(os.path.abspath(path))
     vp = ctypes.c_void_p
     cp = ctypes.POINTER(_Cloud)
     pp = ctypes.POINTER(_Params)
@@ -82,7 +95,6 @@ def load(rebuild: bool = False) -> ctypes.CDLL:
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args
-    _lib = lib
     return lib
 
 
@@ -150,8 +162,8 @@ class Oracle:
 
     def __init__(self, cloud, mach: float, aoa_deg: float, *, cfl: float = 0.2,
                  venkat_k: float = 5.0, n_inner: int = 2, gamma: float = 1.4,
-                 options: int = 0):
-        self.lib = load()
+                 options: int = 0, lib: ctypes.CDLL | None = None):
+        self.lib = lib if lib is not None else load()
         self.cloud = cloud
         self.n = int(cloud.x.shape[0])
         # keep contiguous copies alive for the lifetime of the struct
@@ -313,7 +325,7 @@ class Oracle:
         """The same cloud and settings at another free stream (AoA in radians)."""
         o = Oracle(self.cloud, mach, math.degrees(aoa_rad), cfl=self.cfl,
                    venkat_k=self.venkat_k, n_inner=self.n_inner, gamma=self.gamma,
-                   options=self.options)
+                   options=self.options, lib=self.lib)
         o._p.aoa_rad = aoa_rad  # exactly, not through degrees
         return o
 

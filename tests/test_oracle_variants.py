@@ -4,7 +4,7 @@ before the defect correction of eq. (14)) and classical RK4 time stepping."""
 import numpy as np
 import pytest
 
-from cloudgen.shapes import from_lists, square_cloud
+from cloudgen.shapes import cylinder_cloud, from_lists, square_cloud
 from oracle import ref
 from oracle.ref import FIRST_ORDER, MINMAX, RK4, Oracle
 
@@ -197,3 +197,62 @@ def test_flux_operation_count_matches_the_formula_structure():
     # the fields agree with the plain evaluation of the same formulas
     R, _ = o.flux_residual(q, dq, qlim)
     assert np.all(np.isfinite(R))
+
+
+def _structure(c):
+    """Edges, used half-plane splits, interior and wall points of a cloud."""
+    edges = splits = pi = pw = 0
+    for i in range(c.n):
+        if c.kind[i] == 2:
+            continue
+        pi += int(c.kind[i] == 0)
+        pw += int(c.kind[i] == 1)
+        tx, ty, nx, ny = c.ny[i], -c.nx[i], c.nx[i], c.ny[i]
+        for k in range(c.nbr_count[i]):
+            j = c.col[c.row_ptr[i] + k]
+            dx, dy = c.x[j] - c.x[i], c.y[j] - c.y[i]
+            ds, dn = dx * tx + dy * ty, dx * nx + dy * ny
+            edges += 1
+            splits += int(ds != 0.0) + int(dn > 0.0 or (dn < 0.0 and c.kind[i] == 0))
+    return edges, splits, pi, pw
+
+
+@pytest.mark.parametrize("which", ["square16", "square12", "square20", "cylinder"])
+def test_flux_arithmetic_count_is_the_hand_count_of_the_formulas(which):
+    """Additions (and subtractions), multiplications and divisions of the
+    flux residual on state-dependent values, counted by hand from the
+    formulas with every limiter increment non-zero (a smooth field):
+
+    per edge, each of the 4 components at both ends: the increment
+    -(dx q_x + dy q_y)/2 (3 mul, 1 add), the bound offsets (2 add), the
+    Venkatakrishnan factor (7 mul, 5 add, 1 div), q~ = q + phi delta
+    (1 mul, 1 add) -- 88 mul, 72 add, 8 div over the edge; the inverse
+    of eq. (13) at both ends (7 mul, 3 add, 4 div each); the velocities
+    in the point's frame (4 mul, 2 add each end):
+        110 mul, 82 add, 16 div;
+    per used split: two split fluxes (27 mul, 9 add, 3 div each) and the
+    least-squares moment sums of the four flux differences (2 mul, 3 add
+    each): 62 mul, 30 add, 6 div;
+    per point and used split: the 2x2 solve per component (2 mul, 2 add,
+    1 div); per point the momentum rotation (4 mul, 2 add).  Interior
+    points use 4 splits (36 mul, 34 add, 16 div), wall points 3
+    (28 mul, 26 add, 12 div).  A dropped or extra term anywhere in these
+    formulas changes a total."""
+    if which == "cylinder":
+        c = cylinder_cloud(M=24, L=6)
+    else:
+        c = square_cloud(15, seed={"square16": 4, "square12": 5, "square20": 6}[which],
+                         k=int(which[6:]), random_frames=True)
+    o = Oracle(c, 0.5, 10.0, n_inner=2)
+    U = prim_to_U(*smooth_prims(c.x, c.y))
+    q, _ = o.q_vars(U)
+    dq, qlim = o.q_derivs(q)
+    counts, flags = o.flux_op_counts(q, dq, qlim)
+    assert flags == 0
+    E, S, PI, PW = _structure(c)
+    assert PI > 0 and S > E
+    assert counts["mul"] == 110 * E + 62 * S + 36 * PI + 28 * PW
+    assert counts["add"] == 82 * E + 30 * S + 34 * PI + 26 * PW
+    assert counts["div"] == 16 * E + 6 * S + 16 * PI + 12 * PW
+    if which == "cylinder":
+        assert PW > 0
