@@ -413,6 +413,28 @@ CONFIGS = {
 }
 
 
+def _make_one(spec):
+    return make_airfoil_cloud(*spec)
+
+
+def make_airfoil_clouds(specs, workers: int | None = None):
+    """make_airfoil_cloud(W, L, k_max, seed) for each (W, L, k_max, seed) in
+    `specs`, in forked worker processes (the same clouds as one by one).
+    Call it before the process initialises a GPU."""
+    specs = [tuple(s) for s in specs]
+    workers = min(len(specs), workers or os.cpu_count() or 1, 16)
+    if workers <= 1:
+        return [_make_one(s) for s in specs]
+    # largest first, so that the big clouds do not end the map alone
+    order = sorted(range(len(specs)), key=lambda k: -specs[k][0] * specs[k][1])
+    with multiprocessing.get_context("fork").Pool(workers) as pool:
+        made = pool.map(_make_one, [specs[k] for k in order], chunksize=1)
+    out = [None] * len(specs)
+    for k, c in zip(order, made):
+        out[k] = c
+    return out
+
+
 def named_cloud(name: str, **kw) -> Cloud:
     W, L, k, seed = CONFIGS[name]
     return make_airfoil_cloud(W, L, k, seed, **kw)

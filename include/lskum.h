@@ -149,7 +149,8 @@ int lskum_q_vars(lskum_plan plan, const double *U, double *q, void *stream);
 /* Least-squares q-derivatives (eq. (9) with dq_i = q_i - q_0, then
  * params.n_inner Jacobi sweeps of eq. (14)-(15)) and the stencil bounds
  * qlim.  `work` is an [n][16] scratch buffer (64-byte aligned; unused when
- * n_inner is 0); the final iterate is in dq. */
+ * n_inner is 0); the final iterate is in dq.  dq, qlim and work must not
+ * share a byte with each other or with q (LSKUM_ERR_INVALID_ARG). */
 int lskum_q_derivs(lskum_plan plan, const double *q, double *dq, double *qlim, double *work,
                    void *stream);
 
@@ -157,7 +158,8 @@ int lskum_q_derivs(lskum_plan plan, const double *q, double *dq, double *qlim, d
  * from eq. (11) on its half-plane stencil of the point's (s, n) frame, with
  * differences of split fluxes of the limited modified q-variables of
  * eq. (14).  Interior points use G_s+-, G_n+-; wall points G_s+-, G_n-;
- * outer points get R = 0. */
+ * outer points get R = 0.  R must not share a byte with q, dq or qlim,
+ * which other points read as neighbours (LSKUM_ERR_INVALID_ARG). */
 int lskum_flux_residual(lskum_plan plan, const double *q, const double *dq, const double *qlim,
                         double *R, void *stream);
 
@@ -170,12 +172,13 @@ int lskum_flux_residual(lskum_plan plan, const double *q, const double *dq, cons
  * calls bit for bit.  Un, U, R and q_next are [n][4] (32-byte aligned), dt
  * is [n]; all device memory owned by the caller.  U holds the previous
  * stage on entry and the new one on return; q_next receives the q of the
- * next stage.  U and q_next must be distinct buffers other than q, dq and
- * qlim, which other points still read as neighbours.  Non-physical new
- * states set the status word as lskum_q_vars does.  The stage is always
- * SSP: the plan's LSKUM_RK4 bit is not read here.  Returns
- * LSKUM_ERR_INVALID_ARG for a null or misaligned pointer, stage outside
- * 0..3 or U or q_next equal to q, dq, qlim or each other. */
+ * next stage.  The three written buffers R, U and q_next must not share a
+ * byte with each other or with q, dq, qlim (which other points still read
+ * as neighbours), Un or dt (a point stores R before it reads its own U, Un
+ * and dt).  Non-physical new states set the status word as lskum_q_vars
+ * does.  The stage is always SSP: the plan's LSKUM_RK4 bit is not read
+ * here.  Returns LSKUM_ERR_INVALID_ARG for a null or misaligned pointer,
+ * stage outside 0..3 or overlapping buffers as above. */
 int lskum_flux_residual_stage(lskum_plan plan, int stage, const double *q, const double *dq,
                               const double *qlim, const double *Un, const double *dt, double *R,
                               double *U, double *q_next, void *stream);
@@ -220,6 +223,15 @@ size_t lskum_workspace_bytes(lskum_plan plan);
  * lskum_workspace_bytes(plan) bytes, 256-byte aligned. */
 int lskum_iterate(lskum_plan plan, int32_t iters, double *U, double *hist, void *ws,
                   void *stream);
+
+/* Batched run: lskum_iterate over every cloud of a (batch) plan, with the
+ * residual history cloud-major: hist[c*iters + k] (device, may be NULL) is
+ * the residual norm of cloud c at iteration k's first stage.  U is the
+ * concatenated state [n][4]; ws as for lskum_iterate.  Each cloud's history
+ * and state equal those of the same cloud in a plan of its own.
+ * LSKUM_ERR_INVALID_ARG also when hist overlaps U or ws. */
+int lskum_batch_run(lskum_plan plan, int32_t iters, double *U, double *hist, void *ws,
+                    void *stream);
 
 /* Capture `iters` iterations of lskum_iterate on U into a HIP graph (one
  * launch replays them all).  Each replay appends the residual norms of its
@@ -293,6 +305,20 @@ int lskum_force_coeffs_vjp(lskum_plan plan, const double *U, const double *Jbar,
 size_t lskum_adjoint_workspace_bytes(lskum_plan plan);
 int lskum_adjoint_iterate(lskum_plan plan, const double *U, const double *g, double *Lambda,
                           int32_t iters, double *hist, void *ws, void *stream);
+
+/* The total derivative of J = sum_c Jbar[2c] Cl_c + Jbar[2c+1] Cd_c with
+ * respect to theta_c = (M, alpha [rad]) at the steady state U, from the
+ * adjoint Lambda of lskum_adjoint_iterate:
+ *   total[2c..2c+1] = dJ/dtheta_c|_U - thetabar_c(Lambda),
+ * the first term the partial of lskum_force_coeffs_vjp, the second the theta
+ * cotangent of lskum_flux_residual_vjp with Rbar = Lambda.  partial (may be
+ * NULL) receives the first term.  U, Lambda: device [n][4]; Jbar, total,
+ * partial: device [n_clouds][2]; ws: device, lskum_adjoint_workspace_bytes
+ * bytes, 256-byte aligned.  LSKUM_ERR_INVALID_ARG for null or misaligned
+ * pointers or when total or partial overlaps another argument. */
+int lskum_adjoint_total(lskum_plan plan, const double *U, const double *Lambda,
+                        const double *Jbar, double *total, double *partial, void *ws,
+                        void *stream);
 
 /* Synchronises `stream`, then returns LSKUM_ERR_NONPHYSICAL or
  * LSKUM_ERR_DEGENERATE if a kernel has recorded one since the last clear,

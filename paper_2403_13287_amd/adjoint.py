@@ -62,7 +62,8 @@ class Adjoint:
 
         The adjoint Lambda of the projected residual is found by `iters`
         pseudo-time steps of lskum_adjoint_iterate (from Lam, or zero); then
-        dJ/dtheta = dJ/dtheta|_U - thetabar(Lambda).  Returns a dict with
+        lskum_adjoint_total forms dJ/dtheta = dJ/dtheta|_U - thetabar(Lambda)
+        on the device.  Returns a dict with
         the total and partial derivatives ((n_clouds, 2) each), Lambda and
         the adjoint residual history ((iters, n_clouds))."""
         p, s = self.plan, self.stream
@@ -79,10 +80,9 @@ class Adjoint:
         hist = torch.empty((max(int(iters), 1), p.n_clouds), dtype=torch.float64, device=dev)
         ws = self.workspace()
         L.lskum_adjoint_iterate(p, U, g, lam, iters, hist, ws, s)
-        Ub = p.field(4)
-        tr = torch.empty(2 * p.n_clouds, dtype=torch.float64, device=dev)
-        L.lskum_flux_residual_vjp(p, U, lam, Ub, tr, ws, s)
-        return {"total": (partial - tr).view(p.n_clouds, 2), "partial": partial.view(p.n_clouds, 2),
+        total = torch.empty(2 * p.n_clouds, dtype=torch.float64, device=dev)
+        L.lskum_adjoint_total(p, U, lam, Jb.view(-1), total, partial, ws, s)
+        return {"total": total.view(p.n_clouds, 2), "partial": partial.view(p.n_clouds, 2),
                 "Lambda": lam, "history": hist[:iters]}
 
     def residual(self, U: torch.Tensor, theta: torch.Tensor) -> torch.Tensor:

@@ -200,13 +200,14 @@ __global__ void __launch_bounds__(kBlock) k_norm_partial(const int2 *__restrict_
 }
 
 // Block c combines the partials of cloud c (chunks [first[c], first[c+1]))
-// in a fixed order and writes its norm to out[row * n_clouds + c], where row
-// is *counter when a counter is given (graph replays append rows; rows past
-// `capacity` are not written), else 0.
+// in a fixed order and writes its norm to out[row * row_stride + c * cloud_stride],
+// where row is *counter when a counter is given (graph replays append rows;
+// rows past `capacity` are not written), else 0.
 __global__ void __launch_bounds__(kBlock) k_norm_final(const int32_t *__restrict__ first,
                                                        const double *__restrict__ partial,
-                                                       int n_clouds, const int32_t *counter,
-                                                       int capacity, double *__restrict__ out) {
+                                                       size_t row_stride, size_t cloud_stride,
+                                                       const int32_t *counter, int capacity,
+                                                       double *__restrict__ out) {
   __shared__ double lds[kBlock];
   const int c = blockIdx.x;
   double s = 0.0;
@@ -214,7 +215,7 @@ __global__ void __launch_bounds__(kBlock) k_norm_final(const int32_t *__restrict
   const double t = block_sum(s, lds);
   if (threadIdx.x == 0) {
     const int row = counter ? *counter : 0;
-    if (row < capacity) out[(size_t)row * n_clouds + c] = sqrt(t);
+    if (row < capacity) out[(size_t)row * row_stride + (size_t)c * cloud_stride] = sqrt(t);
   }
 }
 
@@ -479,11 +480,17 @@ int upload_uinf(lskum_plan_s *p) {
   return LSKUM_OK;
 }
 
+// Layout of a residual-norm history: entry (row, cloud) at
+// row * row_stride + cloud * cloud_stride.
+struct HistLayout {
+  size_t row_stride, cloud_stride;
+};
+
 int norm_launch(lskum_plan_s *p, const double *R, double *out, const int32_t *counter,
-                int capacity, void *stream) {
+                int capacity, void *stream, HistLayout lay) {
   k_norm_partial<<<p->n_chunks, kBlock, 0, S(stream)>>>(p->chunks, p->kind, R, p->partial);
-  k_norm_final<<<p->n_clouds, kBlock, 0, S(stream)>>>(p->chunk_first, p->partial, p->n_clouds,
-                                                      counter, capacity, out);
+  k_norm_final<<<p->n_clouds, kBlock, 0, S(stream)>>>(p->chunk_first, p->partial, lay.row_stride,
+                                                      lay.cloud_stride, counter, capacity, out);
   return launched();
 }
 
@@ -505,11 +512,12 @@ int q_derivs_launch(lskum_plan_s *p, const double *q, double *dq, double *qlim, 
   return rc;
 }
 
-// The iteration body shared by lskum_iterate and graph capture.  With a
-// counter, norms go to hist[*counter] and the counter advances after each
-// iteration (graph replays); without one, iteration k writes hist[k].
+// The iteration body shared by lskum_iterate, lskum_batch_run and graph
+// capture.  With a counter, norms go to row *counter of hist and the counter
+// advances after each iteration (graph replays); without one, iteration k
+// writes row k.
 int run_iterations(lskum_plan_s *p, int32_t iters, double *U, double *hist, int32_t hist_rows,
-                   void *ws, int32_t *counter, void *stream) {
+                   void *ws, int32_t *counter, void *stream, HistLayout lay) {
   const size_t n = (size_t)p->n;
   const size_t f1 = align256(n * sizeof(double));
   char *base = static_cast<char *>(ws);
@@ -540,12 +548,13 @@ int run_iterations(lskum_plan_s *p, int32_t iters, double *U, double *hist, int3
       const StageArgs sa{s, Un, dt, U, q2};
       if ((rc = flux_launch(p, q, dq, qlim, R, stream, rk4 ? nullptr : &sa))) return rc;
       if (s == 0) {
+        const HistLayout scratch{0, 1};
         if (counter)
           rc = norm_launch(p, R, hist ? hist : p->norm_scratch, counter, hist ? hist_rows : 1,
-                           stream);
+                           stream, hist ? lay : scratch);
         else
-          rc = norm_launch(p, R, hist ? hist + (size_t)it * p->n_clouds : p->norm_scratch,
-                           nullptr, 1, stream);
+          rc = norm_launch(p, R, hist ? hist + (size_t)it * lay.row_stride : p->norm_scratch,
+                           nullptr, 1, stream, hist ? lay : scratch);
         if (rc) return rc;
       }
       if (rk4) {
@@ -750,7 +759,13 @@ int lskum_q_vars(lskum_plan p, const double *U, double *q, void *stream) {
 
 int lskum_q_derivs(lskum_plan p, const double *q, double *dq, double *qlim, double *work,
                    void *stream) {
-  if (!p || !a32(q) || !a64(dq) || !a64(qlim) || (p->params[0].n_inner > 0 && !a64(work)))
+  const bool inner = p && p->params[0].n_inner > 0;
+  if (!p || !a32(q) || !a64(dq) || !a64(qlim) || (inner && !a64(work)))
+    return LSKUM_ERR_INVALID_ARG;
+  const size_t n = (size_t)p->n;
+  // neighbours read q and the previous iterate while dq, qlim and work are written
+  if (!writes_disjoint({Span{dq, 64 * n}, Span{qlim, 64 * n}, Span{work, inner ? 128 * n : 0}},
+                       {Span{q, 32 * n}}))
     return LSKUM_ERR_INVALID_ARG;
   return q_derivs_launch(p, q, dq, qlim, work, stream);
 }
@@ -758,6 +773,9 @@ int lskum_q_derivs(lskum_plan p, const double *q, double *dq, double *qlim, doub
 int lskum_flux_residual(lskum_plan p, const double *q, const double *dq, const double *qlim,
                         double *R, void *stream) {
   if (!p || !a32(q) || !a64(dq) || !a64(qlim) || !a32(R)) return LSKUM_ERR_INVALID_ARG;
+  const size_t n = (size_t)p->n;
+  if (!writes_disjoint({Span{R, 32 * n}}, {Span{q, 32 * n}, Span{dq, 64 * n}, Span{qlim, 64 * n}}))
+    return LSKUM_ERR_INVALID_ARG;
   return flux_launch(p, q, dq, qlim, R, stream);
 }
 
@@ -767,10 +785,13 @@ int lskum_flux_residual_stage(lskum_plan p, int stage, const double *q, const do
   if (!p || !a32(q) || !a64(dq) || !a64(qlim) || !a32(R) || !a32(Un) || !dt || !a32(U) ||
       !a32(q_next) || stage < 0 || stage > 3)
     return LSKUM_ERR_INVALID_ARG;
-  // other points read q, dq and qlim as neighbours while U and q_next are written
-  for (const double *w : {static_cast<const double *>(U), static_cast<const double *>(q_next)})
-    if (w == q || w == dq || w == qlim) return LSKUM_ERR_INVALID_ARG;
-  if (U == q_next) return LSKUM_ERR_INVALID_ARG;
+  // other points read q, dq and qlim as neighbours while R, U and q_next are
+  // written; a point stores R before it reads its own U, Un and dt
+  const size_t n = (size_t)p->n;
+  if (!writes_disjoint({Span{R, 32 * n}, Span{U, 32 * n}, Span{q_next, 32 * n}},
+                       {Span{q, 32 * n}, Span{dq, 64 * n}, Span{qlim, 64 * n}, Span{Un, 32 * n},
+                        Span{dt, 8 * n}}))
+    return LSKUM_ERR_INVALID_ARG;
   const StageArgs sa{stage, Un, dt, U, q_next};
   return flux_launch(p, q, dq, qlim, R, stream, &sa);
 }
@@ -799,7 +820,7 @@ int lskum_rk4_stage(lskum_plan p, int stage, const double *Un, const double *R, 
 
 int lskum_residual_norm(lskum_plan p, const double *R, double *out, void *stream) {
   if (!p || !a32(R) || !out) return LSKUM_ERR_INVALID_ARG;
-  return norm_launch(p, R, out, nullptr, 1, stream);
+  return norm_launch(p, R, out, nullptr, 1, stream, HistLayout{0, 1});
 }
 
 int lskum_force_coeffs(lskum_plan p, const double *U, double *clcd, void *stream) {
@@ -816,7 +837,19 @@ size_t lskum_workspace_bytes(lskum_plan p) {
 
 int lskum_iterate(lskum_plan p, int32_t iters, double *U, double *hist, void *ws, void *stream) {
   if (!p || !a32(U) || !ws || iters < 0 || ((uintptr_t)ws % 256) != 0) return LSKUM_ERR_INVALID_ARG;
-  return run_iterations(p, iters, U, hist, iters, ws, nullptr, stream);
+  return run_iterations(p, iters, U, hist, iters, ws, nullptr, stream,
+                        HistLayout{(size_t)p->n_clouds, 1});
+}
+
+int lskum_batch_run(lskum_plan p, int32_t iters, double *U, double *hist, void *ws,
+                    void *stream) {
+  if (!p || !a32(U) || !ws || iters < 0 || ((uintptr_t)ws % 256) != 0) return LSKUM_ERR_INVALID_ARG;
+  if (hist && !writes_disjoint({Span{hist, (size_t)iters * p->n_clouds * sizeof(double)}},
+                               {Span{U, (size_t)p->n * 4 * sizeof(double)},
+                                Span{ws, lskum_workspace_bytes(p)}}))
+    return LSKUM_ERR_INVALID_ARG;
+  return run_iterations(p, iters, U, hist, iters, ws, nullptr, stream,
+                        HistLayout{1, (size_t)iters});
 }
 
 int lskum_graph_create(lskum_graph *out, lskum_plan p, int32_t iters, double *U, double *hist,
@@ -835,7 +868,8 @@ int lskum_graph_create(lskum_graph *out, lskum_plan p, int32_t iters, double *U,
       hipStreamBeginCapture(g->capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
     rc = LSKUM_ERR_HIP;
   if (rc == LSKUM_OK) {
-    const int r2 = run_iterations(p, iters, U, hist, hist_rows, ws, p->counter, g->capture);
+    const int r2 = run_iterations(p, iters, U, hist, hist_rows, ws, p->counter, g->capture,
+                                  HistLayout{(size_t)p->n_clouds, 1});
     const hipError_t e = hipStreamEndCapture(g->capture, &g->graph);
     if (r2 != LSKUM_OK) rc = r2;
     else if (e != hipSuccess) rc = LSKUM_ERR_HIP;

@@ -874,6 +874,18 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_step(Geo G, const double *__
   st4(Ub, i, F4{{sqrt(rr), 0.0, 0.0, 0.0}});
 }
 
+// Total derivative of an output at a steady state, per cloud and theta
+// component k: total = dJ/dtheta|_U - thetabar(Lambda); the partial is also
+// copied out when requested.
+__global__ void k_adjoint_total(int count, const double *__restrict__ part,
+                                const double *__restrict__ tr, double *__restrict__ total,
+                                double *__restrict__ partial) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  total[k] = part[k] - tr[k];
+  if (partial) partial[k] = part[k];
+}
+
 // Least-squares geometry of every point (built once per plan).
 __global__ void __launch_bounds__(kBlock) k_ls_geometry(Geo G, double *__restrict__ lsg) {
   const int n = G.n;
@@ -1243,9 +1255,11 @@ int lskum_flux_residual_vjp(lskum_plan p, const double *U, const double *Rbar, d
   return launched();
 }
 
+// The steady adjoint's workspace: the VJP's, then dt [n], Ubar [n][4] and
+// two [n_clouds][2] theta cotangents.
 size_t lskum_adjoint_workspace_bytes(lskum_plan p) {
   if (!p) return 0;
-  return vjp_bytes(p) + 5 * f1_bytes(p);
+  return vjp_bytes(p) + 5 * f1_bytes(p) + align256(4 * (size_t)p->n_clouds * sizeof(double));
 }
 
 int lskum_adjoint_iterate(lskum_plan p, const double *U, const double *g, double *Lambda,
@@ -1268,6 +1282,29 @@ int lskum_adjoint_iterate(lskum_plan p, const double *U, const double *g, double
     if (hist && (rc = lskum_residual_norm(p, Ub, hist + (size_t)k * p->n_clouds, stream)))
       return rc;
   }
+  return launched();
+}
+
+int lskum_adjoint_total(lskum_plan p, const double *U, const double *Lambda, const double *Jbar,
+                        double *total, double *partial, void *ws, void *stream) {
+  if (!p || !a32(U) || !a32(Lambda) || !Jbar || !total || !ws || ((uintptr_t)ws % 256) != 0)
+    return LSKUM_ERR_INVALID_ARG;
+  const size_t nc2 = 2 * (size_t)p->n_clouds * sizeof(double);
+  if (!writes_disjoint({Span{total, nc2}, Span{partial, partial ? nc2 : 0}},
+                       {Span{U, 32 * (size_t)p->n}, Span{Lambda, 32 * (size_t)p->n},
+                        Span{Jbar, nc2}, Span{ws, lskum_adjoint_workspace_bytes(p)}}))
+    return LSKUM_ERR_INVALID_ARG;
+  char *extra = static_cast<char *>(ws) + vjp_bytes(p);
+  double *Ub = reinterpret_cast<double *>(extra + f1_bytes(p));
+  double *part = reinterpret_cast<double *>(extra + 5 * f1_bytes(p));
+  double *tr = part + 2 * (size_t)p->n_clouds;
+  int rc;
+  // the partial at fixed U (its U cotangent, written to Ub, is not needed)
+  if ((rc = lskum_force_coeffs_vjp(p, U, Jbar, Ub, part, stream))) return rc;
+  // theta cotangent of the residual with Rbar = Lambda
+  if ((rc = lskum_flux_residual_vjp(p, U, Lambda, Ub, tr, ws, stream))) return rc;
+  const int count = 2 * p->n_clouds;
+  k_adjoint_total<<<(count + 63) / 64, 64, 0, S(stream)>>>(count, part, tr, total, partial);
   return launched();
 }
 

@@ -80,6 +80,7 @@ _SIGS = {
     "lskum_force_coeffs": (ctypes.c_int, "vvvv"),
     "lskum_workspace_bytes": (ctypes.c_size_t, "v"),
     "lskum_iterate": (ctypes.c_int, "vivvvv"),
+    "lskum_batch_run": (ctypes.c_int, "vivvvv"),
     "lskum_graph_create": (ctypes.c_int, "vvivvivv"),
     "lskum_graph_launch": (ctypes.c_int, "vv"),
     "lskum_graph_destroy": (ctypes.c_int, "v"),
@@ -92,6 +93,7 @@ _SIGS = {
     "lskum_force_coeffs_vjp": (ctypes.c_int, "vvvvvv"),
     "lskum_adjoint_workspace_bytes": (ctypes.c_size_t, "v"),
     "lskum_adjoint_iterate": (ctypes.c_int, "vvvvivvv"),
+    "lskum_adjoint_total": (ctypes.c_int, "vvvvvvvv"),
 }
 _CT = {"v": ctypes.c_void_p, "i": ctypes.c_int32, "d": ctypes.c_double}
 
@@ -350,6 +352,15 @@ def lskum_iterate(plan: Plan, iters: int, U, hist, ws, stream=None):
                                   _stream(stream)), "lskum_iterate")
 
 
+def lskum_batch_run(plan: Plan, iters: int, U, hist, ws, stream=None):
+    """hist: n_clouds x iters residual norms, cloud-major (or None)."""
+    hp = 0 if hist is None else _scalar_out(plan, hist, int(iters) * plan.n_clouds, "hist")
+    if not isinstance(ws, torch.Tensor) or not ws.is_cuda or ws.numel() < lskum_workspace_bytes(plan):
+        raise ValueError("ws: need a cuda tensor of lskum_workspace_bytes(plan) bytes")
+    _check(plan.lib.lskum_batch_run(plan.handle, int(iters), plan._arg(U, 4, "U"), hp,
+                                    ws.data_ptr(), _stream(stream)), "lskum_batch_run")
+
+
 def lskum_set_far_field(plan: Plan, U, stream=None):
     _check(plan.lib.lskum_set_far_field(plan.handle, plan._arg(U, 4, "U"), _stream(stream)),
            "lskum_set_far_field")
@@ -411,6 +422,19 @@ def lskum_adjoint_iterate(plan: Plan, U, g, Lam, iters: int, hist, ws, stream=No
     _check(plan.lib.lskum_adjoint_iterate(plan.handle, plan._arg(U, 4, "U"), plan._arg(g, 4, "g"),
                                           plan._arg(Lam, 4, "Lambda"), int(iters), hp,
                                           ws.data_ptr(), _stream(stream)), "lskum_adjoint_iterate")
+
+
+def lskum_adjoint_total(plan: Plan, U, Lam, Jbar, total, partial, ws, stream=None):
+    """total (and partial, or None): (n_clouds, 2) derivatives of Jbar . (Cl, Cd)."""
+    pp = 0 if partial is None else _scalar_out(plan, partial, 2 * plan.n_clouds, "partial")
+    if not isinstance(ws, torch.Tensor) or not ws.is_cuda or \
+            ws.numel() < lskum_adjoint_workspace_bytes(plan):
+        raise ValueError("ws: need a cuda tensor of lskum_adjoint_workspace_bytes(plan) bytes")
+    _check(plan.lib.lskum_adjoint_total(plan.handle, plan._arg(U, 4, "U"),
+                                        plan._arg(Lam, 4, "Lambda"),
+                                        _scalar_out(plan, Jbar, 2 * plan.n_clouds, "Jbar"),
+                                        _scalar_out(plan, total, 2 * plan.n_clouds, "total"), pp,
+                                        ws.data_ptr(), _stream(stream)), "lskum_adjoint_total")
 
 
 def lskum_status(plan: Plan, stream=None) -> int:

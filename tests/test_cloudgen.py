@@ -137,3 +137,13 @@ def test_restricted_cloud_reproduces_the_residual_at_its_seeds(tiny_cloud):
     os_ = Oracle(sub, 0.63, 2.0, n_inner=2)
     Rs, _ = os_.residual(U[:, ids])
     assert np.array_equal(Rs[:, pos], R[:, seeds])
+
+
+def test_clouds_made_in_workers_equal_clouds_made_one_by_one():
+    from cloudgen import make_airfoil_clouds
+    specs = [(40, 16, 25, 3), (64, 24, 25, 12), (32, 20, 30, 5)]
+    par = make_airfoil_clouds(specs, workers=3)
+    for spec, c in zip(specs, par):
+        s = make_airfoil_cloud(*spec)
+        for f in ("x", "y", "nx", "ny", "kind", "row_ptr", "col", "nbr_count", "wall_loop"):
+            np.testing.assert_array_equal(getattr(c, f), getattr(s, f))

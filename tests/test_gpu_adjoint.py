@@ -139,6 +139,42 @@ def test_10k_vjp_matches_oracle(cut10k):
     np.testing.assert_allclose(tb.cpu().numpy(), tb_o, rtol=TOL)
 
 
+def test_adjoint_total_is_partial_minus_theta_cotangent(cut10k):
+    """lskum_adjoint_total on an arbitrary adjoint field Lambda: the same
+    values as the two VJP entry points it combines (bit for bit) and the
+    oracle's partial minus its residual theta cotangent."""
+    c, params, U = cut10k
+    ad = Adjoint(c, params)
+    rng = np.random.default_rng(21)
+    Lam = torch.from_numpy(rng.standard_normal((c.n, 4))).cuda()
+    Jb = torch.tensor([0.7, -1.9], dtype=torch.float64, device="cuda")
+    ws = ad.workspace()
+    total = torch.empty(2, dtype=torch.float64, device="cuda")
+    partial = torch.empty(2, dtype=torch.float64, device="cuda")
+    L.lskum_adjoint_total(ad.plan, U, Lam, Jb, total, partial, ws)
+    Fb, fb = ad.plan.field(4), torch.empty(2, dtype=torch.float64, device="cuda")
+    L.lskum_force_coeffs_vjp(ad.plan, U, Jb, Fb, fb)
+    Ub, tb = ad.plan.field(4), torch.empty(2, dtype=torch.float64, device="cuda")
+    L.lskum_flux_residual_vjp(ad.plan, U, Lam, Ub, tb, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(partial, fb)
+    assert torch.equal(total, fb - tb)
+    o = Oracle(c, params.mach, params.aoa_deg, n_inner=params.n_inner)
+    Uh = down(U)
+    _, part_o = o.force_coeffs_vjp(Uh, Jb.cpu().numpy())
+    _, tr_o, flags = o.residual_vjp(Uh, down(Lam))
+    assert flags == 0
+    np.testing.assert_allclose(total.cpu().numpy(), part_o - tr_o,
+                               rtol=TOL, atol=TOL * np.max(np.abs(tr_o)))
+    # outputs overlapping an input are rejected
+    lib = ad.plan.lib
+    assert lib.lskum_adjoint_total(ad.plan.handle, U.data_ptr(), Lam.data_ptr(), Jb.data_ptr(),
+                                   Jb.data_ptr(), None, ws.data_ptr(), None) == L.ERR_INVALID_ARG
+    assert lib.lskum_adjoint_total(ad.plan.handle, U.data_ptr(), Lam.data_ptr(), Jb.data_ptr(),
+                                   total.data_ptr(), total.data_ptr(), ws.data_ptr(),
+                                   None) == L.ERR_INVALID_ARG
+
+
 def test_10k_vjp_finite_difference_columns(cut10k):
     c, params, U = cut10k
     ad = Adjoint(c, params)

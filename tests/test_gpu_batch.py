@@ -131,3 +131,56 @@ def test_set_params_per_cloud(batch):
     bad = [L.Params(0.5, 0.0, n_inner=2)] * (len(clouds) - 1) + [L.Params(0.5, 0.0, n_inner=3)]
     with pytest.raises(L.LskumError):
         s.plan.set_params(bad)
+
+
+def test_batch_run_is_the_iteration_with_cloud_major_history(batch):
+    clouds, params = batch
+    plan = L.Plan(clouds, params)
+    nc = len(clouds)
+    Ua, Ub = plan.field(4), plan.field(4)
+    L.lskum_init_state(plan, Ua)
+    Ub.copy_(Ua)
+    ws = L.workspace(plan)
+    ha = torch.full((5, nc), float("nan"), dtype=torch.float64, device="cuda")
+    hb = torch.full((nc, 5), float("nan"), dtype=torch.float64, device="cuda")
+    L.lskum_iterate(plan, 5, Ua, ha, ws)
+    L.lskum_batch_run(plan, 5, Ub, hb, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(Ua, Ub)
+    assert torch.equal(hb, ha.T.contiguous())
+    assert L.lskum_status(plan) == L.OK
+    # hist on the state or the workspace is rejected before any launch
+    lib = plan.lib
+    assert lib.lskum_batch_run(plan.handle, 5, Ub.data_ptr(), Ub.data_ptr(), ws.data_ptr(),
+                               None) == L.ERR_INVALID_ARG
+    assert lib.lskum_batch_run(plan.handle, 5, Ub.data_ptr(), ws.data_ptr() + 256, ws.data_ptr(),
+                               None) == L.ERR_INVALID_ARG
+
+
+@pytest.mark.timeout(900)
+def test_64_cloud_batch_smallest_and_largest_members_against_oracle():
+    """The 64-cloud batch workload (5k-250k points, log-uniform, each with
+    its own Mach number and angle of attack) advanced 2 iterations in one
+    plan; its smallest and largest members against the oracle."""
+    from cloudgen import batch_sizes, make_airfoil_clouds
+    draws = batch_sizes()
+    say("generating the 64 batch clouds")
+    clouds = make_airfoil_clouds([(d["W"], d["L"], 25, d["seed"]) for d in draws])
+    params = [L.Params(d["mach"], d["aoa_deg"], 0.2, 5.0, 2) for d in draws]
+    sizes = [c.n for c in clouds]
+    say("batch of", sum(sizes), "points")
+    b = Solver(clouds, params)
+    hb = b.run(2)
+    torch.cuda.synchronize()
+    assert b.status() == L.OK
+    for c in (int(np.argmin(sizes)), int(np.argmax(sizes))):
+        p = params[c]
+        say(f"member {c}: {sizes[c]} points, M {p.mach:.3f}, AoA {p.aoa_deg:.2f}")
+        o = Oracle(clouds[c], p.mach, p.aoa_deg, cfl=p.cfl, venkat_k=p.venkat_k,
+                   n_inner=p.n_inner)
+        Uo, ho, flags = o.iterate(o.init_state(), 2)
+        assert flags == 0
+        Ug = b.cloud_state(c).cpu().numpy().T
+        for m in range(4):
+            assert np.max(np.abs(Ug[m] - Uo[m])) <= 1e-10 * np.max(np.abs(Uo[m])), (c, m)
+        np.testing.assert_allclose(hb[:, c].cpu().numpy(), ho, rtol=1e-8)

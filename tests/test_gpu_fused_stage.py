@@ -81,7 +81,7 @@ def test_fused_stage_on_a_batch():
         _run_both(plan, U)
 
 
-def test_fused_stage_rejects_aliased_q():
+def test_fused_stage_rejects_aliased_buffers():
     if not torch.cuda.is_available():
         pytest.fail("GPU tests need a GPU")
     c = named_cloud("tiny")
@@ -99,6 +99,33 @@ def test_fused_stage_rejects_aliased_q():
         bad = args[:-1] + (U_bad.data_ptr(),)
         assert lib.lskum_flux_residual_stage(plan.handle, 0, *bad, qn_bad.data_ptr(), None) == \
             L.ERR_INVALID_ARG
+    # R on any other buffer of the launch, or partly overlapping one
+    qn_ok = qn.data_ptr()
+    names = ("q", "dq", "qlim", "Un", "dt", "R", "U")
+    for k, other in enumerate((q, dq, qlim, Un, dt, None, U)):
+        if other is None:
+            continue
+        for off in (0, 32 * 7):
+            bad = list(args)
+            bad[5] = other.data_ptr() + off
+            assert lib.lskum_flux_residual_stage(plan.handle, 0, *bad, qn_ok, None) == \
+                L.ERR_INVALID_ARG, f"R on {names[k]} + {off} B"
+    # U or q_next overlapping the tail of another buffer, and q_next on R
+    big = plan.field(8)
+    bad = list(args)
+    bad[6] = big.data_ptr() + 32 * 4
+    assert lib.lskum_flux_residual_stage(plan.handle, 0, *bad, big.data_ptr(), None) == \
+        L.ERR_INVALID_ARG
+    assert lib.lskum_flux_residual_stage(plan.handle, 0, *args, R.data_ptr(), None) == \
+        L.ERR_INVALID_ARG
+    # the plain flux residual and the derivative passes check their outputs too
+    assert lib.lskum_flux_residual(plan.handle, q.data_ptr(), dq.data_ptr(), qlim.data_ptr(),
+                                   dq.data_ptr(), None) == L.ERR_INVALID_ARG
+    work = plan.field(16)
+    assert lib.lskum_q_derivs(plan.handle, q.data_ptr(), dq.data_ptr(), dq.data_ptr(),
+                              work.data_ptr(), None) == L.ERR_INVALID_ARG
+    assert lib.lskum_q_derivs(plan.handle, q.data_ptr(), dq.data_ptr(), qlim.data_ptr(),
+                              q.data_ptr(), None) == L.ERR_INVALID_ARG
     torch.cuda.synchronize()
     assert L.lskum_status(plan) == L.OK
     for bad in (-1, 4):

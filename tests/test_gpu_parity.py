@@ -217,7 +217,10 @@ def test_solver_run_is_deterministic(tiny):
 
 def test_parity_1m_bench_configuration():
     """The 1M-point workload in the launch configuration the benchmark
-    times (lskum_iterate), then every kernel on the state it produced."""
+    times (lskum_iterate), then every kernel on the state it produced, and
+    one more whole iteration through lskum_iterate (local time step and the
+    four fused flux + SSP stage launches) against the oracle's iteration
+    from the same state."""
     wl = WORKLOADS["1m"]
     say("generating the 1M cloud")
     cloud = wl.cloud()
@@ -239,6 +242,13 @@ def test_parity_1m_bench_configuration():
     # the next iteration's history entry is the norm of R(U5)
     h = s.run(1)
     assert float(host(h)[0]) == pytest.approx(o.residual_norm(Ro), rel=HIST_TOL)
+    say("oracle iteration at 1M")
+    U6o, h6o, flags = o.iterate(U5, 1)
+    assert flags == 0
+    assert float(host(h)[0]) == pytest.approx(h6o[0], rel=HIST_TOL)
+    U6 = down(s.U)
+    assert_field("U after one lskum_iterate iteration at 1M", U6, U6o)
+    assert normwise(U6 - U5, U6o - U5) <= 1e-8  # the increment itself, not only the state
     dt = s.plan.field(1)
     L.lskum_local_dt(s.plan, up(U5), dt)
     np.testing.assert_allclose(host(dt), o.local_dt(U5), rtol=1e-12)
@@ -282,6 +292,22 @@ def test_parity_16m_sampled_points():
     assert_field("dq 16M", host(dq[sidx]).T, dqo[:, pos])
     assert_field("qlim 16M", host(qlim[sidx]).T, qlimo[:, pos])
     assert_field("R 16M", host(R[sidx]).T, Ro[:, pos])
+    # the fused flux + SSP stage launch the iteration driver uses: the
+    # first stage from this state, with its local time step
+    say("fused stage at 16M")
+    dt = s.plan.field(1)
+    L.lskum_local_dt(s.plan, s.U, dt)
+    Un, U1, R1, qn = s.U.clone(), s.U.clone(), s.plan.field(4), s.plan.field(4)
+    L.lskum_flux_residual_stage(s.plan, 0, q, dq, qlim, Un, dt, R1, U1, qn)
+    assert s.status() == L.OK
+    dto = o.local_dt(U_sub)
+    np.testing.assert_allclose(host(dt[sidx]), dto[pos], rtol=1e-12)
+    U1o = o.rk_stage(0, U_sub, Ro, dto, U_sub)
+    q1o, _ = o.q_vars(U1o)
+    assert_field("R fused 16M", host(R1[sidx]).T, Ro[:, pos])
+    assert_field("U stage 16M", host(U1[sidx]).T, U1o[:, pos])
+    assert_field("U stage increment 16M", host(U1[sidx] - Un[sidx]).T, (U1o - U_sub)[:, pos], 1e-8)
+    assert_field("q next stage 16M", host(qn[sidx]).T, q1o[:, pos])
 
 
 @pytest.mark.parametrize("block", [128, 256])
