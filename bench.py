@@ -17,7 +17,16 @@ Besides the throughput the JSON line carries:
   events around every flux launch in the timed region, against the MI355X
   FP64 vector peak;
 * cpu_baseline: the FP64 oracle timed on this host on a bounded sample
-  (one stage over the whole cloud, single thread).
+  (whole RK stages over the cloud), single-threaded and, as `all_cores`,
+  its OpenMP build on every host core, with the host's CPU model and count.
+The default 1m line also carries (after the timed region):
+* sustained: 1000 more iterations through the library's own loop;
+* adjoint: the residual VJP against one forward residual (the metric's
+  second figure);
+* 16m: the 16M-point cloud, 2 warm-up + 10 timed iterations, with its flux
+  roofline and compulsory HBM rate;
+* batch: 64 uneven clouds in one plan (graph replays, autotuned) against
+  the same clouds advanced one after the other, 500 iterations.
 """
 from __future__ import annotations
 
@@ -40,17 +49,32 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cloud, wl, U_host, options: int = 0, n_inner=None, min_seconds: float = 10.0):
-    """The oracle, as it stands, on whole RK stages of the workload (same
-    scheme options and inner sweeps as the GPU run): repeated until at least
-    `min_seconds` of single-thread CPU work (one stage over the 1M cloud
-    takes about 4 s)."""
+# worker processes for cloud generation (before the GPU is initialised)
+GEN_WORKERS = 16
+
+
+def host_info() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "cpus_available": len(os.sched_getaffinity(0))}
+
+
+def oracle_stages(cloud, wl, U_host, options: int, n_inner: int, min_seconds: float, lib=None):
+    """Whole RK stages of the oracle from U_host, repeated until at least
+    `min_seconds`; returns (stages, seconds)."""
     import numpy as np
     from oracle.ref import FIRST_ORDER, RK4, Oracle
 
-    n_inner = wl.n_inner if n_inner is None else n_inner
     o = Oracle(cloud, wl.mach, wl.aoa_deg, cfl=wl.cfl, venkat_k=wl.venkat_k,
-               n_inner=n_inner, gamma=wl.gamma, options=options)
+               n_inner=n_inner, gamma=wl.gamma, options=options, lib=lib)
     U = U_host.copy()
     Un = U_host.copy()
     dt = None
@@ -76,14 +100,34 @@ def cpu_baseline(cloud, wl, U_host, options: int = 0, n_inner=None, min_seconds:
         stages += 1
         sec = time.perf_counter() - t0
         if sec >= min_seconds:
-            break
-    return {"value": cloud.n * stages / sec, "unit": "point-stage updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{stages} RK stages (local time step per 4 stages, q-variables, first-order "
-                      f"+ {n_inner} inner LS sweeps, flux residual, stage update) over all "
-                      f"{cloud.n} points of the {wl.name} cloud from the initial state"
-                      + (f", options {options}" if options else "")
-                      + f", single thread, {sec:.1f} s"}
+            return stages, sec
+
+
+def cpu_baseline(cloud, wl, U_host, options: int = 0, n_inner=None, min_seconds: float = 10.0,
+                 all_cores: bool = True):
+    """The oracle, as it stands, on whole RK stages of the workload (same
+    scheme options and inner sweeps as the GPU run), single-threaded (the
+    parity build), repeated until at least `min_seconds` (one stage over the
+    1M cloud takes about 4 s); with `all_cores` also the OpenMP build of the
+    same source on every host core the process may use."""
+    from oracle import ref
+
+    n_inner = wl.n_inner if n_inner is None else n_inner
+    what = (f"RK stages (local time step per 4 stages, q-variables, first-order + {n_inner} "
+            f"inner LS sweeps, flux residual, stage update) over all {cloud.n} points of the "
+            f"{wl.name} cloud from the initial state" + (f", options {options}" if options else ""))
+    stages, sec = oracle_stages(cloud, wl, U_host, options, n_inner, min_seconds)
+    out = {"value": cloud.n * stages / sec, "unit": "point-stage updates/s", "cores": 1,
+           "kind": "oracle", "sample": f"{stages} {what}, single thread, {sec:.1f} s",
+           "host": host_info()}
+    if all_cores:
+        lib = ref.load_omp()
+        threads = int(lib.lskum_ref_threads())
+        stages, sec = oracle_stages(cloud, wl, U_host, options, n_inner, min_seconds, lib=lib)
+        out["all_cores"] = {"value": cloud.n * stages / sec, "unit": "point-stage updates/s",
+                            "cores": threads, "kind": "oracle (OpenMP build of the same source)",
+                            "sample": f"{stages} {what}, {threads} threads, {sec:.1f} s"}
+    return out
 
 
 ELEMENTARY_RANGES = {
@@ -135,27 +179,22 @@ def calibrate_elementary(n: int = 1 << 24) -> int:
     return 0
 
 
-def bench_batch(args) -> int:
-    """64 uneven airfoil clouds advanced together (one graph launch per
-    replay, autotuned tile size and XCD mapping) against the same 64 clouds
-    advanced one after the other (each with its own graph)."""
+def run_batch(clouds, draws, iters: int) -> dict:
+    """The batch workload on clouds already generated: one plan over all the
+    clouds (autotuned, one graph launch per replay of `per_graph`
+    iterations) against the clouds advanced one after the other (each with
+    its own graph of the same kernels); states must agree bit for bit."""
     import numpy as np
     import torch
 
-    from cloudgen import batch_sizes, make_airfoil_cloud
     from paper_2403_13287_amd import lskum as L
     from paper_2403_13287_amd.solver import Solver
 
-    torch.cuda.set_device(0)
-    iters = 500 if args.steps is None else args.steps
     per_graph = 25 if iters % 25 == 0 else 1
     replays = iters // per_graph
-    draws = batch_sizes()
-    log(f"[bench] generating {len(draws)} clouds")
-    clouds = [make_airfoil_cloud(d["W"], d["L"], 25, d["seed"]) for d in draws]
     params = [L.Params(d["mach"], d["aoa_deg"], 0.2, 5.0, 2) for d in draws]
     total = sum(c.n for c in clouds)
-    log(f"[bench] {total} points in {len(clouds)} clouds ({min(c.n for c in clouds)}-"
+    log(f"[bench] batch: {total} points in {len(clouds)} clouds ({min(c.n for c in clouds)}-"
         f"{max(c.n for c in clouds)}), {iters} iterations")
 
     batch = Solver(clouds, params)
@@ -172,6 +211,7 @@ def bench_batch(args) -> int:
 
     t_loop = 0.0
     loop_status = L.OK
+    identical = True
     for c, (cloud, p) in enumerate(zip(clouds, params)):
         s = Solver(cloud, p)
         g, h = s.capture(per_graph, replays)
@@ -184,33 +224,74 @@ def bench_batch(args) -> int:
         loop_status = loop_status or s.status()
         if not torch.equal(s.U, batch.cloud_state(c)):
             log(f"[bench] cloud {c}: batched and single states differ")
-            loop_status = L.ERR_INVALID_ARG
+            identical = False
         del g, s
-    value = total * 4.0 * iters / t_batch
     out = {
-        "metric": "batched point-RK-stage updates/s FP64, 64 uneven airfoil clouds",
-        "value": value,
+        "value": total * 4.0 * iters / t_batch,
         "unit": "point-stage updates/s",
-        "n_gpus": 1,
-        "steps": iters,
-        "higher_is_better": True,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "batch: 64 NACA 0012 clouds, 5k-250k points log-uniform, "
-                               "M U[0.3, 0.9], AoA U[-4, 6] deg, k_max 25, n_inner 2, CFL 0.2",
-                   "points": total, "clouds": len(clouds), "iterations_per_graph": per_graph},
+        "iterations": iters,
+        "points": total,
+        "clouds": len(clouds),
+        "iterations_per_graph": per_graph,
         "batch_seconds": t_batch,
         "loop_seconds": t_loop,
         "loop_value": total * 4.0 * iters / t_loop,
         "speedup_vs_loop": t_loop / t_batch,
         "tuning": {"block": best.block, "xcd_contiguous": best.xcd_contiguous},
         "autotune_ms_per_2_iterations": {f"{k[0]}/{k[1]}": v for k, v in tune_ms.items()},
+        "batched_equals_looped": identical,
         "status": L.strerror(status),
         "loop_status": L.strerror(loop_status),
         "residual_last": float(np.nanmax(hist[-1].cpu().numpy())),
     }
+    del graph, batch
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
+BATCH_CONFIG = ("batch: 64 NACA 0012 clouds, 5k-250k points log-uniform, M U[0.3, 0.9], "
+                "AoA U[-4, 6] deg, k_max 25, n_inner 2, CFL 0.2")
+
+
+def batch_clouds():
+    from cloudgen import batch_sizes, make_airfoil_clouds
+
+    draws = batch_sizes()
+    log(f"[bench] generating the {len(draws)} batch clouds")
+    clouds = make_airfoil_clouds([(d["W"], d["L"], 25, d["seed"]) for d in draws],
+                                 workers=GEN_WORKERS)
+    return clouds, draws
+
+
+def bench_batch(args) -> int:
+    """64 uneven airfoil clouds advanced together (one graph launch per
+    replay, autotuned tile size and XCD mapping) against the same 64 clouds
+    advanced one after the other (each with its own graph)."""
+    import torch
+
+    from paper_2403_13287_amd import lskum as L
+
+    clouds, draws = batch_clouds()
+    torch.cuda.set_device(0)
+    iters = 500 if args.steps is None else args.steps
+    r = run_batch(clouds, draws, iters)
+    out = {
+        "metric": "batched point-RK-stage updates/s FP64, 64 uneven airfoil clouds",
+        "value": r["value"],
+        "unit": "point-stage updates/s",
+        "n_gpus": 1,
+        "steps": iters,
+        "higher_is_better": True,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": BATCH_CONFIG, "points": r["points"], "clouds": r["clouds"],
+                   "iterations_per_graph": r["iterations_per_graph"]},
+    }
+    out.update({k: v for k, v in r.items() if k not in out and k != "unit"})
     print(json.dumps(out), flush=True)
-    return 0 if status == L.OK and loop_status == L.OK else 1
+    ok = r["status"] == L.strerror(L.OK) and r["loop_status"] == L.strerror(L.OK)
+    return 0 if ok and r["batched_equals_looped"] else 1
 
 
 def time_adjoint(plan, U, reps: int, warmup: int, force: bool = False) -> dict:
@@ -368,84 +449,35 @@ def bench_ksweep(args) -> int:
     return 0
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None, help="timed iterations (default: the workload's)")
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="1m")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-adjoint", action="store_true",
-                    help="skip the adjoint/forward ratio in the 1m line")
-    ap.add_argument("--n-inner", type=int, default=None,
-                    help="inner least-squares sweeps (default: the workload's)")
-    ap.add_argument("--scheme", default="default",
-                    choices=("default", "first-order", "minmax", "rk4"),
-                    help="scheme variant of the sweep (default: the paper's second-order "
-                         "scheme with the Venkatakrishnan limiter and SSPRK(4,3); rk4: the "
-                         "same residual with classical RK4 stages)")
-    ap.add_argument("--copy-bytes", type=int, default=0,
-                    help="instead of the sweep, run 5 plain device copies of this many bytes "
-                         "(calibrates the HBM traffic counters)")
-    ap.add_argument("--calibrate-elementary", action="store_true",
-                    help="instead of the sweep, run the FP64 elementary-function calibration "
-                         "kernels once each over 2^24 inputs (profile with rocprofv3 --pmc)")
-    args = ap.parse_args()
-    if args.calibrate_elementary:
-        return calibrate_elementary()
-    if args.copy_bytes:
-        import torch
-        torch.cuda.set_device(0)
-        src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": src.numel() * 8, "copies": 5}), flush=True)
-        return 0
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the sweep is not "
-              "sharded across GPUs in this build", file=sys.stderr)
-        sys.exit(2)
-    if args.workload == "batch":
-        return bench_batch(args)
-    if args.workload == "adjoint":
-        return bench_adjoint(args)
-    if args.workload == "ksweep":
-        return bench_ksweep(args)
+SUSTAINED_ITERS = 1000
+BATCH_ITERS = 500
 
+
+def run_sweep(cloud, wl, steps: int, warm: int, options: int, n_inner: int,
+              keep_initial: bool = True) -> dict:
+    """Time `steps` iterations (after `warm` untimed ones) of the whole
+    iteration on `cloud` from the initial state, issued from Python one
+    entry point at a time, with HIP events around every flux launch."""
     import numpy as np
     import torch
 
-    from cloudgen.workloads import WORKLOADS
     from paper_2403_13287_amd import costs
     from paper_2403_13287_amd import lskum as L
 
-    wl = WORKLOADS[args.workload]
-    steps = wl.iters if args.steps is None else args.steps
-    warm = args.warmup
-    # the cloud is built (in worker processes for large clouds) before the
-    # GPU is touched
-    log(f"[bench] generating the {wl.name} cloud ({wl.W} x {wl.L})")
-    cloud = wl.cloud()
-    torch.cuda.set_device(0)
     n = cloud.n
     edges = int(cloud.nbr_count.astype(np.int64).sum())
-    options = {"default": 0, "first-order": L.FIRST_ORDER, "minmax": L.MINMAX,
-               "rk4": L.RK4}[args.scheme]
-    n_inner = wl.n_inner if args.n_inner is None else args.n_inner
     p = L.Params(wl.mach, wl.aoa_deg, wl.cfl, wl.venkat_k, n_inner, wl.gamma, options=options)
     plan = L.Plan(cloud, p)
     U = plan.field(4)
     L.lskum_init_state(plan, U)
-    U0_host = U.cpu().numpy().T.copy()  # oracle layout (4, n)
+    # the initial state in the oracle's layout (4, n), for the CPU baseline
+    U0_host = U.cpu().numpy().T.copy() if keep_initial else None
     Un, q, dq, qlim, work, R = (plan.field(c) for c in (4, 4, 8, 8, 16, 4))
     dt, acc, q2 = plan.field(1), plan.field(4), plan.field(4)
     rk4 = bool(options & L.RK4)
     hist = torch.zeros(max(steps + warm, 1), dtype=torch.float64, device="cuda")
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(4 * steps)]
-
     qs = (q, q2)
 
     def step(k, timed):
@@ -488,21 +520,112 @@ def main():
     flux_ms = float(np.mean([a.elapsed_time(b) for a, b in ev])) if ev else float("nan")
     log(f"[bench] {sec:.3f} s, flux mean {flux_ms:.4f} ms, status {status}, "
         f"hist first {h[0]:.6e} last {h[warm + steps - 1]:.6e}")
-
-    value = n * 4.0 * steps / sec
     # the timed launch is the flux with the SSP stage in its epilogue, or
-    # (rk4) the plain flux
+    # (rk4) the plain flux; the FP64 count per edge is the default residual's
     flops = costs.flux_flops(n, edges, stage=not rk4)
     achieved = flops / (flux_ms * 1e-3) / 1e12
-    traffic = None
-    if wl.name == "1m" and args.scheme == "default":  # the profiled launch
-        traffic = costs.stored_flux_traffic(os.path.join(ROOT, "profiles", "k_flux_1m.txt"))
-    if args.scheme not in ("default", "rk4"):  # the FP64 count per edge is the default scheme's
+    if options & (L.FIRST_ORDER | L.MINMAX):
         achieved = None
     stage_gb = costs.stage_bytes(n, cloud.k_pad, n_inner, fused=not rk4) / 1e9
+    return {
+        "plan": plan, "U": U, "U0_host": U0_host, "sec": sec, "flux_ms": flux_ms, "hist": h,
+        "status": status, "edges": edges,
+        "roofline": {"bound": "alu", "kernel": "k_flux" + ("" if rk4 else " + SSP stage"),
+                     "achieved": achieved,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": None if achieved is None else achieved / FP64_PEAK_TFLOPS,
+                     "traffic": None, "flops_per_launch": flops, "avg_launch_ms": flux_ms,
+                     "algorithmic_bytes_per_launch": costs.flux_bytes(n, cloud.k_pad,
+                                                                      stage=not rk4)},
+        "hbm_compulsory": {"GB_per_stage": stage_gb,
+                           "achieved_GBs": stage_gb * 4 * steps / sec,
+                           "frac": stage_gb * 4 * steps / sec / HBM_PEAK_GBS},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed iterations (default: the workload's)")
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="1m")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint/forward ratio in the 1m line")
+    ap.add_argument("--no-16m", action="store_true",
+                    help="skip the 16m object (10 timed iterations) of the default 1m line")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batch object (64 clouds, batched vs looped) of the default "
+                         "1m line")
+    ap.add_argument("--n-inner", type=int, default=None,
+                    help="inner least-squares sweeps (default: the workload's)")
+    ap.add_argument("--scheme", default="default",
+                    choices=("default", "first-order", "minmax", "rk4"),
+                    help="scheme variant of the sweep (default: the paper's second-order "
+                         "scheme with the Venkatakrishnan limiter and SSPRK(4,3); rk4: the "
+                         "same residual with classical RK4 stages)")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="instead of the sweep, run 5 plain device copies of this many bytes "
+                         "(calibrates the HBM traffic counters)")
+    ap.add_argument("--calibrate-elementary", action="store_true",
+                    help="instead of the sweep, run the FP64 elementary-function calibration "
+                         "kernels once each over 2^24 inputs (profile with rocprofv3 --pmc)")
+    args = ap.parse_args()
+    if args.calibrate_elementary:
+        return calibrate_elementary()
+    if args.copy_bytes:
+        import torch
+        torch.cuda.set_device(0)
+        src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 8, "copies": 5}), flush=True)
+        return 0
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the sweep is not "
+              "sharded across GPUs in this build", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "adjoint":
+        return bench_adjoint(args)
+    if args.workload == "ksweep":
+        return bench_ksweep(args)
+
+    import numpy as np
+    import torch
+
+    from cloudgen.workloads import WORKLOADS
+    from paper_2403_13287_amd import lskum as L
+
+    wl = WORKLOADS[args.workload]
+    steps = wl.iters if args.steps is None else args.steps
+    warm = args.warmup
+    options = {"default": 0, "first-order": L.FIRST_ORDER, "minmax": L.MINMAX,
+               "rk4": L.RK4}[args.scheme]
+    n_inner = wl.n_inner if args.n_inner is None else args.n_inner
+    headline = wl.name == "1m" and args.scheme == "default" and args.n_inner is None
+    # every cloud is built (in worker processes) before the GPU is touched
+    log(f"[bench] generating the {wl.name} cloud ({wl.W} x {wl.L})")
+    cloud = wl.cloud(workers=GEN_WORKERS)
+    cloud16 = bclouds = None
+    if headline and not args.no_16m:
+        w16 = WORKLOADS["16m"]
+        log(f"[bench] generating the 16m cloud ({w16.W} x {w16.L})")
+        cloud16 = w16.cloud(workers=GEN_WORKERS)
+    if headline and not args.no_batch:
+        bclouds, draws = batch_clouds()
+    torch.cuda.set_device(0)
+
+    r = run_sweep(cloud, wl, steps, warm, options, n_inner)
+    plan, U, sec, flux_ms, h, status = (r[k] for k in ("plan", "U", "sec", "flux_ms", "hist",
+                                                       "status"))
+    n, edges = cloud.n, r["edges"]
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": n * 4.0 * steps / sec,
         "unit": "point-stage updates/s",
         "n_gpus": 1,
         "steps": steps,
@@ -519,35 +642,74 @@ def main():
                                + ("" if args.scheme == "default" else f", scheme {args.scheme}"),
                    "points": n, "edges": edges, "k_pad": cloud.k_pad, "iterations": steps,
                    "stages_per_iteration": 4},
-        "roofline": {"bound": "alu", "kernel": "k_flux" + ("" if rk4 else " + SSP stage"),
-                     "achieved": achieved,
-                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": None if achieved is None else achieved / FP64_PEAK_TFLOPS,
-                     "traffic": traffic, "flops_per_launch": flops, "avg_launch_ms": flux_ms,
-                     "algorithmic_bytes_per_launch": costs.flux_bytes(n, cloud.k_pad,
-                                                                      stage=not rk4)},
-        "hbm_compulsory": {"GB_per_stage": stage_gb,
-                           "achieved_GBs": stage_gb * 4 * steps / sec,
-                           "frac": stage_gb * 4 * steps / sec / HBM_PEAK_GBS},
+        "roofline": r["roofline"],
+        "hbm_compulsory": r["hbm_compulsory"],
         "status": L.strerror(status),
         "residual_history": {"first": float(h[0]), "last": float(h[warm + steps - 1])},
     }
+    if wl.name == "1m" and args.scheme == "default":  # the profiled launch
+        from paper_2403_13287_amd import costs
+        out["roofline"]["traffic"] = costs.stored_flux_traffic(
+            os.path.join(ROOT, "profiles", "k_flux_1m.txt"))
+    ok = status == L.OK and bool(np.all(np.isfinite(h[:warm + steps])))
+    if headline:
+        # the same iteration over 1000 more iterations through the library's
+        # own loop: the rate a long run settles to
+        ws = L.workspace(plan)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.lskum_iterate(plan, SUSTAINED_ITERS, U, None, ws)
+        torch.cuda.synchronize()
+        t_s = time.perf_counter() - t0
+        out["sustained"] = {"iterations": SUSTAINED_ITERS, "ms_per_step": t_s * 1e3 / SUSTAINED_ITERS,
+                            "value": n * 4.0 * SUSTAINED_ITERS / t_s, "driver": "lskum_iterate",
+                            "status": L.strerror(L.lskum_status(plan))}
+        log(f"[bench] sustained: {out['sustained']}")
+        del ws
     # the headline's second figure: the residual VJP against the forward
     # residual, on this plan at the state the timed iterations reached
     if wl.name == "1m" and not args.no_adjoint and not options & (L.FIRST_ORDER | L.MINMAX):
         log("[bench] timing the residual VJP against the forward residual")
         adj = time_adjoint(plan, U, reps=20, warmup=5)
-        adj["state"] = f"the {wl.name} state after the {warm + steps} iterations above"
+        adj["state"] = (f"the {wl.name} state after the {warm + steps} iterations above"
+                        + (f" and {SUSTAINED_ITERS} more" if headline else ""))
         adj["cotangents"] = "N(0, 1), seed 7"
         adj["status"] = L.strerror(L.lskum_status(plan))
         out["adjoint"] = adj
         log(f"[bench] forward {adj['forward_ms']:.4f} ms, vjp {adj['vjp_ms']:.4f} ms, "
             f"ratio {adj['ratio']:.3f}")
     if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on one stage")
-        out["cpu_baseline"] = cpu_baseline(cloud, wl, U0_host, options, n_inner)
+        log("[bench] timing the CPU oracle (one thread, then all cores)")
+        out["cpu_baseline"] = cpu_baseline(cloud, wl, r["U0_host"], options, n_inner)
+    del plan, U, r
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if cloud16 is not None:
+        w16 = WORKLOADS["16m"]
+        log("[bench] 16m: 2 warm-up + 10 timed iterations")
+        r16 = run_sweep(cloud16, w16, 10, 2, 0, w16.n_inner, keep_initial=False)
+        out["16m"] = {
+            "workload": f"16m: NACA 0012 O-type airfoil cloud {w16.W} x {w16.L}, k_max "
+                        f"{w16.k_max}, M {w16.mach}, AoA {w16.aoa_deg} deg, n_inner {w16.n_inner}",
+            "points": cloud16.n, "edges": r16["edges"], "iterations": 10, "warmup": 2,
+            "ms_per_step": r16["sec"] * 1e3 / 10,
+            "value": cloud16.n * 4.0 * 10 / r16["sec"], "unit": "point-stage updates/s",
+            "roofline": r16["roofline"], "hbm_compulsory": r16["hbm_compulsory"],
+            "status": L.strerror(r16["status"])}
+        ok = ok and r16["status"] == L.OK
+        log(f"[bench] 16m: {out['16m']['value']:.4g} point-stage updates/s")
+        del r16, cloud16
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    if bclouds is not None:
+        rb = run_batch(bclouds, draws, BATCH_ITERS)
+        rb["workload"] = BATCH_CONFIG
+        out["batch"] = rb
+        ok = ok and rb["batched_equals_looped"] and rb["status"] == L.strerror(L.OK)
+        log(f"[bench] batch: {rb['value']:.4g} point-stage updates/s, "
+            f"{rb['speedup_vs_loop']:.2f}x the loop")
     print(json.dumps(out), flush=True)
-    return 0 if status == L.OK and np.all(np.isfinite(h[:warm + steps])) else 1
+    return 0 if ok else 1
 
 
 if __name__ == "__main__":

@@ -337,8 +337,11 @@ def _chunk_stencils_pooled(start):
 
 def make_airfoil_cloud(W: int, L: int, k_max: int, seed: int, *, t: float = 0.12,
                        r_outer: float = 15.0, jitter: float = 0.2, reorder: bool = True,
-                       chunk: int = 1 << 18) -> Cloud:
-    """Build the cloud described in the module docstring."""
+                       chunk: int = 1 << 18, workers: int | None = None) -> Cloud:
+    """Build the cloud described in the module docstring.  Stencils are built
+    in forked worker processes for clouds above PARALLEL_POINTS points, or
+    whenever `workers` > 1 is given (call it before the process initialises a
+    GPU then); the result does not depend on it."""
     if W < 16 or L < 4 or k_max < 8:
         raise ValueError("cloud too small")
     k_pad = (k_max + 3) // 4 * 4
@@ -356,8 +359,9 @@ def make_airfoil_cloud(W: int, L: int, k_max: int, seed: int, *, t: float = 0.12
     cnt_all = np.zeros(n, dtype=np.int64)
     starts = list(range(0, n, chunk))
     args = (W, L, side, xflat, yflat, kind, nxf, nyf, k_max, chunk, n)
-    workers = min(len(starts), os.cpu_count() or 1, 16)
-    if n > PARALLEL_POINTS and workers > 1:
+    forced = workers is not None
+    workers = min(len(starts), workers or os.cpu_count() or 1, 16)
+    if (forced or n > PARALLEL_POINTS) and workers > 1:
         # chunks are independent (each point's stencil depends only on the
         # positions in its index window), so the result does not depend on
         # how they are distributed

@@ -34,8 +34,8 @@ class Workload:
     def n_points(self) -> int:
         return self.W * self.L
 
-    def cloud(self):
-        return make_airfoil_cloud(self.W, self.L, self.k_max, self.seed)
+    def cloud(self, workers: int | None = None):
+        return make_airfoil_cloud(self.W, self.L, self.k_max, self.seed, workers=workers)
 
 
 def _wl(name, mach, aoa, n_inner, iters):

@@ -42,6 +42,10 @@
 #include <limits>
 #include <vector>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 namespace {
 
 const double kPi = 3.14159265358979323846;
@@ -634,6 +638,14 @@ void force_t(const lskum_ref_cloud &c, double gamma, T mach, T aoa, const UW &Uw
 // Exported point-level formulas
 
 extern "C" {
+
+int lskum_ref_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 void lskum_ref_free_stream(const lskum_ref_params *p, double U[4]) {
   double w[4];

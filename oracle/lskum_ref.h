@@ -58,6 +58,10 @@ typedef struct {
 #define LSKUM_REF_NONPHYSICAL 1u  /* rho, p or beta <= 0, or non-finite */
 #define LSKUM_REF_DEGENERATE  2u  /* a used half-plane stencil is singular */
 
+/* threads the forward sweeps use: omp_get_max_threads() in the OpenMP
+ * build, 1 in the parity build */
+int lskum_ref_threads(void);
+
 /* point-level formulas (exported for the pinning tests) */
 void lskum_ref_free_stream(const lskum_ref_params *p, double U[4]);
 void lskum_ref_q_from_prim(double gamma, const double prim[4], double q[4]);

@@ -67,6 +67,7 @@ def bind(path: str) -> ctypes.CDLL:
     cp = ctypes.POINTER(_Cloud)
     pp = ctypes.POINTER(_Params)
     sig = {
+        "lskum_ref_threads": (ctypes.c_int, []),
         "lskum_ref_free_stream": (None, [pp, vp]),
         "lskum_ref_q_from_prim": (None, [ctypes.c_double, vp, vp]),
         "lskum_ref_prim_from_q": (None, [ctypes.c_double, vp, vp]),

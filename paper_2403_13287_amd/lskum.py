@@ -102,7 +102,7 @@ _lib = None
 
 def library_path() -> str:
     """The in-tree library, or LSKUM_LIBRARY if set (an alternative build)."""
-    return os.environ.get("LSKUM_LIBRARY", _build.LIB)
+    return os.environ.get("LSKUM_LIBRARY") or _build.LIB
 
 
 def load() -> ctypes.CDLL:

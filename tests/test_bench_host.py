@@ -88,8 +88,14 @@ def test_cpu_baseline_record(tiny_cloud):
     U0 = Oracle(tiny_cloud, wl.mach, wl.aoa_deg).init_state()
     for options in (0, RK4):
         r = bench.cpu_baseline(tiny_cloud, wl, U0, options, None, min_seconds=0.2)
-        assert set(r) == {"value", "unit", "cores", "kind", "sample"}
+        assert set(r) == {"value", "unit", "cores", "kind", "sample", "host", "all_cores"}
         assert r["kind"] == "oracle" and r["cores"] == 1
         assert r["unit"] == "point-stage updates/s" and r["value"] > 0
         assert "9600 points" in r["sample"]
         assert ("options 4" in r["sample"]) == (options == RK4)
+        assert r["host"]["nproc"] == os.cpu_count() and r["host"]["cpus_available"] >= 1
+        a = r["all_cores"]
+        assert a["cores"] >= 1 and a["value"] > 0 and a["unit"] == r["unit"]
+        assert a["kind"].startswith("oracle") and f"{a['cores']} threads" in a["sample"]
+    r = bench.cpu_baseline(tiny_cloud, wl, U0, 0, None, min_seconds=0.1, all_cores=False)
+    assert "all_cores" not in r
