@@ -31,7 +31,11 @@ __device__ __forceinline__ unsigned degenerate_splits(const F8 &W, bool interior
 // residual, state, U^n and dt, and the q-variables of its new state into
 // S.q_next (the next stage's q; the q read here stays unchanged for the
 // other threads' neighbour loads).
-template <int BLK, int VAR, bool FUSE>
+// G14: gamma = 1.4, known when compiled: the end states' density needs no
+// log, and the kernel carries neither the general-gamma branch nor that
+// branch's constants, which otherwise hold vector registers through the
+// loop (192 -> 179 VGPRs).
+template <int BLK, int VAR, bool FUSE, bool G14>
 __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__restrict__ spw,
                                                  const double *__restrict__ q,
                                                  const double *__restrict__ dq,
@@ -150,8 +154,8 @@ __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__res
       }
     }
     EndState sj, s0;
-    f |= end_state(qtj, P, tx, ty, nx, ny, sj);
-    f |= end_state(qt0, P, tx, ty, nx, ny, s0);
+    f |= end_state<G14 ? 1 : 0>(qtj, P, tx, ty, nx, ny, sj);
+    f |= end_state<G14 ? 1 : 0>(qt0, P, tx, ty, nx, ny, s0);
     const F8 W = rd8(s_w, threadIdx.x);
 
     // s-direction split: ds < 0 -> G_s^+, ds > 0 -> G_s^-
@@ -214,14 +218,21 @@ int flux_launch(lskum_plan_s *p, const double *q, const double *dq, const double
   const int gr = grid_for(p->n, kFluxBlock);
   hipStream_t st = S(stream);
   const StageArgs sa = stage ? *stage : StageArgs{-1, nullptr, nullptr, nullptr, nullptr};
-#define LSKUM_FLUX_V(var)                                                                  \
+#define LSKUM_FLUX_G(var, g14)                                                             \
   do {                                                                                     \
     if (stage)                                                                             \
-      k_flux<kFluxBlock, var, true><<<gr, kFluxBlock, 0, st>>>(g, f, p->spw, q, dq, qlim, R, \
-                                                               p->status, sa);             \
+      k_flux<kFluxBlock, var, true, g14>                                                   \
+          <<<gr, kFluxBlock, 0, st>>>(g, f, p->spw, q, dq, qlim, R, p->status, sa);        \
     else                                                                                   \
-      k_flux<kFluxBlock, var, false><<<gr, kFluxBlock, 0, st>>>(g, f, p->spw, q, dq, qlim, R, \
-                                                                p->status, sa);            \
+      k_flux<kFluxBlock, var, false, g14>                                                  \
+          <<<gr, kFluxBlock, 0, st>>>(g, f, p->spw, q, dq, qlim, R, p->status, sa);        \
+  } while (0)
+#define LSKUM_FLUX_V(var)        \
+  do {                           \
+    if (f.gamma_is_14)           \
+      LSKUM_FLUX_G(var, true);   \
+    else                         \
+      LSKUM_FLUX_G(var, false);  \
   } while (0)
   switch (flux_variant(p)) {
     case 1: LSKUM_FLUX_V(1); break;
@@ -229,6 +240,7 @@ int flux_launch(lskum_plan_s *p, const double *q, const double *dq, const double
     default: LSKUM_FLUX_V(0); break;
   }
 #undef LSKUM_FLUX_V
+#undef LSKUM_FLUX_G
   return launched();
 }
 

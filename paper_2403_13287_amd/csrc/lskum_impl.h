@@ -287,7 +287,10 @@ struct EndExtra {
   double beta, ib, u, v, uu;  // ib = 1/beta
 };
 
-template <bool KEEP>
+// G14: 1 when gamma = 1.4 is known at compile time, 0 for a general gamma,
+// -1 to decide from P.gamma_is_14 at run time.  A kernel compiled for one
+// case carries neither the other's code nor its constants in registers.
+template <bool KEEP, int G14 = -1>
 __device__ __forceinline__ unsigned end_state_t(const double qt[4], const Flow &P, double tx,
                                                 double ty, double nx, double ny, EndState &s,
                                                 EndExtra *x) {
@@ -300,7 +303,7 @@ __device__ __forceinline__ unsigned end_state_t(const double qt[4], const Flow &
   const double v = qt[2] * inv2b;
   const double uu = u * u + v * v;
   double rho;
-  if (P.gamma_is_14)
+  if (G14 == 1 || (G14 < 0 && P.gamma_is_14))
     rho = exp(qt[0] + beta * uu) * (rsb * ib * ib);
   else
     rho = exp(qt[0] + beta * uu - log(beta) * P.inv_gm1);
@@ -318,9 +321,10 @@ __device__ __forceinline__ unsigned end_state_t(const double qt[4], const Flow &
              : 0u;
 }
 
+template <int G14 = -1>
 __device__ __forceinline__ unsigned end_state(const double qt[4], const Flow &P, double tx,
                                               double ty, double nx, double ny, EndState &s) {
-  return end_state_t<false>(qt, P, tx, ty, nx, ny, s, nullptr);
+  return end_state_t<false, G14>(qt, P, tx, ty, nx, ny, s, nullptr);
 }
 
 // Kinetic split flux along direction d with sign sg (+1 or -1): half-range
