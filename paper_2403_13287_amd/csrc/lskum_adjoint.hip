@@ -80,7 +80,7 @@ __device__ __forceinline__ void split_flux_rev(double sg, const EndState &s, dou
                                                double &uob) {
   const double S = ud * s.sqb;
   const double ex = exp(-(S * S));
-  const double A = 0.5 * (1.0 + sg * erf(S));
+  const double A = 0.5 * (1.0 + sg * lskum_math::lk_erf(S));
   const double B = ex * s.bcoef;
   const double F = ud * A + sg * B;
   const double Fb = Gb[0] * s.rho + Gb[2] * s.rho * uo;

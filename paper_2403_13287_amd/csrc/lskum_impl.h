@@ -334,7 +334,7 @@ __device__ __forceinline__ unsigned end_state(const double qt[4], const Flow &P,
 __device__ __forceinline__ void split_flux(double sg, const EndState &s, double ud, double uo,
                                            double G[4]) {
   const double S = ud * s.sqb;
-  const double A = 0.5 * (1.0 + sg * erf(S));
+  const double A = 0.5 * (1.0 + sg * lskum_math::lk_erf(S));
   const double B = exp(-(S * S)) * s.bcoef;
   const double F = ud * A + sg * B;
   G[0] = s.rho * F;

@@ -89,7 +89,11 @@ def test_1m_vjp_on_a_cut_against_oracle(state1m):
                n_inner=params.n_inner)
     U_sub = s.U[torch.from_numpy(ids).cuda()].cpu().numpy().T
     Ub_o, tb_o, flags = o.residual_vjp(U_sub, Rb[ids].T)
-    assert flags == 0
+    # points on the cut's outermost rings lose the neighbours outside it, so
+    # some of their half-plane stencils are singular (the degenerate bit);
+    # their residuals carry a zero cotangent and do not enter Ubar.  No
+    # state may be non-physical.
+    assert flags & ~2 == 0, flags
     Ub_g = Ub.cpu().numpy()
     e = normwise(Ub_g[ids].T, Ub_o)
     say("1M cut Ubar normwise", e, "theta", tb.cpu().numpy(), tb_o)
@@ -127,7 +131,7 @@ def test_1m_vjp_finite_difference_columns(state1m):
 
     pts = samples[c.kind[samples] != 2][:16]
     checked = kinks = 0
-    worst = 0.0
+    worst = worst_excess = 0.0
     for j in pts:
         for m in range(4):
             h = 1e-6 * np.abs(Uh[:, m]).max()
@@ -136,7 +140,15 @@ def test_1m_vjp_finite_difference_columns(state1m):
                 kinks += 1
                 continue
             checked += 1
-            worst = max(worst, abs(Ub[j, m] - f2) / scale)
-    say("1M FD columns: checked", checked, "kinks", kinks, "worst", worst)
+            # error of the h/4 quotient: truncation c h^2/16 = |f1 - f2|/15
+            # when truncation dominates, rounding r(h/4) = 4 r(h), i.e.
+            # 4/3 |f1 - f2|, when rounding does; the VJP must agree within
+            # 2 |f1 - f2| plus a floor of 1e-8 of its scale
+            err = abs(Ub[j, m] - f2)
+            worst = max(worst, err / scale)
+            worst_excess = max(worst_excess, (err - 2.0 * abs(f1 - f2)) / scale)
+    say("1M FD columns: checked", checked, "kinks", kinks, "worst", worst,
+        "worst beyond the FD's own error", worst_excess)
     assert checked >= 48
-    assert worst <= 5e-8
+    assert worst <= 2e-7
+    assert worst_excess <= 1e-8

@@ -1,5 +1,5 @@
-"""Accuracy of the flux kernel's Newton-refined divide and rsqrt
-(lskum_math.h) on the GPU, against numpy double precision."""
+"""Accuracy of the flux kernel's Newton-refined divide and rsqrt and of its
+erf (lskum_math.h) on the GPU, against numpy / scipy double precision."""
 import ctypes
 import numpy as np
 import pytest
@@ -46,3 +46,23 @@ def test_div_and_rsqrt(calib):
     ref = 1.0 / np.sqrt(x)
     rel = np.abs(got - ref) / ref
     assert rel.max() <= 3 * ULP, rel.max()
+
+
+def test_erf(calib):
+    """lk_erf: its own polynomial for |x| < 1, the device library beyond;
+    within 2 ulp of 1 (absolute) of scipy's erf everywhere, and within 3 ulp
+    relative for |x| < 1, where erf(x) ~ 2x/sqrt(pi) may be tiny; odd."""
+    from scipy.special import erf
+    rng = np.random.Generator(np.random.PCG64(5))
+    x = np.concatenate([rng.uniform(-1, 1, 200000), rng.uniform(-7, 7, 200000),
+                        np.sign(rng.normal(size=20000)) * np.exp(rng.uniform(-700, 0, 20000)),
+                        [0.0, -0.0, 1.0, -1.0, np.nextafter(1.0, 0.0), 6.0, 30.0, -30.0]])
+    got = calib(11, x)
+    ref = erf(x)
+    assert np.max(np.abs(got - ref)) <= 2 * ULP
+    small = np.abs(x) < 1
+    nz = small & (ref != 0)
+    rel = np.abs(got[nz] - ref[nz]) / np.abs(ref[nz])
+    assert rel.max() <= 3 * ULP, rel.max()
+    assert np.array_equal(calib(11, -x), -got)
+    assert np.all(np.isnan(calib(11, np.array([np.nan]))))
