@@ -52,7 +52,8 @@ typedef enum {
   LSKUM_ERR_HIP = -3,         /* a HIP runtime call or launch failed     */
   LSKUM_ERR_NONPHYSICAL = -4, /* rho, p or beta <= 0 or non-finite met   */
   LSKUM_ERR_NO_MEMORY = -5,   /* device allocation failed                */
-  LSKUM_ERR_DEGENERATE = -6   /* a used half-plane stencil is singular   */
+  LSKUM_ERR_DEGENERATE = -6,  /* a used half-plane stencil is singular   */
+  LSKUM_ERR_SCRATCH_LIMIT = -7 /* cloud larger than a static scratch     */
 } lskum_status_t;
 
 /* Point cloud, HOST pointers, read only inside lskum_plan_create. */
@@ -153,6 +154,21 @@ int lskum_q_vars(lskum_plan plan, const double *U, double *q, void *stream);
  * share a byte with each other or with q (LSKUM_ERR_INVALID_ARG). */
 int lskum_q_derivs(lskum_plan plan, const double *q, double *dq, double *qlim, double *work,
                    void *stream);
+
+/* lskum_q_derivs without the `work` argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): the inner sweeps' [n][16] scratch is a
+ * static device array of the library (128 MiB, held on every GPU the
+ * library runs on until the process ends), so the call allocates nothing.
+ * dq and qlim equal those of lskum_q_derivs bit for bit.  Plans of more
+ * than 1048576 points with n_inner > 0 get LSKUM_ERR_SCRATCH_LIMIT; other
+ * errors as lskum_q_derivs, and LSKUM_ERR_HIP if the scratch's device
+ * address could not be resolved when the plan was created.  Every call on
+ * one GPU uses that GPU's one array: calls that overlap in time on one GPU
+ * (other streams, other plans, other host threads) race and give wrong
+ * results; calls ordered on one stream are safe. */
+int lskum_q_derivs_static(lskum_plan plan, const double *q, double *dq, double *qlim,
+                          void *stream);
 
 /* Flux residual: the sum of the split-flux derivatives of eq. (10), each
  * from eq. (11) on its half-plane stencil of the point's (s, n) frame, with

@@ -31,6 +31,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -572,6 +573,54 @@ int run_iterations(lskum_plan_s *p, int32_t iters, double *U, double *hist, int3
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Static scratch of lskum_q_derivs_static, the entry point for callers that
+// cannot allocate: the [n][16] work buffer of the inner sweeps for up to
+// kScratchPoints points (128 MiB).  Every GPU the library runs on holds its
+// own copy until the process ends.  Host code never passes `scratch` itself
+// (in host code the name stands for a host-side shadow); it passes the
+// device address resolved once per device below.
+namespace {
+
+constexpr size_t kScratchPoints = (size_t)1 << 20;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[16 * kScratchPoints];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+int g_scratch_rc[kMaxDevices];  // 0: not resolved yet; LSKUM_OK or LSKUM_ERR_HIP once tried
+
+// Resolve the device address of `scratch` on `device`, which must be the
+// current device: once per device (plan creation calls it), later calls read
+// the stored result.
+int resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return LSKUM_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_rc[device] == 0) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_rc[device] = (e == hipSuccess && ptr) ? LSKUM_OK : LSKUM_ERR_HIP;
+    if (e != hipSuccess) (void)hipGetLastError();  // do not leave the error for the next call
+    g_scratch_ptr[device] = g_scratch_rc[device] == LSKUM_OK ? ptr : nullptr;
+  }
+  return g_scratch_rc[device];
+}
+
+// The stored device address of `scratch` on `device` (nullptr if its
+// resolution failed).
+void *scratch_on(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_rc[device] == LSKUM_OK ? g_scratch_ptr[device] : nullptr;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *lskum_strerror(int code) {
@@ -583,6 +632,8 @@ const char *lskum_strerror(int code) {
     case LSKUM_ERR_NONPHYSICAL: return "non-physical state (rho, p or beta <= 0, or non-finite)";
     case LSKUM_ERR_NO_MEMORY: return "device allocation failed";
     case LSKUM_ERR_DEGENERATE: return "singular half-plane stencil";
+    case LSKUM_ERR_SCRATCH_LIMIT:
+      return "the cloud exceeds the static scratch of lskum_q_derivs_static (1048576 points)";
     default: return "unknown status";
   }
 }
@@ -700,6 +751,9 @@ int lskum_batch_plan_create(lskum_plan *out, int32_t n_clouds, const lskum_cloud
     release(p);
     return rc;
   }
+  // the static scratch's address on this device, for lskum_q_derivs_static;
+  // a failure here is reported by that entry point, not by plan creation
+  (void)resolve_scratch(p->device);
   *out = p;
   return LSKUM_OK;
 }
@@ -767,6 +821,23 @@ int lskum_q_derivs(lskum_plan p, const double *q, double *dq, double *qlim, doub
   if (!writes_disjoint({Span{dq, 64 * n}, Span{qlim, 64 * n}, Span{work, inner ? 128 * n : 0}},
                        {Span{q, 32 * n}}))
     return LSKUM_ERR_INVALID_ARG;
+  return q_derivs_launch(p, q, dq, qlim, work, stream);
+}
+
+int lskum_q_derivs_static(lskum_plan p, const double *q, double *dq, double *qlim,
+                          void *stream) {
+  if (!p || !a32(q) || !a64(dq) || !a64(qlim)) return LSKUM_ERR_INVALID_ARG;
+  const size_t n = (size_t)p->n;
+  if (!writes_disjoint({Span{dq, 64 * n}, Span{qlim, 64 * n}}, {Span{q, 32 * n}}))
+    return LSKUM_ERR_INVALID_ARG;
+  double *work = nullptr;
+  if (p->params[0].n_inner > 0) {
+    if (n > kScratchPoints) return LSKUM_ERR_SCRATCH_LIMIT;
+    work = static_cast<double *>(scratch_on(p->device));
+    if (!work) return LSKUM_ERR_HIP;
+  }
+  // the same launches as lskum_q_derivs; every entry of work is written
+  // before it is read, so nothing needs clearing between calls
   return q_derivs_launch(p, q, dq, qlim, work, stream);
 }
 

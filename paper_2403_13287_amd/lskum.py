@@ -26,6 +26,7 @@ ERR_HIP = -3
 ERR_NONPHYSICAL = -4
 ERR_NO_MEMORY = -5
 ERR_DEGENERATE = -6
+ERR_SCRATCH_LIMIT = -7
 
 FIRST_ORDER = 1  # Params.options bits
 MINMAX = 2
@@ -71,6 +72,7 @@ _SIGS = {
     "lskum_init_state": (ctypes.c_int, "vvv"),
     "lskum_q_vars": (ctypes.c_int, "vvvv"),
     "lskum_q_derivs": (ctypes.c_int, "vvvvvv"),
+    "lskum_q_derivs_static": (ctypes.c_int, "vvvvv"),
     "lskum_flux_residual": (ctypes.c_int, "vvvvvv"),
     "lskum_local_dt": (ctypes.c_int, "vvvv"),
     "lskum_rk_stage": (ctypes.c_int, "vivvvvv"),
@@ -275,6 +277,14 @@ def lskum_q_derivs(plan: Plan, q, dq, qlim, work, stream=None):
     _check(plan.lib.lskum_q_derivs(plan.handle, plan._arg(q, 4, "q"), plan._arg(dq, 8, "dq"),
                                    plan._arg(qlim, 8, "qlim"), plan._arg(work, 16, "work"),
                                    _stream(stream)), "lskum_q_derivs")
+
+
+def lskum_q_derivs_static(plan: Plan, q, dq, qlim, stream=None):
+    """lskum_q_derivs with the library's static scratch in place of `work`
+    (the call allocates nothing; plans up to 2^20 points when n_inner > 0)."""
+    _check(plan.lib.lskum_q_derivs_static(plan.handle, plan._arg(q, 4, "q"),
+                                          plan._arg(dq, 8, "dq"), plan._arg(qlim, 8, "qlim"),
+                                          _stream(stream)), "lskum_q_derivs_static")
 
 
 def lskum_flux_residual(plan: Plan, q, dq, qlim, R, stream=None):

@@ -41,6 +41,7 @@ def test_binding_covers_every_declared_symbol():
 
 def test_strerror():
     assert L.strerror(0) == "ok"
+    assert "static scratch" in L.strerror(L.ERR_SCRATCH_LIMIT)
     assert "validation" in L.strerror(L.ERR_BAD_CLOUD)
     assert L.strerror(12345) == "unknown status"
 
@@ -127,6 +128,7 @@ def test_null_arguments_are_rejected():
     lib = L.load()
     assert lib.lskum_plan_create(None, None, None, None) == L.ERR_INVALID_ARG
     assert lib.lskum_q_vars(None, None, None, None) == L.ERR_INVALID_ARG
+    assert lib.lskum_q_derivs_static(None, None, None, None, None) == L.ERR_INVALID_ARG
     assert lib.lskum_flux_residual(None, None, None, None, None, None) == L.ERR_INVALID_ARG
     assert lib.lskum_rk_stage(None, 0, None, None, None, None, None) == L.ERR_INVALID_ARG
     assert lib.lskum_rk4_stage(None, 0, None, None, None, None, None, None) == L.ERR_INVALID_ARG
