@@ -49,7 +49,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# worker processes for cloud generation (before the GPU is initialised)
+# worker processes for cloud generation (before the GPU is initialised;
+# --gen-workers 1 builds in-process, e.g. under a profiler that has already
+# initialised the GPU)
 GEN_WORKERS = 16
 
 
@@ -237,8 +239,10 @@ def run_batch(clouds, draws, iters: int) -> dict:
         "loop_seconds": t_loop,
         "loop_value": total * 4.0 * iters / t_loop,
         "speedup_vs_loop": t_loop / t_batch,
-        "tuning": {"block": best.block, "xcd_contiguous": best.xcd_contiguous},
-        "autotune_ms_per_2_iterations": {f"{k[0]}/{k[1]}": v for k, v in tune_ms.items()},
+        "tuning": {"block": best.block, "xcd_contiguous": best.xcd_contiguous,
+                   "flux_block": best.flux_block},
+        "autotune_ms_per_2_iterations (block/xcd_contiguous/flux_block)":
+            {k.key(): v for k, v in tune_ms.items()},
         "batched_equals_looped": identical,
         "status": L.strerror(status),
         "loop_status": L.strerror(loop_status),
@@ -363,11 +367,11 @@ def bench_adjoint(args) -> int:
     from paper_2403_13287_amd import lskum as L
     from paper_2403_13287_amd.solver import Solver
 
+    log("[bench] generating the 1m cloud (1000 x 1000)")
+    cloud = named_cloud("1m", workers=GEN_WORKERS)
     torch.cuda.set_device(0)
     reps = 20 if args.steps is None else args.steps
     state_iters = 300
-    log("[bench] generating the 1m cloud (1000 x 1000)")
-    cloud = named_cloud("1m")
     params = L.Params(0.63, 2.0, 0.2, 5.0, 3)
     s = Solver(cloud, params)
     s.run(state_iters)
@@ -378,6 +382,34 @@ def bench_adjoint(args) -> int:
     status = s.status()
     log(f"[bench] forward {t_fwd:.4f} ms, vjp {t_vjp:.4f} ms, ratio {ratio:.3f}, "
         f"force vjp {t_force:.4f} ms, status {status}")
+    converged = None
+    if args.converge:
+        # the same flow advanced until the density residual has fallen 10
+        # orders from the first iteration's or `converge` iterations have run
+        chunk = 1000
+        h = s.history().cpu().numpy()
+        r1 = float(h[0])
+        while s.iteration < args.converge:
+            hc = s.run(min(chunk, args.converge - s.iteration)).cpu().numpy()
+            rel = float(hc[-1]) / r1
+            log(f"[bench] converging: iteration {s.iteration}, r/r1 {rel:.3e}, "
+                f"status {s.status()}")
+            if not np.isfinite(rel) or rel <= 1e-10 or s.status() != L.OK:
+                break
+        torch.cuda.synchronize()
+        hist = s.history().cpu().numpy()
+        tc = time_adjoint(plan, U, reps, args.warmup, force=True)
+        cl_cd = s.force_coeffs().cpu().numpy()
+        converged = {"iterations": s.iteration, "r_over_r1": float(hist[-1]) / r1,
+                     "r_over_r1_min": float(np.min(hist)) / r1,
+                     "cl": float(cl_cd[0]), "cd": float(cl_cd[1]),
+                     "forward_ms": tc["forward_ms"], "vjp_ms": tc["vjp_ms"],
+                     "force_vjp_ms": tc["force_vjp_ms"], "ratio": tc["ratio"],
+                     "finite": tc["finite"], "status": L.strerror(s.status())}
+        log(f"[bench] converged state: {converged}")
+        if args.save_state:
+            np.save(args.save_state, U.cpu().numpy())
+        status = s.status() if status == L.OK else status
     out = {
         "metric": "adjoint/forward time ratio (residual VJP incl. recompute / forward residual)",
         "value": ratio,
@@ -402,6 +434,8 @@ def bench_adjoint(args) -> int:
         "status": L.strerror(status),
         "finite": t["finite"],
     }
+    if converged is not None:
+        out["converged_state"] = converged
     print(json.dumps(out), flush=True)
     return 0 if status == L.OK and out["finite"] else 1
 
@@ -454,7 +488,7 @@ BATCH_ITERS = 500
 
 
 def run_sweep(cloud, wl, steps: int, warm: int, options: int, n_inner: int,
-              keep_initial: bool = True) -> dict:
+              keep_initial: bool = True, tuning=None) -> dict:
     """Time `steps` iterations (after `warm` untimed ones) of the whole
     iteration on `cloud` from the initial state, issued from Python one
     entry point at a time, with HIP events around every flux launch."""
@@ -467,7 +501,7 @@ def run_sweep(cloud, wl, steps: int, warm: int, options: int, n_inner: int,
     n = cloud.n
     edges = int(cloud.nbr_count.astype(np.int64).sum())
     p = L.Params(wl.mach, wl.aoa_deg, wl.cfl, wl.venkat_k, n_inner, wl.gamma, options=options)
-    plan = L.Plan(cloud, p)
+    plan = L.Plan(cloud, p, tuning=tuning)
     U = plan.field(4)
     L.lskum_init_state(plan, U)
     # the initial state in the oracle's layout (4, n), for the CPU baseline
@@ -544,6 +578,7 @@ def run_sweep(cloud, wl, steps: int, warm: int, options: int, n_inner: int,
 
 
 def main():
+    global GEN_WORKERS
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed iterations (default: the workload's)")
@@ -552,6 +587,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward ratio in the 1m line")
+    ap.add_argument("--no-sustained", action="store_true",
+                    help="skip the 1000-iteration sustained figure of the default 1m line "
+                         "(e.g. under a per-dispatch counter profiler)")
     ap.add_argument("--no-16m", action="store_true",
                     help="skip the 16m object (10 timed iterations) of the default 1m line")
     ap.add_argument("--no-batch", action="store_true",
@@ -564,6 +602,17 @@ def main():
                     help="scheme variant of the sweep (default: the paper's second-order "
                          "scheme with the Venkatakrishnan limiter and SSPRK(4,3); rk4: the "
                          "same residual with classical RK4 stages)")
+    ap.add_argument("--tuning", default=None,
+                    help="launch tuning of the timed plan as block/xcd_contiguous/flux_block, "
+                         "e.g. 256/1/64 (default: the library's)")
+    ap.add_argument("--gen-workers", type=int, default=GEN_WORKERS,
+                    help="worker processes that build the clouds (1: in this process)")
+    ap.add_argument("--converge", type=int, default=0,
+                    help="--workload adjoint: also advance the flow until the residual has "
+                         "fallen 10 orders (at most this many iterations) and time the "
+                         "adjoint ratio there")
+    ap.add_argument("--save-state", default=None,
+                    help="--workload adjoint --converge: save the state reached (.npy)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of the sweep, run 5 plain device copies of this many bytes "
                          "(calibrates the HBM traffic counters)")
@@ -571,6 +620,7 @@ def main():
                     help="instead of the sweep, run the FP64 elementary-function calibration "
                          "kernels once each over 2^24 inputs (profile with rocprofv3 --pmc)")
     args = ap.parse_args()
+    GEN_WORKERS = max(1, args.gen_workers)
     if args.calibrate_elementary:
         return calibrate_elementary()
     if args.copy_bytes:
@@ -619,7 +669,11 @@ def main():
         bclouds, draws = batch_clouds()
     torch.cuda.set_device(0)
 
-    r = run_sweep(cloud, wl, steps, warm, options, n_inner)
+    tuning = None
+    if args.tuning:
+        b, x, fb = (int(v) for v in args.tuning.split("/"))
+        tuning = L.Tuning(b, x, fb)
+    r = run_sweep(cloud, wl, steps, warm, options, n_inner, tuning=tuning)
     plan, U, sec, flux_ms, h, status = (r[k] for k in ("plan", "U", "sec", "flux_ms", "hist",
                                                        "status"))
     n, edges = cloud.n, r["edges"]
@@ -641,7 +695,8 @@ def main():
                                f"n_inner {n_inner}, CFL {wl.cfl}, Venkatakrishnan K {wl.venkat_k}"
                                + ("" if args.scheme == "default" else f", scheme {args.scheme}"),
                    "points": n, "edges": edges, "k_pad": cloud.k_pad, "iterations": steps,
-                   "stages_per_iteration": 4},
+                   "stages_per_iteration": 4,
+                   "tuning": (tuning or L.Tuning()).key()},
         "roofline": r["roofline"],
         "hbm_compulsory": r["hbm_compulsory"],
         "status": L.strerror(status),
@@ -652,7 +707,7 @@ def main():
         out["roofline"]["traffic"] = costs.stored_flux_traffic(
             os.path.join(ROOT, "profiles", "k_flux_1m.txt"))
     ok = status == L.OK and bool(np.all(np.isfinite(h[:warm + steps])))
-    if headline:
+    if headline and not args.no_sustained:
         # the same iteration over 1000 more iterations through the library's
         # own loop: the rate a long run settles to
         ws = L.workspace(plan)

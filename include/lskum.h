@@ -99,12 +99,14 @@ typedef struct {
 #define LSKUM_RK4 4
 
 /* Launch tuning of a plan: the block size (= points per LDS tile of the
- * gather kernels) and whether blocks are relabelled so that each of the 8
+ * gather kernels), whether blocks are relabelled so that each of the 8
  * XCDs walks one contiguous range of points (its L2 then holds that range's
- * neighbours).  Results do not depend on the tuning. */
+ * neighbours), and the flux kernel's block size (= points whose records it
+ * stages in LDS).  Results do not depend on the tuning. */
 typedef struct {
   int32_t block;          /* 128, 256 or 512 (0: 256)                         */
   int32_t xcd_contiguous; /* 1 (default): XCD-contiguous ranges; 0: round-robin */
+  int32_t flux_block;     /* 64, 128 or 256 (0: 64)                           */
 } lskum_tuning;
 
 typedef struct lskum_plan_s *lskum_plan;

@@ -388,7 +388,9 @@ bool batch_params_ok(int32_t nc, const lskum_params *p) {
 
 bool tuning_ok(const lskum_tuning *t) {
   return !t || ((t->block == 0 || t->block == 128 || t->block == 256 || t->block == 512) &&
-                (t->xcd_contiguous == 0 || t->xcd_contiguous == 1));
+                (t->xcd_contiguous == 0 || t->xcd_contiguous == 1) &&
+                (t->flux_block == 0 || t->flux_block == 64 || t->flux_block == 128 ||
+                 t->flux_block == 256));
 }
 
 void free_stream_state(const lskum_params &q, double U[4]) {
@@ -715,6 +717,7 @@ int lskum_batch_plan_create(lskum_plan *out, int32_t n_clouds, const lskum_cloud
   if (tuning) {
     p->block = tuning->block ? tuning->block : 256;
     p->xcd = tuning->xcd_contiguous;
+    p->flux_block = tuning->flux_block ? tuning->flux_block : 64;
   }
   int rc = LSKUM_OK;
   if (rc == LSKUM_OK) rc = upload(&p->xy, xy.data(), xy.size());
@@ -782,6 +785,7 @@ int lskum_plan_set_tuning(lskum_plan p, const lskum_tuning *tuning) {
   if (!p || !tuning || !tuning_ok(tuning)) return LSKUM_ERR_INVALID_ARG;
   p->block = tuning->block ? tuning->block : 256;
   p->xcd = tuning->xcd_contiguous;
+  p->flux_block = tuning->flux_block ? tuning->flux_block : 64;
   return ensure_tile_map(p);
 }
 

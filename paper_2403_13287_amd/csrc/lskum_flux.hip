@@ -205,27 +205,24 @@ namespace lskum_impl {
 
 // The flux launch for the plan's scheme variant.  The flux kernel stages
 // only its own block's records (it has no tile tables), so its block size is
-// independent of the plan's tile size: one-wavefront (64-point) blocks
-// shorten the tail of each launch, and the whole iteration on the 1M cloud
-// runs 1.3 % faster than with 256-point blocks.  Results do not depend on
-// the block size (each point's sums run in its row order).
-constexpr int kFluxBlock = 64;
-
-int flux_launch(lskum_plan_s *p, const double *q, const double *dq, const double *qlim,
-                double *R, void *stream, const StageArgs *stage) {
-  const Geo g = geo(p);
-  const Flow f = flow(p);
-  const int gr = grid_for(p->n, kFluxBlock);
-  hipStream_t st = S(stream);
+// independent of the plan's tile size and tuned on its own (64, 128 or 256
+// points; 64 by default: one-wavefront blocks shorten the tail of each
+// launch).  Results do not depend on it (each point's sums run in its row
+// order).
+template <int BLK>
+void flux_launch_blk(lskum_plan_s *p, const Geo &g, const Flow &f, const double *q,
+                     const double *dq, const double *qlim, double *R, hipStream_t st,
+                     const StageArgs *stage) {
+  const int gr = grid_for(p->n, BLK);
   const StageArgs sa = stage ? *stage : StageArgs{-1, nullptr, nullptr, nullptr, nullptr};
-#define LSKUM_FLUX_G(var, g14)                                                             \
-  do {                                                                                     \
-    if (stage)                                                                             \
-      k_flux<kFluxBlock, var, true, g14>                                                   \
-          <<<gr, kFluxBlock, 0, st>>>(g, f, p->spw, q, dq, qlim, R, p->status, sa);        \
-    else                                                                                   \
-      k_flux<kFluxBlock, var, false, g14>                                                  \
-          <<<gr, kFluxBlock, 0, st>>>(g, f, p->spw, q, dq, qlim, R, p->status, sa);        \
+#define LSKUM_FLUX_G(var, g14)                                                          \
+  do {                                                                                  \
+    if (stage)                                                                          \
+      k_flux<BLK, var, true, g14><<<gr, BLK, 0, st>>>(g, f, p->spw, q, dq, qlim, R,    \
+                                                       p->status, sa);                 \
+    else                                                                                \
+      k_flux<BLK, var, false, g14><<<gr, BLK, 0, st>>>(g, f, p->spw, q, dq, qlim, R,   \
+                                                        p->status, sa);                \
   } while (0)
 #define LSKUM_FLUX_V(var)        \
   do {                           \
@@ -241,6 +238,18 @@ int flux_launch(lskum_plan_s *p, const double *q, const double *dq, const double
   }
 #undef LSKUM_FLUX_V
 #undef LSKUM_FLUX_G
+}
+
+int flux_launch(lskum_plan_s *p, const double *q, const double *dq, const double *qlim,
+                double *R, void *stream, const StageArgs *stage) {
+  const Geo g = geo(p);
+  const Flow f = flow(p);
+  hipStream_t st = S(stream);
+  switch (p->flux_block) {
+    case 128: flux_launch_blk<128>(p, g, f, q, dq, qlim, R, st, stage); break;
+    case 256: flux_launch_blk<256>(p, g, f, q, dq, qlim, R, st, stage); break;
+    default: flux_launch_blk<64>(p, g, f, q, dq, qlim, R, st, stage); break;
+  }
   return launched();
 }
 

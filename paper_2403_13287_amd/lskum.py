@@ -56,7 +56,8 @@ class _Params(ctypes.Structure):
 
 
 class _Tuning(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_int32), ("xcd_contiguous", ctypes.c_int32)]
+    _fields_ = [("block", ctypes.c_int32), ("xcd_contiguous", ctypes.c_int32),
+                ("flux_block", ctypes.c_int32)]
 
 
 # name -> (restype, argtypes); 'v' = void*, 'i' = int32, 'd' = double
@@ -160,15 +161,20 @@ class Params:
                        self.venkat_k, int(self.n_inner), int(self.options))
 
 
-@dataclass
+@dataclass(frozen=True)
 class Tuning:
-    """Block size (points per LDS tile: 128, 256, 512) and XCD-contiguous
-    block mapping; results do not depend on it."""
+    """Block size of the gather kernels (points per LDS tile: 128, 256, 512),
+    XCD-contiguous block mapping, and the flux kernel's block size (64, 128,
+    256); results do not depend on it."""
     block: int = 256
     xcd_contiguous: int = 1
+    flux_block: int = 64
 
     def c(self) -> _Tuning:
-        return _Tuning(int(self.block), int(self.xcd_contiguous))
+        return _Tuning(int(self.block), int(self.xcd_contiguous), int(self.flux_block))
+
+    def key(self) -> str:
+        return f"{self.block}/{self.xcd_contiguous}/{self.flux_block}"
 
 
 def _cloud_struct(cloud):
@@ -489,13 +495,13 @@ class Graph:
             pass
 
 
-TUNING_SPACE = [Tuning(b, x) for b in (128, 256, 512) for x in (1, 0)]
+TUNING_SPACE = [Tuning(b, x, fb) for b in (128, 256, 512) for x in (1, 0) for fb in (64, 128)]
 
 
 def autotune(plan: Plan, U, ws, iters: int = 2, reps: int = 3, space=None, stream=None):
-    """Time `iters` iterations for every tuning in `space` (default: block
-    128/256/512 x XCD mapping on/off) on a scratch copy of U, keep the
-    fastest on the plan and return (best, {tuning: ms})."""
+    """Time `iters` iterations for every tuning in `space` (default: tile
+    block 128/256/512 x XCD mapping on/off x flux block 64/128) on a scratch
+    copy of U, keep the fastest on the plan and return (best, {tuning: ms})."""
     space = space or TUNING_SPACE
     scratch = U.clone()
     times = {}
@@ -511,9 +517,8 @@ def autotune(plan: Plan, U, ws, iters: int = 2, reps: int = 3, space=None, strea
             b.record()
             torch.cuda.synchronize()
             ms.append(a.elapsed_time(b))
-        times[(t.block, t.xcd_contiguous)] = min(ms)
-    best_key = min(times, key=times.get)
-    best = Tuning(*best_key)
+        times[t] = min(ms)
+    best = min(times, key=times.get)
     plan.set_tuning(best)
     lskum_clear_status(plan, stream)
     return best, times

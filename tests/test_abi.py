@@ -115,6 +115,21 @@ def test_validation_rejects_bad_params(cyl):
         assert _create(s, bad)[0] == L.ERR_INVALID_ARG
 
 
+def test_validation_rejects_bad_tunings(cyl):
+    """Tile block, XCD mapping and flux block outside their sets are argument
+    errors, found on the host before any device work."""
+    s, keep = _c_cloud(cyl)
+    lib = L.load()
+    p = L.Params(0.5, 0.0).c()
+    for bad in [L.Tuning(64, 1, 64), L.Tuning(256, 2, 64), L.Tuning(256, 1, 96),
+                L.Tuning(256, 1, 512), L.Tuning(256, 1, -64)]:
+        h = ctypes.c_void_p()
+        t = bad.c()
+        rc = lib.lskum_batch_plan_create(ctypes.byref(h), 1, ctypes.byref(s), ctypes.byref(p),
+                                         ctypes.byref(t), None)
+        assert rc == L.ERR_INVALID_ARG and not h.value, bad
+
+
 def test_empty_cloud_is_rejected(cyl):
     """A cloud of no points is an argument error, found on the host before
     any device work."""

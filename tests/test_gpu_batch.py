@@ -64,7 +64,7 @@ def test_batch_matches_single_clouds_bitwise(batch):
 def test_tuning_does_not_change_results(batch):
     clouds, params = batch
     ref = None
-    for t in L.TUNING_SPACE:
+    for t in L.TUNING_SPACE + [L.Tuning(256, 1, 256)]:
         say("tuning", t)
         s = Solver(clouds, params, tuning=t)
         h = s.run(3)
@@ -99,7 +99,8 @@ def test_autotune_keeps_results(batch):
     best, times = L.autotune(s.plan, s.U, s.ws, iters=1, reps=1)
     assert torch.equal(s.U, U0)  # autotuning runs on a scratch copy
     assert len(times) == len(L.TUNING_SPACE)
-    assert (best.block, best.xcd_contiguous) in times
+    assert best in times
+    assert len({(t.block, t.xcd_contiguous, t.flux_block) for t in times}) >= 12
 
 
 def test_batch_member_against_oracle(batch):
