@@ -193,6 +193,7 @@ __device__ __forceinline__ void frame_seed(const F4 &rb, double tx, double ty, d
 // Reverse of one end of one edge: the end's record (qe, ge, le), the edge
 // vector d as row i sees it and row i's frame.  Adds the cotangents of the
 // end's q, dq and qlim records to qb, gb, lb.
+template <bool G14>
 __device__ __forceinline__ unsigned end_reverse(const Flow &P, const F4 &qe, const F8 &ge,
                                                 const F8 &le, double dx, double dy, double eps2,
                                                 double tx, double ty, double nx, double ny,
@@ -207,7 +208,7 @@ __device__ __forceinline__ unsigned end_reverse(const Flow &P, const F4 &qe, con
   }
   EndState st;
   EndExtra ex;
-  const unsigned f = end_state_t<true>(qt, P, tx, ty, nx, ny, st, &ex);
+  const unsigned f = end_state_t<true, G14 ? 1 : 0>(qt, P, tx, ty, nx, ny, st, &ex);
   EndBar b{0, 0, 0, 0, 0, 0, 0};
   if (e.wt_s != 0.0) split_flux_rev(e.sg_s, st, st.us, st.un, e.Gs, b, b.us, b.un);
   if (e.wt_n != 0.0) split_flux_rev(e.sg_n, st, st.un, st.us, e.Gn, b, b.un, b.us);
@@ -233,7 +234,8 @@ __device__ __forceinline__ unsigned end_reverse(const Flow &P, const F4 &qe, con
 // Own end of every edge of row i: writes the own-end parts of qbar_i, gbar_i
 // and lbar_i.  The thread's own record is re-read from LDS at every edge
 // rather than held in registers through the loop (two waves per SIMD).
-template <int BLK>
+// G14: compiled for gamma = 1.4 (as the forward flux kernel).
+template <int BLK, bool G14>
 __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(2)))
 k_flux_rev_own(Geo G, Flow P, const double *__restrict__ spw, const double *__restrict__ q,
                const double *__restrict__ dq, const double *__restrict__ qlim,
@@ -295,7 +297,7 @@ k_flux_rev_own(Geo G, Flow P, const double *__restrict__ spw, const double *__re
       asm volatile("" ::: "memory");
       const F4 q0 = pl_rd4<BLK>(s_q, threadIdx.x);
       const F8 g0 = pl_rd8<BLK>(s_g, threadIdx.x), l0 = pl_rd8<BLK>(s_l, threadIdx.x);
-      f |= end_reverse(P, q0, g0, l0, dx, dy, edge_eps2(K, dx, dy), tx, ty, nx, ny, e, qb, gb, lb);
+      f |= end_reverse<G14>(P, q0, g0, l0, dx, dy, edge_eps2(K, dx, dy), tx, ty, nx, ny, e, qb, gb, lb);
       xj = xn;
       j_next = j_after;
     }
@@ -332,7 +334,7 @@ struct InRow {
 // weights and seed.  Adds the own-end parts left by k_flux_rev_own; in
 // place: qbar_j, lbar_j complete, and sbar_j (holding the own-end gbar_j on
 // entry) becomes M_j^-1 gbar_j, the seed of the derivative reverse.
-template <int BLK>
+template <int BLK, bool G14>
 __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(2)))
 k_flux_gather(Geo G, Flow P, const int32_t *__restrict__ in_cnt,
               const int32_t *__restrict__ in_ent, const double *__restrict__ lsg,
@@ -417,7 +419,7 @@ k_flux_gather(Geo G, Flow P, const int32_t *__restrict__ in_cnt,
     asm volatile("" ::: "memory");
     const F4 qj = pl_rd4<BLK>(s_q, threadIdx.x);
     const F8 gj = pl_rd8<BLK>(s_g, threadIdx.x), lj = pl_rd8<BLK>(s_l, threadIdx.x);
-    end_reverse(P, qj, gj, lj, dx, dy, edge_eps2(K, dx, dy), tx, ty, nx, ny, es, qb, gb, lb);
+    end_reverse<G14>(P, qj, gj, lj, dx, dy, edge_eps2(K, dx, dy), tx, ty, nx, ny, es, qb, gb, lb);
   }
   const F4 qo = ld4(qbar, j);
   const F8 go = ld8(sbar, j), lo8 = ld8(lbar, j);
@@ -1177,10 +1179,19 @@ int reverse_passes(lskum_plan_s *p, const VjpWs &w, const double *U, const doubl
     // the two flux reverses have no tile tables: one-wavefront blocks
     // shorten their launch tails, as for the forward flux
     const int g64 = grid_for(p->n, 64);
-    k_flux_rev_own<64><<<g64, 64, 0, S(stream)>>>(g, f, p->spw, w.q, dqK, w.qlim, Rbar, w.qbar,
-                                                  w.sa, w.lbar, p->status);
-    k_flux_gather<64><<<g64, 64, 0, S(stream)>>>(g, f, p->in_cnt, p->in_ent, p->lsg, p->spw, w.q,
-                                                 dqK, w.qlim, Rbar, w.qbar, w.sa, w.lbar);
+    if (f.gamma_is_14) {
+      k_flux_rev_own<64, true><<<g64, 64, 0, S(stream)>>>(g, f, p->spw, w.q, dqK, w.qlim, Rbar,
+                                                          w.qbar, w.sa, w.lbar, p->status);
+      k_flux_gather<64, true><<<g64, 64, 0, S(stream)>>>(g, f, p->in_cnt, p->in_ent, p->lsg,
+                                                         p->spw, w.q, dqK, w.qlim, Rbar, w.qbar,
+                                                         w.sa, w.lbar);
+    } else {
+      k_flux_rev_own<64, false><<<g64, 64, 0, S(stream)>>>(g, f, p->spw, w.q, dqK, w.qlim, Rbar,
+                                                           w.qbar, w.sa, w.lbar, p->status);
+      k_flux_gather<64, false><<<g64, 64, 0, S(stream)>>>(g, f, p->in_cnt, p->in_ent, p->lsg,
+                                                          p->spw, w.q, dqK, w.qlim, Rbar, w.qbar,
+                                                          w.sa, w.lbar);
+    }
   }
   // the derivative reverses on the in-edge tile tables when a block's
   // table fits the LDS budget
