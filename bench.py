@@ -106,7 +106,7 @@ def oracle_stages(cloud, wl, U_host, options: int, n_inner: int, min_seconds: fl
 
 
 def cpu_baseline(cloud, wl, U_host, options: int = 0, n_inner=None, min_seconds: float = 10.0,
-                 all_cores: bool = True):
+                 all_cores: bool = True, state: str = "the initial state"):
     """The oracle, as it stands, on whole RK stages of the workload (same
     scheme options and inner sweeps as the GPU run), single-threaded (the
     parity build), repeated until at least `min_seconds` (one stage over the
@@ -117,7 +117,7 @@ def cpu_baseline(cloud, wl, U_host, options: int = 0, n_inner=None, min_seconds:
     n_inner = wl.n_inner if n_inner is None else n_inner
     what = (f"RK stages (local time step per 4 stages, q-variables, first-order + {n_inner} "
             f"inner LS sweeps, flux residual, stage update) over all {cloud.n} points of the "
-            f"{wl.name} cloud from the initial state" + (f", options {options}" if options else ""))
+            f"{wl.name} cloud from {state}" + (f", options {options}" if options else ""))
     stages, sec = oracle_stages(cloud, wl, U_host, options, n_inner, min_seconds)
     out = {"value": cloud.n * stages / sec, "unit": "point-stage updates/s", "cores": 1,
            "kind": "oracle", "sample": f"{stages} {what}, single thread, {sec:.1f} s",
@@ -484,14 +484,29 @@ def bench_ksweep(args) -> int:
 
 
 SUSTAINED_ITERS = 1000
+# iterations that develop the flow before timing.  From the free stream the
+# disturbance of the body crosses the 1M cloud's 1000 point layers in about
+# 50 iterations (each stage reads n_inner + 2 = 5 stencil hops), the 16M
+# cloud's 4000 in about 200; ahead of it the derivatives are exactly zero
+# and the flux kernel skips its limiter divisions.  The 1M workload's input
+# is the state half-way through its 1000 iterations (measured: 0.583 ms per
+# flux launch from the free stream, 0.590 after 200 iterations, 0.614 after
+# 1000); the 16M object's, the state once the disturbance has crossed it.
+PREPARE_ITERS = 500
+PREPARE_ITERS_16M = 200
 BATCH_ITERS = 500
 
 
 def run_sweep(cloud, wl, steps: int, warm: int, options: int, n_inner: int,
-              keep_initial: bool = True, tuning=None) -> dict:
+              keep_initial: bool = True, tuning=None, prepare: int = 0) -> dict:
     """Time `steps` iterations (after `warm` untimed ones) of the whole
-    iteration on `cloud` from the initial state, issued from Python one
-    entry point at a time, with HIP events around every flux launch."""
+    iteration on `cloud`, issued from Python one entry point at a time, with
+    HIP events around every flux launch.  The input state is the free stream
+    advanced `prepare` iterations (untimed, through the library's own loop):
+    from the free stream, the points the disturbance of the body has not yet
+    reached have exactly zero derivatives, where the flux kernel skips its
+    limiter divisions, so the first iterations are not representative of a
+    run."""
     import numpy as np
     import torch
 
@@ -504,7 +519,14 @@ def run_sweep(cloud, wl, steps: int, warm: int, options: int, n_inner: int,
     plan = L.Plan(cloud, p, tuning=tuning)
     U = plan.field(4)
     L.lskum_init_state(plan, U)
-    # the initial state in the oracle's layout (4, n), for the CPU baseline
+    if prepare > 0:
+        ws = L.workspace(plan)
+        L.lskum_iterate(plan, prepare, U, None, ws)
+        torch.cuda.synchronize()
+        del ws
+        if L.lskum_status(plan) != L.OK:
+            raise RuntimeError("the prepared state is not physical")
+    # the input state in the oracle's layout (4, n), for the CPU baseline
     U0_host = U.cpu().numpy().T.copy() if keep_initial else None
     Un, q, dq, qlim, work, R = (plan.field(c) for c in (4, 4, 8, 8, 16, 4))
     dt, acc, q2 = plan.field(1), plan.field(4), plan.field(4)
@@ -602,6 +624,11 @@ def main():
                     help="scheme variant of the sweep (default: the paper's second-order "
                          "scheme with the Venkatakrishnan limiter and SSPRK(4,3); rk4: the "
                          "same residual with classical RK4 stages)")
+    ap.add_argument("--prepare", type=int, default=PREPARE_ITERS,
+                    help="untimed iterations that develop the flow before the warm-up "
+                         "(the timed input state); 0 times from the free stream")
+    ap.add_argument("--prepare-16m", type=int, default=PREPARE_ITERS_16M,
+                    help="the same for the 16m object of the default 1m line")
     ap.add_argument("--tuning", default=None,
                     help="launch tuning of the timed plan as block/xcd_contiguous/flux_block, "
                          "e.g. 256/1/64 (default: the library's)")
@@ -673,7 +700,7 @@ def main():
     if args.tuning:
         b, x, fb = (int(v) for v in args.tuning.split("/"))
         tuning = L.Tuning(b, x, fb)
-    r = run_sweep(cloud, wl, steps, warm, options, n_inner, tuning=tuning)
+    r = run_sweep(cloud, wl, steps, warm, options, n_inner, tuning=tuning, prepare=args.prepare)
     plan, U, sec, flux_ms, h, status = (r[k] for k in ("plan", "U", "sec", "flux_ms", "hist",
                                                        "status"))
     n, edges = cloud.n, r["edges"]
@@ -696,6 +723,8 @@ def main():
                                + ("" if args.scheme == "default" else f", scheme {args.scheme}"),
                    "points": n, "edges": edges, "k_pad": cloud.k_pad, "iterations": steps,
                    "stages_per_iteration": 4,
+                   "input_state": f"free stream advanced {args.prepare} iterations (untimed) "
+                                  "before the warm-up",
                    "tuning": (tuning or L.Tuning()).key()},
         "roofline": r["roofline"],
         "hbm_compulsory": r["hbm_compulsory"],
@@ -735,18 +764,22 @@ def main():
             f"ratio {adj['ratio']:.3f}")
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle (one thread, then all cores)")
-        out["cpu_baseline"] = cpu_baseline(cloud, wl, r["U0_host"], options, n_inner)
+        out["cpu_baseline"] = cpu_baseline(
+            cloud, wl, r["U0_host"], options, n_inner,
+            state=f"the GPU's input state (free stream + {args.prepare} iterations)")
     del plan, U, r
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     if cloud16 is not None:
         w16 = WORKLOADS["16m"]
-        log("[bench] 16m: 2 warm-up + 10 timed iterations")
-        r16 = run_sweep(cloud16, w16, 10, 2, 0, w16.n_inner, keep_initial=False)
+        log(f"[bench] 16m: prepare {args.prepare_16m}, 2 warm-up + 10 timed iterations")
+        r16 = run_sweep(cloud16, w16, 10, 2, 0, w16.n_inner, keep_initial=False,
+                        prepare=args.prepare_16m)
         out["16m"] = {
             "workload": f"16m: NACA 0012 O-type airfoil cloud {w16.W} x {w16.L}, k_max "
                         f"{w16.k_max}, M {w16.mach}, AoA {w16.aoa_deg} deg, n_inner {w16.n_inner}",
             "points": cloud16.n, "edges": r16["edges"], "iterations": 10, "warmup": 2,
+            "input_state": f"free stream advanced {args.prepare_16m} iterations (untimed)",
             "ms_per_step": r16["sec"] * 1e3 / 10,
             "value": cloud16.n * 4.0 * 10 / r16["sec"], "unit": "point-stage updates/s",
             "roofline": r16["roofline"], "hbm_compulsory": r16["hbm_compulsory"],

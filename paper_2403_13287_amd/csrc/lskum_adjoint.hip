@@ -79,7 +79,7 @@ __device__ __forceinline__ void split_flux_rev(double sg, const EndState &s, dou
                                                const double Gb[4], EndBar &b, double &udb,
                                                double &uob) {
   const double S = ud * s.sqb;
-  const double ex = exp(-(S * S));
+  const double ex = lskum_math::lk_exp(-(S * S));
   const double A = 0.5 * (1.0 + sg * lskum_math::lk_erf(S));
   const double B = ex * s.bcoef;
   const double F = ud * A + sg * B;

@@ -304,9 +304,9 @@ __device__ __forceinline__ unsigned end_state_t(const double qt[4], const Flow &
   const double uu = u * u + v * v;
   double rho;
   if (G14 == 1 || (G14 < 0 && P.gamma_is_14))
-    rho = exp(qt[0] + beta * uu) * (rsb * ib * ib);
+    rho = lskum_math::lk_exp(qt[0] + beta * uu) * (rsb * ib * ib);
   else
-    rho = exp(qt[0] + beta * uu - log(beta) * P.inv_gm1);
+    rho = lskum_math::lk_exp(qt[0] + beta * uu - log(beta) * P.inv_gm1);
   const double p = rho * inv2b;
   s.rho = rho;
   s.p = p;
@@ -335,7 +335,7 @@ __device__ __forceinline__ void split_flux(double sg, const EndState &s, double 
                                            double G[4]) {
   const double S = ud * s.sqb;
   const double A = 0.5 * (1.0 + sg * lskum_math::lk_erf(S));
-  const double B = exp(-(S * S)) * s.bcoef;
+  const double B = lskum_math::lk_exp(-(S * S)) * s.bcoef;
   const double F = ud * A + sg * B;
   G[0] = s.rho * F;
   G[1] = (s.p + s.rho * ud * ud) * A + sg * s.rho * ud * B;

@@ -1,5 +1,6 @@
 """Accuracy of the flux kernel's Newton-refined divide and rsqrt and of its
-erf (lskum_math.h) on the GPU, against numpy / scipy double precision."""
+erf and exp (lskum_math.h) on the GPU, against numpy / scipy double
+precision."""
 import ctypes
 import numpy as np
 import pytest
@@ -66,3 +67,21 @@ def test_erf(calib):
     assert rel.max() <= 3 * ULP, rel.max()
     assert np.array_equal(calib(11, -x), -got)
     assert np.all(np.isnan(calib(11, np.array([np.nan]))))
+
+
+def test_exp(calib):
+    """lk_exp within 2 ulp (relative) of numpy's exp over the whole finite
+    range, 0 below the underflow threshold, +inf above the overflow one,
+    NaN for NaN; exact at 0."""
+    rng = np.random.Generator(np.random.PCG64(6))
+    x = np.concatenate([rng.uniform(-1, 1, 100000), rng.uniform(-50, 5, 200000),
+                        rng.uniform(-708, 709, 100000), [0.0, -0.0, 1.0, -1.0, 0.5, 700.0]])
+    got = calib(12, x)
+    ref = np.exp(x)
+    rel = np.abs(got - ref) / ref
+    assert rel.max() <= 2 * ULP, rel.max()
+    assert calib(12, np.array([0.0]))[0] == 1.0
+    edge = calib(12, np.array([-800.0, -1e10, 720.0, 1e10, np.nan]))
+    assert edge[0] == 0.0 and edge[1] == 0.0
+    assert np.isinf(edge[2]) and np.isinf(edge[3]) and edge[2] > 0
+    assert np.isnan(edge[4])
