@@ -141,6 +141,11 @@ ELEMENTARY_RANGES = {
     4: ("sqrt", 1e-8, 1e-2),   # edge length squared
     5: ("rsqrt", 0.3, 3.0),    # beta
     6: ("divide", 0.1, 3.0),
+    # the flux kernel's own versions (lskum_math.h)
+    9: ("lk_div", 0.1, 3.0),
+    10: ("lk_rsqrt", 0.3, 3.0),
+    11: ("lk_erf", -2.5, 2.5),
+    12: ("lk_exp", -6.0, 1.0),
 }
 
 
@@ -498,7 +503,8 @@ BATCH_ITERS = 500
 
 
 def run_sweep(cloud, wl, steps: int, warm: int, options: int, n_inner: int,
-              keep_initial: bool = True, tuning=None, prepare: int = 0) -> dict:
+              keep_initial: bool = True, tuning=None, prepare: int = 0,
+              save_input: str | None = None, load_input: str | None = None) -> dict:
     """Time `steps` iterations (after `warm` untimed ones) of the whole
     iteration on `cloud`, issued from Python one entry point at a time, with
     HIP events around every flux launch.  The input state is the free stream
@@ -519,6 +525,14 @@ def run_sweep(cloud, wl, steps: int, warm: int, options: int, n_inner: int,
     plan = L.Plan(cloud, p, tuning=tuning)
     U = plan.field(4)
     L.lskum_init_state(plan, U)
+    if load_input:
+        # a state saved by an earlier run with --save-input (e.g. prepared
+        # outside a per-dispatch counter profiler)
+        U_in = np.load(load_input)
+        if U_in.shape != (n, 4) or U_in.dtype != np.float64:
+            raise ValueError(f"{load_input}: need a float64 array of shape ({n}, 4)")
+        U.copy_(torch.from_numpy(U_in))
+        prepare = 0
     if prepare > 0:
         ws = L.workspace(plan)
         L.lskum_iterate(plan, prepare, U, None, ws)
@@ -526,6 +540,8 @@ def run_sweep(cloud, wl, steps: int, warm: int, options: int, n_inner: int,
         del ws
         if L.lskum_status(plan) != L.OK:
             raise RuntimeError("the prepared state is not physical")
+    if save_input:
+        np.save(save_input, U.cpu().numpy())
     # the input state in the oracle's layout (4, n), for the CPU baseline
     U0_host = U.cpu().numpy().T.copy() if keep_initial else None
     Un, q, dq, qlim, work, R = (plan.field(c) for c in (4, 4, 8, 8, 16, 4))
@@ -629,6 +645,11 @@ def main():
                          "(the timed input state); 0 times from the free stream")
     ap.add_argument("--prepare-16m", type=int, default=PREPARE_ITERS_16M,
                     help="the same for the 16m object of the default 1m line")
+    ap.add_argument("--save-input", default=None,
+                    help="save the timed input state (after --prepare) as .npy")
+    ap.add_argument("--load-input", default=None,
+                    help="take the timed input state from a .npy saved by --save-input "
+                         "(no --prepare iterations)")
     ap.add_argument("--tuning", default=None,
                     help="launch tuning of the timed plan as block/xcd_contiguous/flux_block, "
                          "e.g. 256/1/64 (default: the library's)")
@@ -700,7 +721,8 @@ def main():
     if args.tuning:
         b, x, fb = (int(v) for v in args.tuning.split("/"))
         tuning = L.Tuning(b, x, fb)
-    r = run_sweep(cloud, wl, steps, warm, options, n_inner, tuning=tuning, prepare=args.prepare)
+    r = run_sweep(cloud, wl, steps, warm, options, n_inner, tuning=tuning, prepare=args.prepare,
+                  save_input=args.save_input, load_input=args.load_input)
     plan, U, sec, flux_ms, h, status = (r[k] for k in ("plan", "U", "sec", "flux_ms", "hist",
                                                        "status"))
     n, edges = cloud.n, r["edges"]
@@ -723,8 +745,9 @@ def main():
                                + ("" if args.scheme == "default" else f", scheme {args.scheme}"),
                    "points": n, "edges": edges, "k_pad": cloud.k_pad, "iterations": steps,
                    "stages_per_iteration": 4,
-                   "input_state": f"free stream advanced {args.prepare} iterations (untimed) "
-                                  "before the warm-up",
+                   "input_state": (f"loaded from {args.load_input}" if args.load_input else
+                                   f"free stream advanced {args.prepare} iterations (untimed) "
+                                   "before the warm-up"),
                    "tuning": (tuning or L.Tuning()).key()},
         "roofline": r["roofline"],
         "hbm_compulsory": r["hbm_compulsory"],
@@ -755,8 +778,10 @@ def main():
     if wl.name == "1m" and not args.no_adjoint and not options & (L.FIRST_ORDER | L.MINMAX):
         log("[bench] timing the residual VJP against the forward residual")
         adj = time_adjoint(plan, U, reps=20, warmup=5)
-        adj["state"] = (f"the {wl.name} state after the {warm + steps} iterations above"
-                        + (f" and {SUSTAINED_ITERS} more" if headline else ""))
+        adj["state"] = (f"the {wl.name} state after the input state's {args.prepare} iterations, "
+                        f"the {warm + steps} above"
+                        + (f" and {SUSTAINED_ITERS} more" if headline and not args.no_sustained
+                           else ""))
         adj["cotangents"] = "N(0, 1), seed 7"
         adj["status"] = L.strerror(L.lskum_status(plan))
         out["adjoint"] = adj
