@@ -35,6 +35,7 @@ __global__ void __launch_bounds__(256) k_elem(int64_t n, const double *__restric
   if constexpr (F == 10) r = lskum_math::lk_rsqrt(a);
   if constexpr (F == 11) r = lskum_math::lk_erf(a);
   if constexpr (F == 12) r = lskum_math::lk_exp(a);
+  if constexpr (F == 13) r = lskum_math::lk_div1(y[i], a);
   out[i] = r;
 }
 
@@ -44,11 +45,11 @@ extern "C" {
 
 // fn: 0 copy (baseline), 1 exp, 2 erf, 3 log, 4 sqrt, 5 rsqrt, 6 divide
 // y[i] / x[i]; the sweep's versions: 9 lk_div y[i] / x[i], 10 lk_rsqrt,
-// 11 lk_erf, 12 lk_exp.  x, y, out: device arrays of n doubles.  Returns 0, or -1 for
+// 11 lk_erf, 12 lk_exp, 13 lk_div1 y[i] / x[i].  x, y, out: device arrays of n doubles.  Returns 0, or -1 for
 // a bad argument, -3 for a failed launch.
 int lskum_calib_elementary(int fn, int64_t n, const double *x, const double *y, double *out,
                            void *stream) {
-  if (n <= 0 || !x || !out || ((fn == 6 || fn == 9) && !y)) return -1;
+  if (n <= 0 || !x || !out || ((fn == 6 || fn == 9 || fn == 13) && !y)) return -1;
   const dim3 grid((unsigned)((n + 255) / 256));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   switch (fn) {
@@ -63,6 +64,7 @@ int lskum_calib_elementary(int fn, int64_t n, const double *x, const double *y, 
     case 10: k_elem<10><<<grid, 256, 0, s>>>(n, x, y, out); break;
     case 11: k_elem<11><<<grid, 256, 0, s>>>(n, x, y, out); break;
     case 12: k_elem<12><<<grid, 256, 0, s>>>(n, x, y, out); break;
+    case 13: k_elem<13><<<grid, 256, 0, s>>>(n, x, y, out); break;
     default: return -1;
   }
   return hipGetLastError() == hipSuccess ? 0 : -3;

@@ -58,7 +58,7 @@ __device__ __forceinline__ LimRev limited_rev(double delta, double room_max, dou
   const double D = delta > 0.0 ? room_max : room_min;
   const double num = D * D + eps2 + 2.0 * delta * D;
   const double den = D * D + 2.0 * delta * delta + delta * D + eps2;
-  const double r = lk_div(num, den);
+  const double r = lskum_math::lk_div1(num, den);  // the forward's quotient
   if (!(r < 1.0)) return LimRev{ob, 0.0, 0};  // phi = 1
   // r = num/den: dr/ddelta = (2D - r (4 delta + D))/den,
   //              dr/dD     = (2D + 2 delta - r (2D + delta))/den

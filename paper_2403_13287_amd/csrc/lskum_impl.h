@@ -245,7 +245,7 @@ __device__ __forceinline__ double limited(double delta, double room_max, double 
   const double D = delta > 0.0 ? room_max : room_min;
   const double num = D * D + eps2 + 2.0 * delta * D;
   const double den = D * D + 2.0 * delta * delta + delta * D + eps2;
-  const double phi = delta == 0.0 ? 1.0 : fmin(1.0, lk_div(num, den));
+  const double phi = delta == 0.0 ? 1.0 : fmin(1.0, lskum_math::lk_div1(num, den));
   return phi * delta;
 }
 

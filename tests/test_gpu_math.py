@@ -42,6 +42,12 @@ def test_div_and_rsqrt(calib):
     got = calib(9, b, a)
     rel = np.abs(got - a / b) / np.abs(a / b)
     assert rel.max() <= 2 * ULP, rel.max()
+    # one Newton step on the hardware reciprocal, no correction (the
+    # limiter's quotient): the estimate's relative error e0 leaves e0^2
+    # plus the rounding of three operations
+    got = calib(13, b, a)
+    rel = np.abs(got - a / b) / np.abs(a / b)
+    assert rel.max() <= 16 * ULP, rel.max()
     x = np.exp(rng.uniform(-40, 40, 200000))
     got = calib(10, x)
     ref = 1.0 / np.sqrt(x)

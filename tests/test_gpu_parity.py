@@ -256,6 +256,43 @@ def test_parity_1m_bench_configuration():
 
 
 @pytest.mark.timeout(600)
+def test_parity_1m_developed_state():
+    """The 1M-point workload at the benchmark's input state (the free stream
+    advanced 500 iterations through lskum_iterate, where every limiter is
+    active): q, dq, qlim and R of that state, then one more lskum_iterate
+    iteration, against the oracle on the whole cloud from the same state."""
+    wl = WORKLOADS["1m"]
+    say("generating the 1M cloud")
+    cloud = wl.cloud()
+    p = params_of(wl)
+    s = Solver(cloud, p)
+    say("500 GPU iterations at 1M")
+    s.run(500)
+    assert s.status() == L.OK
+    U0 = down(s.U)
+    q, dq, qlim, R = s.residual()
+    o = oracle_of(cloud, p)
+    say("oracle residual at the developed 1M state")
+    qo, _ = o.q_vars(U0)
+    dqo, qlimo = o.q_derivs(qo)
+    Ro, flags = o.flux_residual(qo, dqo, qlimo)
+    assert flags == 0
+    assert_field("q 1M developed", down(q), qo)
+    assert_field("dq 1M developed", down(dq), dqo)
+    assert_field("qlim 1M developed", down(qlim), qlimo)
+    assert_field("R 1M developed", down(R), Ro)
+    say("oracle iteration from the developed 1M state")
+    h = s.run(1)
+    U1o, h1o, flags = o.iterate(U0, 1)
+    assert flags == 0
+    assert float(host(h)[0]) == pytest.approx(h1o[0], rel=HIST_TOL)
+    U1 = down(s.U)
+    assert_field("U after one iteration from the developed 1M state", U1, U1o)
+    assert normwise(U1 - U0, U1o - U0) <= 1e-8
+    assert s.status() == L.OK
+
+
+@pytest.mark.timeout(600)
 def test_parity_16m_sampled_points():
     """The 16M-point workload after 2 GPU iterations: q, dq, qlim and R at
     sampled points (random interior and wall points, and the wall points
