@@ -30,15 +30,15 @@ import os
 # measured FP64 operations per call (FMA = 2), calibration kernels, gfx950
 ELEMENTARY_FLOPS = {"exp": 27, "erf": 54.4, "log": 79, "sqrt": 17, "rsqrt": 9, "div": 14}
 
-EDGE_FLOPS = 580.6  # flux kernel, FP64 operations per (point, neighbour) pair
+EDGE_FLOPS = 569.3  # flux kernel, FP64 operations per (point, neighbour) pair
 # the SSP stage update and the q-variables of the new state (eq. (13)) run
 # as the flux launch's epilogue: FP64 operations per point, the difference
 # of the fused and the plain flux launch's SQ_INSTS_VALU_FLOPS_FP64 over the
-# points of the 1M cloud (1.7625e10 - 580.6 x 29,967,646, averaged over the
+# points of the 1M cloud (1.7286e10 - 569.3 x 29,967,646, averaged over the
 # four stages).  The fused total is what the counters fix; the split moves
 # with the state the plain launch is counted on (the RK4 run's) by a few
 # operations per edge.
-STAGE_FLOPS = 224.9
+STAGE_FLOPS = 226.2
 
 
 def flux_flops(n_points: int, n_edges: int, stage: bool = False) -> float:
