@@ -496,9 +496,10 @@ SUSTAINED_ITERS = 1000
 # and the flux kernel skips its limiter divisions.  The 1M workload's input
 # is the state half-way through its 1000 iterations (measured: 0.583 ms per
 # flux launch from the free stream, 0.590 after 200 iterations, 0.614 after
-# 1000); the 16M object's, the state once the disturbance has crossed it.
+# 1000); the 16M object's, the state well after the disturbance has crossed
+# it.
 PREPARE_ITERS = 500
-PREPARE_ITERS_16M = 200
+PREPARE_ITERS_16M = 400
 BATCH_ITERS = 500
 
 
