@@ -156,12 +156,13 @@ __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__res
     EndState sj, s0;
     f |= end_state<G14 ? 1 : 0>(qtj, P, tx, ty, nx, ny, sj);
     f |= end_state<G14 ? 1 : 0>(qt0, P, tx, ty, nx, ny, s0);
-    const F8 W = rd8(s_w, threadIdx.x);
 
     // s-direction split: ds < 0 -> G_s^+, ds > 0 -> G_s^-
     {
       const bool pos = ds < 0.0;
-      const double wa = pos ? W.v[0] : W.v[2], wb = pos ? W.v[1] : W.v[3];
+      // only the pair of the side the edge falls on is read: plane 0 (s+) or 1 (s-)
+      const double2 wp = s_w[pos ? 0 : 1][threadIdx.x];
+      const double wa = wp.x, wb = wp.y;
       const double wt = ds != 0.0 ? wa * ds + wb * dn : 0.0;
       const double sg = pos ? 1.0 : -1.0;
       double Gj[4], G0[4];
@@ -175,7 +176,8 @@ __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__res
     // n-direction split: dn < 0 -> G_n^+ (interior only), dn > 0 -> G_n^-
     {
       const bool pos = dn < 0.0;
-      const double wa = pos ? W.v[4] : W.v[6], wb = pos ? W.v[5] : W.v[7];
+      const double2 wp = s_w[pos ? 2 : 3][threadIdx.x];  // n+ or n-
+      const double wa = wp.x, wb = wp.y;
       const bool used = dn > 0.0 || (pos && interior);
       const double wt = used ? wa * ds + wb * dn : 0.0;
       const double sg = pos ? 1.0 : -1.0;
