@@ -277,40 +277,56 @@ struct lskum_graph_s {
 
 namespace lskum_impl {
 
-int tile_slots(int32_t n, int32_t width, int blk, const int32_t *ids, const int32_t *cnt,
-               std::vector<int32_t> &slots, std::vector<int32_t> &hoff,
-               std::vector<int32_t> &hids, int &hmax) {
-  const int32_t nt = (n + blk - 1) / blk;
+int tile_slots(int32_t n, int32_t width, int blk, int cap, const int32_t *ids,
+               const int32_t *cnt, std::vector<int32_t> &slots, std::vector<int32_t> &tlo,
+               std::vector<int32_t> &hoff, std::vector<int32_t> &hids, int &hmax) {
   std::vector<int32_t> ext;
+  // the out-of-tile points named by the rows of points lo .. hi-1, ascending
+  auto halo = [&](int32_t lo, int32_t hi) {
+    ext.clear();
+    for (int32_t i = lo; i < hi; ++i)
+      for (int32_t s = 0; s < cnt[i]; ++s) {
+        const int32_t j = ids[(size_t)s * n + i];
+        if (j < lo || j >= hi) ext.push_back(j);
+      }
+    std::sort(ext.begin(), ext.end());
+    ext.erase(std::unique(ext.begin(), ext.end()), ext.end());
+  };
   hmax = 0;
   try {
     slots.resize((size_t)width * n);
-    hoff.assign((size_t)nt + 1, 0);
+    tlo.assign(1, 0);
+    hoff.assign(1, 0);
     hids.clear();
     hids.reserve((size_t)n);
-    for (int32_t t = 0; t < nt; ++t) {
-      const int32_t lo = t * blk, hi = std::min(n, lo + blk);
-      ext.clear();
-      for (int32_t i = lo; i < hi; ++i)
-        for (int32_t s = 0; s < cnt[i]; ++s) {
-          const int32_t j = ids[(size_t)s * n + i];
-          if (j < lo || j >= hi) ext.push_back(j);
+    for (int32_t lo = 0; lo < n;) {
+      int32_t size = std::min<int32_t>(blk, n - lo);
+      halo(lo, lo + size);
+      if (cap > 0)
+        while (size > 1 && size + (int64_t)ext.size() > cap) {
+          size = size > 8 ? size - 8 : size - 1;
+          halo(lo, lo + size);
         }
-      std::sort(ext.begin(), ext.end());
-      ext.erase(std::unique(ext.begin(), ext.end()), ext.end());
-      if ((int64_t)blk + (int64_t)ext.size() > 65535) return LSKUM_ERR_INVALID_ARG;
-      hmax = std::max(hmax, (int)ext.size());
-      hoff[(size_t)t + 1] = hoff[(size_t)t] + (int32_t)ext.size();
+      const int32_t hi = lo + size, base = size;
+      if ((int64_t)base + (int64_t)ext.size() > 65535) return LSKUM_ERR_INVALID_ARG;
+      hmax = std::max(hmax, base + (int)ext.size() - blk);
+      hoff.push_back(hoff.back() + (int32_t)ext.size());
       hids.insert(hids.end(), ext.begin(), ext.end());
+      tlo.push_back(hi);
       for (int32_t i = lo; i < hi; ++i)
         for (int32_t s = 0; s < width; ++s) {
           const int32_t j = s < cnt[i] ? ids[(size_t)s * n + i] : i;
           slots[(size_t)s * n + i] =
               (j >= lo && j < hi)
                   ? j - lo
-                  : blk + (int32_t)(std::lower_bound(ext.begin(), ext.end(), j) - ext.begin());
+                  : base + (int32_t)(std::lower_bound(ext.begin(), ext.end(), j) - ext.begin());
         }
+      lo = hi;
     }
+    // a spare entry (point 0) after the last tile's halo: readers clamp
+    // their indices into a tile's list, which then stays in bounds when the
+    // list is empty
+    hids.push_back(0);
   } catch (const std::bad_alloc &) {
     return LSKUM_ERR_NO_MEMORY;
   }
@@ -324,10 +340,19 @@ namespace {
 int build_tile_map(lskum_plan_s *p, int blk, const int32_t *nbr, const int32_t *cnt) {
   TileMap &m = p->maps[tile_index(blk)];
   if (m.blk == blk) return LSKUM_OK;
-  std::vector<int32_t> slots, hoff, hids;
+  std::vector<int32_t> slots, tlo, hoff, hids;
   std::vector<uint16_t> lcol;
   int hmax = 0;
-  int rc = tile_slots(p->n, p->k_pad, blk, nbr, cnt, slots, hoff, hids, hmax);
+  // Tiles capped at 2 blk table slots: the inner sweep's table (80 B a
+  // slot) then takes 40 KB at blk = 256, four blocks to a CU's 160 KB where
+  // the largest halo of fixed tiles would allow three.  Where capping
+  // shrinks the tiles a lot (clouds not ordered along a space-filling
+  // curve), fixed tiles instead: their tables exceed the LDS budget and the
+  // direct-gather kernels run.
+  int rc = tile_slots(p->n, p->k_pad, blk, 2 * blk, nbr, cnt, slots, tlo, hoff, hids, hmax);
+  const int64_t fixed_tiles = ((int64_t)p->n + blk - 1) / blk;
+  if (!rc && (int64_t)tlo.size() - 1 > fixed_tiles + fixed_tiles / 8 + 8)
+    rc = tile_slots(p->n, p->k_pad, blk, 0, nbr, cnt, slots, tlo, hoff, hids, hmax);
   if (rc) return rc;
   try {
     lcol.assign(slots.begin(), slots.end());
@@ -335,10 +360,13 @@ int build_tile_map(lskum_plan_s *p, int blk, const int32_t *nbr, const int32_t *
     return LSKUM_ERR_NO_MEMORY;
   }
   if ((rc = upload(&m.lcol, lcol.data(), lcol.size())) ||
+      (rc = upload(&m.tlo, tlo.data(), tlo.size())) ||
       (rc = upload(&m.hoff, hoff.data(), hoff.size())) ||
       (rc = upload(&m.hids, hids.data(), hids.size())))
     return rc;
   m.hmax = (hmax + 3) / 4 * 4;
+  m.rows = p->k_pad;
+  m.ntiles = (int)tlo.size() - 1;
   m.blk = blk;
   return LSKUM_OK;
 }
@@ -412,6 +440,7 @@ void release(lskum_plan_s *p) {
                   p->in_cnt, p->in_ent, p->spw, p->lsg, p->outer, p->ooff};
   for (void *b : bufs) (void)hipFree(b);
   for (TileMap &m : p->maps) {
+    (void)hipFree(m.tlo);
     (void)hipFree(m.lcol);
     (void)hipFree(m.hoff);
     (void)hipFree(m.hids);

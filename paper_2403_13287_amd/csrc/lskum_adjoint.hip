@@ -788,6 +788,7 @@ __global__ void __launch_bounds__(BLK) k_first_rev_t(Geo G, Flow P, Tiles T,
     }
   }
   const int h0 = T.hoff[tile];
+  const int hb = n - lo < BLK ? n - lo : BLK;  // the tile's points; its halo slots follow
   auto edge = [&](uint32_t ent) {
     const int sl = (int)(ent & 0xffffu);
     const int slot = (int)(ent >> 16);
@@ -799,7 +800,7 @@ __global__ void __launch_bounds__(BLK) k_first_rev_t(Geo G, Flow P, Tiles T,
     bool hit = false;
     for (int h = 0; h < 8; ++h) hit |= (int8_t)(ai >> (8 * h)) == slot;
     if (hit) {
-      const int i = sl < BLK ? lo + sl : T.hids[h0 + sl - BLK];
+      const int i = sl < hb ? lo + sl : T.hids[h0 + sl - hb];
       const F8 li8 = ld8(lbar, i);
       for (int m = 0; m < 4; ++m) {
         if ((int8_t)(ai >> (8 * m)) == slot) qb[m] += li8.v[m];
@@ -1099,7 +1100,7 @@ int ensure_in_tiles(lskum_plan_s *p, void *stream) {
   (void)hipFree(m.hids);
   m = InTileMap{};
   const int32_t n = p->n, ki = p->k_in;
-  std::vector<int32_t> ent, cnt, ids, slots, hoff, hids;
+  std::vector<int32_t> ent, cnt, ids, slots, tlo, hoff, hids;
   std::vector<uint32_t> lent;
   int hmax = 0, rc;
   if ((rc = download(ent, p->in_ent, (size_t)ki * n)) || (rc = download(cnt, p->in_cnt, (size_t)n)))
@@ -1110,7 +1111,8 @@ int ensure_in_tiles(lskum_plan_s *p, void *stream) {
   } catch (const std::bad_alloc &) {
     return LSKUM_ERR_NO_MEMORY;
   }
-  if ((rc = tile_slots(n, ki, p->block, ids.data(), cnt.data(), slots, hoff, hids, hmax)))
+  if ((rc = tile_slots(n, ki, p->block, 0, ids.data(), cnt.data(), slots, tlo, hoff, hids,
+                       hmax)))
     return rc;
   try {
     lent.resize(slots.size());

@@ -190,12 +190,14 @@ __global__ void __launch_bounds__(BLK) k_deriv_inner(Geo G, const double *__rest
 // ---------------------------------------------------------------------------
 // derivative passes on LDS tables (tile maps)
 //
-// Block b stages in LDS the records of its BLK points and of their
-// out-of-tile neighbours (the tile's halo, a few hundred points for a
-// Hilbert-ordered cloud), loaded by all threads at once with no dependent
-// round trips; each row is stored as table slots (uint16), so the gather
-// loop reads LDS only.  Same arithmetic, in the same order, as k_deriv_first
-// and k_deriv_inner, which remain the path for clouds whose halos do not fit.
+// Block b stages in LDS the records of the points of tile b (up to BLK
+// consecutive points, fewer where their halo would make the table exceed
+// 2 BLK slots) and of their out-of-tile neighbours (the tile's halo, a few
+// hundred points for a Hilbert-ordered cloud), loaded by all threads at
+// once: the halo ids, then the records, are the only dependent round trips;
+// each row is stored as table slots (uint16), so the gather loop reads LDS
+// only.  Same arithmetic, in the same order, as k_deriv_first and
+// k_deriv_inner, which remain the path for clouds whose halos do not fit.
 
 // Reader of point i's row of table slots; entries past the count return
 // the point's own slot (prefetching ahead never leaves the row).
@@ -219,8 +221,8 @@ __global__ void __launch_bounds__(BLK) k_deriv_first_t(Geo G, Tiles T,
   extern __shared__ __align__(64) unsigned char smem[];
   const int n = G.n;
   const int tile = block_id(G.xcd);
-  const int lo = tile * BLK;
-  if (lo >= n) return;  // blocks past the last tile (the grid is a multiple of 8)
+  if (tile >= T.ntiles) return;  // blocks past the last tile (the grid is a multiple of 8)
+  const int lo = T.tlo[tile], hi = T.tlo[tile + 1];
   const int cap = BLK + T.hmax;
   // 16-byte planes (coordinates, q0 q1, q2 q3): random-slot reads spread
   // over all LDS banks, where whole 32-byte records would share few
@@ -231,18 +233,22 @@ __global__ void __launch_bounds__(BLK) k_deriv_first_t(Geo G, Tiles T,
     return F4{{a.x, a.y, b.x, b.y}};
   };
   const int i = lo + threadIdx.x;
-  const int c = i < n ? G.cnt[i] : 0;
+  int c = 0;
   SlotRegs<KMAX ? KMAX : 1> sr;
-  if (KMAX && i < n) sr.load(T.lcol + i, n, c, threadIdx.x);
   stage_tile<BLK, XyQ>(
-      T, tile, lo, n, [&](int p) { return XyQ{G.xy[p], ld4(q, p)}; },
+      T, tile, lo, hi, hi - lo, [&](int p) { return XyQ{G.xy[p], ld4(q, p)}; },
       [&](int sl, const XyQ &r) {
         s_xy[sl] = r.xy;
         s_q[sl] = make_double2(r.q.v[0], r.q.v[1]);
         s_q[cap + sl] = make_double2(r.q.v[2], r.q.v[3]);
+      },
+      [&] {
+        const int ic = i < hi ? i : hi - 1;
+        c = G.cnt[ic];
+        if (KMAX) sr.load_rows(T.lcol + ic, n, T.rows);
       });
   __syncthreads();
-  if (i >= n) return;
+  if (i >= hi) return;
   const double2 xi = s_xy[threadIdx.x];
   const F4 q0 = rd_q(threadIdx.x);
   double qmax[4], qmin[4], sxq[4], syq[4];
@@ -322,8 +328,8 @@ __global__ void __launch_bounds__(BLK) k_deriv_inner_t(Geo G, Tiles T,
   extern __shared__ __align__(64) unsigned char smem[];
   const int n = G.n;
   const int tile = block_id(G.xcd);
-  const int lo = tile * BLK;
-  if (lo >= n) return;
+  if (tile >= T.ntiles) return;  // blocks past the last tile (the grid is a multiple of 8)
+  const int lo = T.tlo[tile], hi = T.tlo[tile + 1];
   const int cap = BLK + T.hmax;
   // 16-byte planes (coordinates, then the derivative record in four pairs)
   double2 *s_xy = reinterpret_cast<double2 *>(smem);
@@ -338,17 +344,23 @@ __global__ void __launch_bounds__(BLK) k_deriv_inner_t(Geo G, Tiles T,
     return g;
   };
   const int i = lo + threadIdx.x;
-  const int c = i < n ? G.cnt[i] : 0;
+  int c = 0;
   SlotRegs<KMAX ? KMAX : 1> sr;
-  if (KMAX && i < n) sr.load(T.lcol + i, n, c, threadIdx.x);
+  F8 d0{};  // the first-order solution, loaded with the table
   stage_tile<BLK, XyG>(
-      T, tile, lo, n, [&](int p) { return XyG{G.xy[p], ld8(dqp, p)}; },
+      T, tile, lo, hi, hi - lo, [&](int p) { return XyG{G.xy[p], ld8(dqp, p)}; },
       [&](int sl, const XyG &r) {
         s_xy[sl] = r.xy;
         for (int h = 0; h < 4; ++h) s_g[h * cap + sl] = make_double2(r.g.v[2 * h], r.g.v[2 * h + 1]);
+      },
+      [&] {
+        const int ic = i < hi ? i : hi - 1;
+        c = G.cnt[ic];
+        if (KMAX) sr.load_rows(T.lcol + ic, n, T.rows);
+        d0 = ld8(dq0, ic);
       });
   __syncthreads();
-  if (i >= n) return;
+  if (i >= hi) return;
   const double2 xi = s_xy[threadIdx.x];
   const F8 g0 = rd_g(threadIdx.x);
   double ax[4] = {0, 0, 0, 0}, ay[4] = {0, 0, 0, 0};
@@ -382,7 +394,6 @@ __global__ void __launch_bounds__(BLK) k_deriv_inner_t(Geo G, Tiles T,
     }
   }
   const double det = sxx * syy - sxy * sxy;
-  const F8 d0 = ld8(dq0, i);
   F8 g;
   for (int m = 0; m < 4; ++m) {
     g.v[m] = d0.v[m] + 0.5 * g0.v[m] - 0.5 * ((syy * ax[m] - sxy * ay[m]) / det);
@@ -435,17 +446,16 @@ __global__ void __launch_bounds__(BLK) k_local_dt_t(Geo G, Flow P, Tiles T,
   extern __shared__ __align__(64) unsigned char smem[];
   const int n = G.n;
   const int tile = block_id(G.xcd);
-  const int lo = tile * BLK;
-  if (lo >= n) return;
+  if (tile >= T.ntiles) return;  // blocks past the last tile (the grid is a multiple of 8)
+  const int lo = T.tlo[tile], hi = T.tlo[tile + 1];
   const int cap = BLK + T.hmax;
   double2 *s_xy = reinterpret_cast<double2 *>(smem);
   double *s_w = reinterpret_cast<double *>(smem + 16 * (size_t)cap);
   const int i = lo + threadIdx.x;
-  const int c = i < n ? G.cnt[i] : 0;
+  int c = 0;
   SlotRegs<KMAX ? KMAX : 1> sr;
-  if (KMAX && i < n) sr.load(T.lcol + i, n, c, threadIdx.x);
   stage_tile<BLK, XyW>(
-      T, tile, lo, n,
+      T, tile, lo, hi, hi - lo,
       [&](int p) {
         double rho, u, v, pr;
         prim_from_cons(P.gamma, ld4(U, p), rho, u, v, pr);
@@ -455,9 +465,14 @@ __global__ void __launch_bounds__(BLK) k_local_dt_t(Geo G, Flow P, Tiles T,
       [&](int sl, const XyW &r) {
         s_xy[sl] = r.xy;
         s_w[sl] = r.w;
+      },
+      [&] {
+        const int ic = i < hi ? i : hi - 1;
+        c = G.cnt[ic];
+        if (KMAX) sr.load_rows(T.lcol + ic, n, T.rows);
       });
   __syncthreads();
-  if (i >= n) return;
+  if (i >= hi) return;
   const double2 xi = s_xy[threadIdx.x];
   double best = INFINITY;
   auto edge = [&](int sl) {
@@ -493,11 +508,11 @@ namespace lskum_impl {
 int deriv_first_launch(lskum_plan_s *p, const double *q, double *dq, double *qlim,
                        int8_t *argext, void *stream) {
   const Geo g = geo(p);
-  const int gr = grid_for(p->n, p->block);
   hipStream_t st = S(stream);
   const TileMap &m = p->maps[tile_index(p->block)];
   const size_t lds = (size_t)(p->block + m.hmax) * 48;
   if (m.blk == p->block && lds <= kTileLdsBytes) {
+    const int gr = grid_tiles(m.ntiles);
     const Tiles t = tiles(m);
     const bool k32 = p->k_pad <= 32;
 #define ARGS_ q, dq, qlim, argext
@@ -518,18 +533,19 @@ int deriv_first_launch(lskum_plan_s *p, const double *q, double *dq, double *qli
 #undef ARGS_
     return launched();
   }
+  const int gd = grid_for(p->n, p->block);
   switch (p->block) {
     case 128:
-      if (argext) k_deriv_first<128, true><<<gr, 128, 0, st>>>(g, q, dq, qlim, argext);
-      else k_deriv_first<128, false><<<gr, 128, 0, st>>>(g, q, dq, qlim, nullptr);
+      if (argext) k_deriv_first<128, true><<<gd, 128, 0, st>>>(g, q, dq, qlim, argext);
+      else k_deriv_first<128, false><<<gd, 128, 0, st>>>(g, q, dq, qlim, nullptr);
       break;
     case 512:
-      if (argext) k_deriv_first<512, true><<<gr, 512, 0, st>>>(g, q, dq, qlim, argext);
-      else k_deriv_first<512, false><<<gr, 512, 0, st>>>(g, q, dq, qlim, nullptr);
+      if (argext) k_deriv_first<512, true><<<gd, 512, 0, st>>>(g, q, dq, qlim, argext);
+      else k_deriv_first<512, false><<<gd, 512, 0, st>>>(g, q, dq, qlim, nullptr);
       break;
     default:
-      if (argext) k_deriv_first<256, true><<<gr, 256, 0, st>>>(g, q, dq, qlim, argext);
-      else k_deriv_first<256, false><<<gr, 256, 0, st>>>(g, q, dq, qlim, nullptr);
+      if (argext) k_deriv_first<256, true><<<gd, 256, 0, st>>>(g, q, dq, qlim, argext);
+      else k_deriv_first<256, false><<<gd, 256, 0, st>>>(g, q, dq, qlim, nullptr);
       break;
   }
   return launched();
@@ -540,7 +556,7 @@ int deriv_inner_launch(lskum_plan_s *p, const double *dq0, const double *dqp, do
   const TileMap &m = p->maps[tile_index(p->block)];
   const size_t lds = (size_t)(p->block + m.hmax) * 80;
   if (m.blk == p->block && lds <= kTileLdsBytes) {
-    const int gr = grid_for(p->n, p->block);
+    const int gr = grid_tiles(m.ntiles);
     const Tiles t = tiles(m);
     const Geo g = geo(p);
     hipStream_t st = S(stream);
@@ -565,7 +581,7 @@ int local_dt_launch(lskum_plan_s *p, const double *U, double *dt, void *stream) 
   const Flow f = flow(p);
   hipStream_t st = S(stream);
   if (m.blk == p->block && lds <= kTileLdsBytes) {
-    const int gr = grid_for(p->n, p->block);
+    const int gr = grid_tiles(m.ntiles);
     const Tiles t = tiles(m);
     const bool k32 = p->k_pad <= 32;
 #define LSKUM_DT_T(blk)                                                                  \

@@ -376,14 +376,18 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
 constexpr int kSlotShift = 25;
 constexpr int32_t kPointMask = (1 << kSlotShift) - 1;
 
-// LDS tables of one tile size: block b stages the BLK points of its tile
-// and their out-of-tile neighbours (the tile's halo) in LDS, and its rows
-// are stored as slots of that table, so the gather loop reads LDS only.
+// LDS tables of one tile size: block b stages the points of its tile (at
+// most BLK consecutive points) and their out-of-tile neighbours (the tile's
+// halo) in LDS, and its rows are stored as slots of that table, so the
+// gather loop reads LDS only.
 struct TileMap {
-  int blk = 0;                // tile size; 0 = not built
-  int hmax = 0;               // largest halo, rounded up to a multiple of 4
+  int blk = 0;                // largest tile (the block size); 0 = not built
+  int hmax = 0;               // table slots past blk, rounded up to a multiple of 4
+  int rows = 0;               // rows of lcol (the plan's k_pad)
+  int ntiles = 0;
+  int32_t *tlo = nullptr;     // [ntiles + 1] tile t holds points tlo[t] .. tlo[t+1]-1
   uint16_t *lcol = nullptr;   // [k_pad][n] table slot of every row entry (pads: own slot)
-  int32_t *hoff = nullptr;    // [n_tiles + 1] halo of tile t is hids[hoff[t] .. hoff[t+1])
+  int32_t *hoff = nullptr;    // [ntiles + 1] halo of tile t is hids[hoff[t] .. hoff[t+1])
   int32_t *hids = nullptr;    // halo point ids, ascending within a tile
 };
 
@@ -405,6 +409,9 @@ struct Tiles {
   const int32_t *hoff;
   const int32_t *hids;
   int hmax;
+  int rows;            // rows of lcol
+  const int32_t *tlo;  // tile bounds (tables of capped tiles)
+  int ntiles;
 };
 
 }  // namespace lskum_impl
@@ -533,31 +540,54 @@ struct SlotRegs {
       s[k] = k < c ? sl : own;
     }
   }
+  // The same from a table of `rows` rows, with no load waiting for the
+  // count: entries past it are loaded but never read.
+  __device__ __forceinline__ void load_rows(const E *col, int n, int rows) {
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) s[k] = col[(size_t)(k < rows ? k : rows - 1) * n];
+  }
 };
 
-// Stage the records of tile `tile` (its BLK points, then its halo) into LDS
+// Stage the records of tile `tile` (its points, then its halo) into LDS
 // slots: every thread issues all of its loads before it stores any.  get(p)
-// loads point p's records, put(slot, rec) stores them.
+// loads point p's records, put(slot, rec) stores them; the tile's points are
+// lo .. n-1 (at most BLK) and its halo takes slots hb + k.  The halo ids head
+// the longest chain of dependent loads (ids, then records, then the
+// barrier), so they are issued first, and pre() then issues the caller's
+// loads that depend on nothing staged, in their shadow.  No load sits in a
+// divergent branch, so each wait covers only the loads it needs: indices
+// are clamped (threads past n load point n-1; the halo list ends with a
+// spare entry) and only the stores are conditional.
+template <int BLK, class Rec, class Get, class Put, class Pre>
+__device__ __forceinline__ void stage_tile(const Tiles &T, int tile, int lo, int n, int hb,
+                                           Get get, Put put, Pre pre) {
+  const int h0 = T.hoff[tile];
+  const int nh = T.hoff[tile + 1] - h0;
+  const int last = nh > 0 ? nh - 1 : 0;
+  const int own = lo + threadIdx.x;
+  const int t0 = threadIdx.x;
+  int p0 = T.hids[h0 + min(t0, last)];
+  int p1 = T.hids[h0 + min(t0 + BLK, last)];
+  pre();
+  const Rec r0 = get(own < n ? own : n - 1);
+  // keeps the scheduler from moving work that needs the halo ids (and so
+  // waits for them) above the loads issued in their shadow
+  __builtin_amdgcn_sched_barrier(0);
+  for (int b = 0;; b += 2 * BLK) {
+    const int a0 = b + t0, a1 = a0 + BLK;
+    const Rec r1 = get(p0), r2 = get(p1);
+    if (b == 0 && own < n) put(t0, r0);
+    if (a0 < nh) put(hb + a0, r1);
+    if (a1 < nh) put(hb + a1, r2);
+    if (b + 2 * BLK >= nh) break;
+    p0 = T.hids[h0 + min(a0 + 2 * BLK, last)];
+    p1 = T.hids[h0 + min(a1 + 2 * BLK, last)];
+  }
+}
 template <int BLK, class Rec, class Get, class Put>
 __device__ __forceinline__ void stage_tile(const Tiles &T, int tile, int lo, int n, Get get,
                                            Put put) {
-  const int h0 = T.hoff[tile];
-  const int nh = T.hoff[tile + 1] - h0;
-  const int own = lo + threadIdx.x;
-  Rec r0{};
-  if (own < n) r0 = get(own);
-  for (int b = 0; b < nh; b += 2 * BLK) {
-    const int a0 = b + threadIdx.x, a1 = a0 + BLK;
-    const int p0 = a0 < nh ? T.hids[h0 + a0] : -1;
-    const int p1 = a1 < nh ? T.hids[h0 + a1] : -1;
-    Rec r1{}, r2{};
-    if (p0 >= 0) r1 = get(p0);
-    if (p1 >= 0) r2 = get(p1);
-    if (b == 0 && own < n) put(threadIdx.x, r0);
-    if (p0 >= 0) put(BLK + a0, r1);
-    if (p1 >= 0) put(BLK + a1, r2);
-  }
-  if (nh == 0 && own < n) put(threadIdx.x, r0);
+  stage_tile<BLK, Rec>(T, tile, lo, n, n - lo < BLK ? n - lo : BLK, get, put, [] {});
 }
 
 struct XyQ {
@@ -570,20 +600,28 @@ struct XyG {
 };
 
 // tile maps: index of a tile size in lskum_plan_s::maps, kernel view, and
-// the LDS budget of one block's table (two blocks per CU)
+// the largest table a block may stage (half of a CU's LDS)
 inline int tile_index(int blk) { return blk == 128 ? 0 : (blk == 512 ? 2 : 1); }
-inline Tiles tiles(const TileMap &m) { return Tiles{m.lcol, m.hoff, m.hids, m.hmax}; }
+inline Tiles tiles(const TileMap &m) {
+  return Tiles{m.lcol, m.hoff, m.hids, m.hmax, m.rows, m.tlo, m.ntiles};
+}
+// grid of one block per tile, a multiple of the XCD count
+inline int grid_tiles(int ntiles) { return (ntiles + kXcds - 1) / kXcds * kXcds; }
 constexpr size_t kTileLdsBytes = 80 * 1024;
 // builds the tile map of the plan's current tile size if missing (synchronous)
 int ensure_tile_map(lskum_plan_s *p);
 // LDS slots of rows of point ids (column-major [width][n]; row i's entries
-// past cnt[i] stand for i itself) on tiles of blk consecutive points: a
-// tile's own points take slots 0..blk-1, the out-of-tile points its rows
-// name (its halo, ascending in hids[hoff[t] .. hoff[t+1])) slots blk + k.
-// LSKUM_ERR_INVALID_ARG when a tile needs more than 65535 slots.
-int tile_slots(int32_t n, int32_t width, int blk, const int32_t *ids, const int32_t *cnt,
-               std::vector<int32_t> &slots, std::vector<int32_t> &hoff,
-               std::vector<int32_t> &hids, int &hmax);
+// past cnt[i] stand for i itself) on tiles of consecutive points: a tile's
+// own points take slots 0..size-1 and the out-of-tile points its rows name
+// (its halo, ascending in hids[hoff[t] .. hoff[t+1])) slots size + k.
+// cap = 0: tiles of blk points (the last one shorter); cap > 0: a tile
+// takes blk points, fewer (in steps of 8) while its points and halo exceed
+// cap slots.  tlo gets the tile bounds, hmax the table slots past blk;
+// hids ends with a spare entry.  LSKUM_ERR_INVALID_ARG when a tile needs
+// more than 65535 slots.
+int tile_slots(int32_t n, int32_t width, int blk, int cap, const int32_t *ids,
+               const int32_t *cnt, std::vector<int32_t> &slots, std::vector<int32_t> &tlo,
+               std::vector<int32_t> &hoff, std::vector<int32_t> &hids, int &hmax);
 
 // launchers of the forward kernels (lskum.hip, lskum_deriv.hip, lskum_flux.hip),
 // reused by the adjoint
