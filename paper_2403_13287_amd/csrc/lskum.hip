@@ -354,8 +354,15 @@ int build_tile_map(lskum_plan_s *p, int blk, const int32_t *nbr, const int32_t *
   if (!rc && (int64_t)tlo.size() - 1 > fixed_tiles + fixed_tiles / 8 + 8)
     rc = tile_slots(p->n, p->k_pad, blk, 0, nbr, cnt, slots, tlo, hoff, hids, hmax);
   if (rc) return rc;
+  // slots grouped by 8 entries of a row: [groups][n][8], 16 bytes per point
+  // and group (entries past k_pad: slot 0, never read)
+  const int groups = (p->k_pad + 7) / 8;
+  const size_t n = (size_t)p->n;
   try {
-    lcol.assign(slots.begin(), slots.end());
+    lcol.assign((size_t)groups * n * 8, 0);
+    for (int32_t s = 0; s < p->k_pad; ++s)
+      for (size_t i = 0; i < n; ++i)
+        lcol[((size_t)(s >> 3) * n + i) * 8 + (s & 7)] = (uint16_t)slots[s * n + i];
   } catch (const std::bad_alloc &) {
     return LSKUM_ERR_NO_MEMORY;
   }
@@ -365,7 +372,7 @@ int build_tile_map(lskum_plan_s *p, int blk, const int32_t *nbr, const int32_t *
       (rc = upload(&m.hids, hids.data(), hids.size())))
     return rc;
   m.hmax = (hmax + 3) / 4 * 4;
-  m.rows = p->k_pad;
+  m.groups = groups;
   m.ntiles = (int)tlo.size() - 1;
   m.blk = blk;
   return LSKUM_OK;

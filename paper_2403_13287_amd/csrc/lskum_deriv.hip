@@ -202,11 +202,11 @@ __global__ void __launch_bounds__(BLK) k_deriv_inner(Geo G, const double *__rest
 // Reader of point i's row of table slots; entries past the count return
 // the point's own slot (prefetching ahead never leaves the row).
 struct SlotRow {
-  const uint16_t *col;  // &lcol[i], stride n
-  int n, c, own;
+  const uint16_t *lcol;  // [groups][n][8]
+  int n, i, c, own;
   __device__ __forceinline__ int operator()(int k) const {
     const int kk = k < c ? k : c - 1;
-    const int sl = col[(size_t)kk * n];
+    const int sl = lcol[((size_t)(kk >> 3) * n + i) * 8 + (kk & 7)];
     return k < c ? sl : own;
   }
 };
@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(BLK) k_deriv_first_t(Geo G, Tiles T,
   };
   const int i = lo + threadIdx.x;
   int c = 0;
-  SlotRegs<KMAX ? KMAX : 1> sr;
+  SlotGroups<KMAX ? KMAX : 8> sr;
   stage_tile<BLK, XyQ>(
       T, tile, lo, hi, hi - lo, [&](int p) { return XyQ{G.xy[p], ld4(q, p)}; },
       [&](int sl, const XyQ &r) {
@@ -245,7 +245,7 @@ __global__ void __launch_bounds__(BLK) k_deriv_first_t(Geo G, Tiles T,
       [&] {
         const int ic = i < hi ? i : hi - 1;
         c = G.cnt[ic];
-        if (KMAX) sr.load_rows(T.lcol + ic, n, T.rows);
+        if (KMAX) sr.load(T.lcol, n, ic, T.groups);
       });
   __syncthreads();
   if (i >= hi) return;
@@ -288,9 +288,9 @@ __global__ void __launch_bounds__(BLK) k_deriv_first_t(Geo G, Tiles T,
   if (KMAX) {
 #pragma unroll
     for (int k = 0; k < (KMAX ? KMAX : 1); ++k)
-      if (k < c) edge(k, sr.s[k]);
+      if (k < c) edge(k, sr[k]);
   } else {
-    const SlotRow row{T.lcol + i, n, c, (int)threadIdx.x};
+    const SlotRow row{T.lcol, n, i, c, (int)threadIdx.x};
     int s_next = row(1);
     int s_cur = row(0);
     for (int k = 0; k < c; ++k) {
@@ -345,7 +345,7 @@ __global__ void __launch_bounds__(BLK) k_deriv_inner_t(Geo G, Tiles T,
   };
   const int i = lo + threadIdx.x;
   int c = 0;
-  SlotRegs<KMAX ? KMAX : 1> sr;
+  SlotGroups<KMAX ? KMAX : 8> sr;
   F8 d0{};  // the first-order solution, loaded with the table
   stage_tile<BLK, XyG>(
       T, tile, lo, hi, hi - lo, [&](int p) { return XyG{G.xy[p], ld8(dqp, p)}; },
@@ -356,7 +356,7 @@ __global__ void __launch_bounds__(BLK) k_deriv_inner_t(Geo G, Tiles T,
       [&] {
         const int ic = i < hi ? i : hi - 1;
         c = G.cnt[ic];
-        if (KMAX) sr.load_rows(T.lcol + ic, n, T.rows);
+        if (KMAX) sr.load(T.lcol, n, ic, T.groups);
         d0 = ld8(dq0, ic);
       });
   __syncthreads();
@@ -381,9 +381,9 @@ __global__ void __launch_bounds__(BLK) k_deriv_inner_t(Geo G, Tiles T,
   if (KMAX) {
 #pragma unroll
     for (int k = 0; k < (KMAX ? KMAX : 1); ++k)
-      if (k < c) edge(sr.s[k]);
+      if (k < c) edge(sr[k]);
   } else {
-    const SlotRow row{T.lcol + i, n, c, (int)threadIdx.x};
+    const SlotRow row{T.lcol, n, i, c, (int)threadIdx.x};
     int s_next = row(1);
     int s_cur = row(0);
     for (int k = 0; k < c; ++k) {
@@ -453,7 +453,7 @@ __global__ void __launch_bounds__(BLK) k_local_dt_t(Geo G, Flow P, Tiles T,
   double *s_w = reinterpret_cast<double *>(smem + 16 * (size_t)cap);
   const int i = lo + threadIdx.x;
   int c = 0;
-  SlotRegs<KMAX ? KMAX : 1> sr;
+  SlotGroups<KMAX ? KMAX : 8> sr;
   stage_tile<BLK, XyW>(
       T, tile, lo, hi, hi - lo,
       [&](int p) {
@@ -469,7 +469,7 @@ __global__ void __launch_bounds__(BLK) k_local_dt_t(Geo G, Flow P, Tiles T,
       [&] {
         const int ic = i < hi ? i : hi - 1;
         c = G.cnt[ic];
-        if (KMAX) sr.load_rows(T.lcol + ic, n, T.rows);
+        if (KMAX) sr.load(T.lcol, n, ic, T.groups);
       });
   __syncthreads();
   if (i >= hi) return;
@@ -483,9 +483,9 @@ __global__ void __launch_bounds__(BLK) k_local_dt_t(Geo G, Flow P, Tiles T,
   if (KMAX) {
 #pragma unroll
     for (int k = 0; k < (KMAX ? KMAX : 1); ++k)
-      if (k < c) edge(sr.s[k]);
+      if (k < c) edge(sr[k]);
   } else {
-    const SlotRow row{T.lcol + i, n, c, (int)threadIdx.x};
+    const SlotRow row{T.lcol, n, i, c, (int)threadIdx.x};
     for (int k = 0; k < c; ++k) edge(row(k));
   }
   dt[i] = P.cfl * sqrt(best);

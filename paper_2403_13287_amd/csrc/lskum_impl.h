@@ -383,10 +383,10 @@ constexpr int32_t kPointMask = (1 << kSlotShift) - 1;
 struct TileMap {
   int blk = 0;                // largest tile (the block size); 0 = not built
   int hmax = 0;               // table slots past blk, rounded up to a multiple of 4
-  int rows = 0;               // rows of lcol (the plan's k_pad)
+  int groups = 0;             // groups of 8 row entries: k_pad rounded up to 8, over 8
   int ntiles = 0;
   int32_t *tlo = nullptr;     // [ntiles + 1] tile t holds points tlo[t] .. tlo[t+1]-1
-  uint16_t *lcol = nullptr;   // [k_pad][n] table slot of every row entry (pads: own slot)
+  uint16_t *lcol = nullptr;   // [groups][n][8] table slot of every row entry (pads: own slot)
   int32_t *hoff = nullptr;    // [ntiles + 1] halo of tile t is hids[hoff[t] .. hoff[t+1])
   int32_t *hids = nullptr;    // halo point ids, ascending within a tile
 };
@@ -409,7 +409,7 @@ struct Tiles {
   const int32_t *hoff;
   const int32_t *hids;
   int hmax;
-  int rows;            // rows of lcol
+  int groups;          // 8-entry groups of lcol
   const int32_t *tlo;  // tile bounds (tables of capped tiles)
   int ntiles;
 };
@@ -540,11 +540,29 @@ struct SlotRegs {
       s[k] = k < c ? sl : own;
     }
   }
-  // The same from a table of `rows` rows, with no load waiting for the
-  // count: entries past it are loaded but never read.
-  __device__ __forceinline__ void load_rows(const E *col, int n, int rows) {
+};
+
+// Point i's whole row of table slots in registers, from a table laid out
+// as [groups][n][8] (16 bytes per point and group: one load per 8 entries),
+// two slots to a register; no load waits for the row's count (entries past
+// it are loaded but never read).  Rows of at most KMAX entries.
+template <int KMAX>
+struct SlotGroups {
+  static_assert(KMAX % 8 == 0, "whole groups");
+  uint32_t w[KMAX / 2];
+  __device__ __forceinline__ void load(const uint16_t *lcol, int n, int i, int groups) {
+    const uint4 *g4 = reinterpret_cast<const uint4 *>(lcol);
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) s[k] = col[(size_t)(k < rows ? k : rows - 1) * n];
+    for (int g = 0; g < KMAX / 8; ++g) {
+      const uint4 v = g4[(size_t)(g < groups ? g : groups - 1) * n + i];
+      w[4 * g] = v.x;
+      w[4 * g + 1] = v.y;
+      w[4 * g + 2] = v.z;
+      w[4 * g + 3] = v.w;
+    }
+  }
+  __device__ __forceinline__ int operator[](int k) const {
+    return (int)((w[k >> 1] >> (16 * (k & 1))) & 0xffffu);
   }
 };
 
@@ -603,7 +621,7 @@ struct XyG {
 // the largest table a block may stage (half of a CU's LDS)
 inline int tile_index(int blk) { return blk == 128 ? 0 : (blk == 512 ? 2 : 1); }
 inline Tiles tiles(const TileMap &m) {
-  return Tiles{m.lcol, m.hoff, m.hids, m.hmax, m.rows, m.tlo, m.ntiles};
+  return Tiles{m.lcol, m.hoff, m.hids, m.hmax, m.groups, m.tlo, m.ntiles};
 }
 // grid of one block per tile, a multiple of the XCD count
 inline int grid_tiles(int ntiles) { return (ntiles + kXcds - 1) / kXcds * kXcds; }
