@@ -452,6 +452,11 @@ void release(lskum_plan_s *p) {
     (void)hipFree(m.hoff);
     (void)hipFree(m.hids);
   }
+  // the adjoint's in-edge tile tables (built by the first VJP call)
+  (void)hipFree(p->in_map.tlo);
+  (void)hipFree(p->in_map.lent);
+  (void)hipFree(p->in_map.hoff);
+  (void)hipFree(p->in_map.hids);
   (void)hipSetDevice(cur);
   delete p;
 }

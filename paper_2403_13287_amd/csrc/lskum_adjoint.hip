@@ -666,7 +666,7 @@ struct XySA {  // plain members: a 64-byte aligned F8 member kept this record on
 
 template <int BLK, int KMAX>
 __global__ void __launch_bounds__(BLK) k_inner_rev_t(Geo G, Tiles T,
-                                                        const uint32_t *__restrict__ lent,
+                                                        const uint32_t *__restrict__ lent, int rows,
                                                         const int32_t *__restrict__ in_cnt,
                                                         const double *__restrict__ lsg,
                                                         const double *__restrict__ s_in,
@@ -675,8 +675,8 @@ __global__ void __launch_bounds__(BLK) k_inner_rev_t(Geo G, Tiles T,
   extern __shared__ __align__(64) unsigned char smem[];
   const int n = G.n;
   const int tile = block_id(G.xcd);
-  const int lo = tile * BLK;
-  if (lo >= n) return;
+  if (tile >= T.ntiles) return;  // blocks past the last tile (the grid is a multiple of 8)
+  const int lo = T.tlo[tile], hi = T.tlo[tile + 1];
   const int cap = BLK + T.hmax;
   double2 *s_xy = reinterpret_cast<double2 *>(smem);
   double2 *s_s = s_xy + cap;  // 4 planes
@@ -690,17 +690,21 @@ __global__ void __launch_bounds__(BLK) k_inner_rev_t(Geo G, Tiles T,
     return r;
   };
   const int j = lo + threadIdx.x;
-  const int c = j < n ? in_cnt[j] : 0;
+  int c = 0;
   SlotRegs<KMAX ? KMAX : 1, uint32_t> sr;
-  if (KMAX && j < n) sr.load(lent + j, n, c, threadIdx.x);
   stage_tile<BLK, XyS>(
-      T, tile, lo, n, [&](int p) { return XyS{G.xy[p], ld8(s_in, p)}; },
+      T, tile, lo, hi, hi - lo, [&](int p) { return XyS{G.xy[p], ld8(s_in, p)}; },
       [&](int sl, const XyS &r) {
         s_xy[sl] = r.xy;
         for (int h = 0; h < 4; ++h) s_s[h * cap + sl] = make_double2(r.s.v[2 * h], r.s.v[2 * h + 1]);
+      },
+      [&] {
+        const int jc = j < hi ? j : hi - 1;
+        c = in_cnt[jc];
+        if (KMAX) sr.load_rows(lent + jc, n, rows);
       });
   __syncthreads();
-  if (j >= n) return;
+  if (j >= hi) return;
   const double2 xj = s_xy[threadIdx.x];
   const F8 sj = rd_s(threadIdx.x);
   double aq[4] = {0, 0, 0, 0}, ax[4] = {0, 0, 0, 0}, ay[4] = {0, 0, 0, 0};
@@ -728,7 +732,7 @@ __global__ void __launch_bounds__(BLK) k_inner_rev_t(Geo G, Tiles T,
 
 template <int BLK, int KMAX>
 __global__ void __launch_bounds__(BLK) k_first_rev_t(Geo G, Flow P, Tiles T,
-                                                        const uint32_t *__restrict__ lent,
+                                                        const uint32_t *__restrict__ lent, int rows,
                                                         const int32_t *__restrict__ in_cnt,
                                                         const double *__restrict__ lsg,
                                                         const double *__restrict__ s0,
@@ -741,8 +745,8 @@ __global__ void __launch_bounds__(BLK) k_first_rev_t(Geo G, Flow P, Tiles T,
   const uint64_t *arg = reinterpret_cast<const uint64_t *>(argext);
   const int n = G.n;
   const int tile = block_id(G.xcd);
-  const int lo = tile * BLK;
-  if (lo >= n) return;
+  if (tile >= T.ntiles) return;  // blocks past the last tile (the grid is a multiple of 8)
+  const int lo = T.tlo[tile], hi = T.tlo[tile + 1];
   const int cap = BLK + T.hmax;
   double2 *s_xy = reinterpret_cast<double2 *>(smem);
   double2 *s_s = s_xy + cap;                                // 4 planes
@@ -757,11 +761,10 @@ __global__ void __launch_bounds__(BLK) k_first_rev_t(Geo G, Flow P, Tiles T,
     return r;
   };
   const int j = lo + threadIdx.x;
-  const int c = j < n ? in_cnt[j] : 0;
+  int c = 0;
   SlotRegs<KMAX ? KMAX : 1, uint32_t> sr;
-  if (KMAX && j < n) sr.load(lent + j, n, c, threadIdx.x);
   stage_tile<BLK, XySA>(
-      T, tile, lo, n,
+      T, tile, lo, hi, hi - lo,
       [&](int p) {
         const F8 s = ld8(s0, p);
         return XySA{G.xy[p], {s.v[0], s.v[1], s.v[2], s.v[3], s.v[4], s.v[5], s.v[6], s.v[7]},
@@ -771,9 +774,14 @@ __global__ void __launch_bounds__(BLK) k_first_rev_t(Geo G, Flow P, Tiles T,
         s_xy[sl] = r.xy;
         for (int h = 0; h < 4; ++h) s_s[h * cap + sl] = make_double2(r.s[2 * h], r.s[2 * h + 1]);
         s_a[sl] = r.a;
+      },
+      [&] {
+        const int jc = j < hi ? j : hi - 1;
+        c = in_cnt[jc];
+        if (KMAX) sr.load_rows(lent + jc, n, rows);
       });
   __syncthreads();
-  if (j >= n) return;
+  if (j >= hi) return;
   const double2 xj = s_xy[threadIdx.x];
   const F8 sj = rd_s(threadIdx.x);
   const uint64_t aj = s_a[threadIdx.x];
@@ -788,7 +796,7 @@ __global__ void __launch_bounds__(BLK) k_first_rev_t(Geo G, Flow P, Tiles T,
     }
   }
   const int h0 = T.hoff[tile];
-  const int hb = n - lo < BLK ? n - lo : BLK;  // the tile's points; its halo slots follow
+  const int hb = hi - lo;  // the tile's points; its halo slots follow
   auto edge = [&](uint32_t ent) {
     const int sl = (int)(ent & 0xffffu);
     const int slot = (int)(ent >> 16);
@@ -1080,7 +1088,7 @@ int adjoint_prepare(lskum_plan_s *p, void *stream) {
 // free whatever a failed preparation left
 void adjoint_reset(lskum_plan_s *p) {
   void *bufs[] = {p->in_cnt, p->in_ent, p->lsg, p->outer, p->ooff,
-                  p->in_map.lent, p->in_map.hoff, p->in_map.hids};
+                  p->in_map.tlo, p->in_map.lent, p->in_map.hoff, p->in_map.hids};
   for (void *b : bufs) (void)hipFree(b);
   p->in_cnt = p->in_ent = p->outer = p->ooff = nullptr;
   p->lsg = nullptr;
@@ -1095,6 +1103,7 @@ int ensure_in_tiles(lskum_plan_s *p, void *stream) {
   if (m.blk == p->block) return LSKUM_OK;
   // earlier VJP calls on this stream may still read the old tables
   if (hipStreamSynchronize(S(stream)) != hipSuccess) return LSKUM_ERR_HIP;
+  (void)hipFree(m.tlo);
   (void)hipFree(m.lent);
   (void)hipFree(m.hoff);
   (void)hipFree(m.hids);
@@ -1111,9 +1120,14 @@ int ensure_in_tiles(lskum_plan_s *p, void *stream) {
   } catch (const std::bad_alloc &) {
     return LSKUM_ERR_NO_MEMORY;
   }
-  if ((rc = tile_slots(n, ki, p->block, 0, ids.data(), cnt.data(), slots, tlo, hoff, hids,
-                       hmax)))
-    return rc;
+  // tiles capped at 2 blk table slots as for the forward passes' tables,
+  // fixed tiles where capping would shrink them a lot
+  rc = tile_slots(n, ki, p->block, 2 * p->block, ids.data(), cnt.data(), slots, tlo, hoff, hids,
+                  hmax);
+  const int64_t fixed_tiles = ((int64_t)n + p->block - 1) / p->block;
+  if (!rc && (int64_t)tlo.size() - 1 > fixed_tiles + fixed_tiles / 8 + 8)
+    rc = tile_slots(n, ki, p->block, 0, ids.data(), cnt.data(), slots, tlo, hoff, hids, hmax);
+  if (rc) return rc;
   try {
     lent.resize(slots.size());
     for (int32_t e = 0; e < ki; ++e)
@@ -1126,10 +1140,12 @@ int ensure_in_tiles(lskum_plan_s *p, void *stream) {
     return LSKUM_ERR_NO_MEMORY;
   }
   if ((rc = upload(&m.lent, lent.data(), lent.size())) ||
+      (rc = upload(&m.tlo, tlo.data(), tlo.size())) ||
       (rc = upload(&m.hoff, hoff.data(), hoff.size())) ||
       (rc = upload(&m.hids, hids.data(), hids.size())))
     return rc;
   m.hmax = (hmax + 3) / 4 * 4;
+  m.ntiles = (int)tlo.size() - 1;
   m.blk = p->block;
   return LSKUM_OK;
 }
@@ -1198,11 +1214,11 @@ int reverse_passes(lskum_plan_s *p, const VjpWs &w, const double *U, const doubl
   // the derivative reverses on the in-edge tile tables when a block's
   // table fits the LDS budget
   const InTileMap &m = p->in_map;
-  const Tiles t{nullptr, m.hoff, m.hids, m.hmax};
+  const Tiles t{nullptr, m.hoff, m.hids, m.hmax, 0, m.tlo, m.ntiles};
   const size_t cap = (size_t)p->block + m.hmax;
   const bool tiled = m.blk == p->block && cap * 88 <= kTileLdsBytes;
   const bool k48 = p->k_in <= 48;
-  const int gr = grid_for(p->n, p->block);
+  const int gr = grid_tiles(m.ntiles);
   hipStream_t st = S(stream);
 #define LSKUM_REV_T(kern, lds, ...)                                                      \
   do {                                                                                   \
@@ -1224,7 +1240,8 @@ int reverse_passes(lskum_plan_s *p, const VjpWs &w, const double *U, const doubl
   double *cur = w.sa, *nxt = w.sb;
   for (int k = K; k >= 1; --k) {
     if (tiled)
-      LSKUM_REV_T(k_inner_rev_t, cap * 80, g, t, m.lent, p->in_cnt, p->lsg, cur, w.qbar, nxt);
+      LSKUM_REV_T(k_inner_rev_t, cap * 80, g, t, m.lent, p->k_in, p->in_cnt, p->lsg, cur,
+                  w.qbar, nxt);
     else
       LSKUM_TILED_ADJ(k_inner_rev, p, stream, g, p->in_cnt, p->in_ent, p->lsg, cur, w.qbar, nxt);
     double *tmp = cur;
@@ -1232,8 +1249,8 @@ int reverse_passes(lskum_plan_s *p, const VjpWs &w, const double *U, const doubl
     nxt = tmp;
   }
   if (tiled)
-    LSKUM_REV_T(k_first_rev_t, cap * 88, g, f, t, m.lent, p->in_cnt, p->lsg, cur, w.argext,
-                w.lbar, U, w.qbar, Ubar);
+    LSKUM_REV_T(k_first_rev_t, cap * 88, g, f, t, m.lent, p->k_in, p->in_cnt, p->lsg, cur,
+                w.argext, w.lbar, U, w.qbar, Ubar);
   else
     LSKUM_TILED_ADJ(k_first_rev, p, stream, g, f, p->in_cnt, p->in_ent, p->lsg, cur, w.argext,
                     w.lbar, U, w.qbar, Ubar);

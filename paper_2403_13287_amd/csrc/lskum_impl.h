@@ -398,6 +398,8 @@ struct TileMap {
 struct InTileMap {
   int blk = 0;
   int hmax = 0;
+  int ntiles = 0;
+  int32_t *tlo = nullptr;  // [ntiles + 1] tile bounds
   uint32_t *lent = nullptr;
   int32_t *hoff = nullptr;
   int32_t *hids = nullptr;
@@ -539,6 +541,12 @@ struct SlotRegs {
       const int sl = col[(size_t)(k < c ? k : 0) * n];
       s[k] = k < c ? sl : own;
     }
+  }
+  // The same from a table of `rows` rows, with no load waiting for the
+  // count: entries past it are loaded but never read.
+  __device__ __forceinline__ void load_rows(const E *col, int n, int rows) {
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) s[k] = col[(size_t)(k < rows ? k : rows - 1) * n];
   }
 };
 
