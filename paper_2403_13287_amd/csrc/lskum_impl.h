@@ -101,9 +101,10 @@ __device__ __forceinline__ void pl_wr8(double2 (*pl)[BLK], int sl, const F8 &v) 
 // ---------------------------------------------------------------------------
 // launch helpers
 
-// Blocks are dispatched to the 8 XCDs round-robin.  With xcd set, re-label
-// them so that XCD x processes one contiguous range of logical blocks.  The
-// grid is a multiple of 8; threads past n exit at once.
+// Blocks are dispatched to the 8 XCDs round-robin (the default mapping).
+// With xcd set, re-label them so that XCD x processes one contiguous range
+// of logical blocks.  The grid is a multiple of 8; threads past n exit at
+// once.
 __device__ __forceinline__ int block_id(int xcd) {
   if (!xcd) return blockIdx.x;
   const int per = gridDim.x / kXcds;
@@ -424,7 +425,7 @@ struct Tiles {
 struct lskum_plan_s {
   int device = 0;
   int32_t n = 0, k_pad = 0, n_clouds = 0, n_wall = 0, n_chunks = 0;
-  int block = 256, xcd = 1;
+  int block = 256, xcd = 0;
   int flux_block = 64;  // points per block of the flux kernel
   lskum_impl::TileMap maps[3];       // tile sizes 128, 256, 512 (built on demand)
   std::vector<lskum_params> params;  // one per cloud

@@ -167,7 +167,7 @@ class Tuning:
     XCD-contiguous block mapping, and the flux kernel's block size (64, 128,
     256); results do not depend on it."""
     block: int = 256
-    xcd_contiguous: int = 1
+    xcd_contiguous: int = 0
     flux_block: int = 64
 
     def c(self) -> _Tuning:
