@@ -99,10 +99,12 @@ typedef struct {
 #define LSKUM_RK4 4
 
 /* Launch tuning of a plan: the block size (= points per LDS tile of the
- * gather kernels), whether blocks are relabelled so that each of the 8
- * XCDs walks one contiguous range of points (its L2 then holds that range's
- * neighbours), and the flux kernel's block size (= points whose records it
- * stages in LDS).  Results do not depend on the tuning. */
+ * gather kernels), whether the blocks of the flux kernel and of the
+ * per-point kernels are relabelled so that each of the 8 XCDs walks one
+ * contiguous range of points (its L2 then holds that range's neighbours;
+ * the derivative passes and the local time step always do), and the flux
+ * kernel's block size (= points whose records it stages in LDS).  Results
+ * do not depend on the tuning. */
 typedef struct {
   int32_t block;          /* 128, 256 or 512 (0: 256)                         */
   int32_t xcd_contiguous; /* 0 (default): round-robin over the XCDs;     */

@@ -505,9 +505,19 @@ namespace lskum_impl {
     else kern<__VA_ARGS__, 0><<<gr, blk, lds, st>>>(g, t, ARGS_);                     \
   } while (0)
 
+// The derivative passes and the local time step walk XCD-contiguous ranges
+// whatever the plan's block mapping: a tile's halo then sits in the L2 of
+// the XCD that runs the tile.  The flux kernel, which gains more from an
+// even spread of the work over the XCDs, follows the plan's mapping.
+inline Geo gather_geo(const lskum_plan_s *p) {
+  Geo g = geo(p);
+  g.xcd = 1;
+  return g;
+}
+
 int deriv_first_launch(lskum_plan_s *p, const double *q, double *dq, double *qlim,
                        int8_t *argext, void *stream) {
-  const Geo g = geo(p);
+  const Geo g = gather_geo(p);
   hipStream_t st = S(stream);
   const TileMap &m = p->maps[tile_index(p->block)];
   const size_t lds = (size_t)(p->block + m.hmax) * 48;
@@ -558,7 +568,7 @@ int deriv_inner_launch(lskum_plan_s *p, const double *dq0, const double *dqp, do
   if (m.blk == p->block && lds <= kTileLdsBytes) {
     const int gr = grid_tiles(m.ntiles);
     const Tiles t = tiles(m);
-    const Geo g = geo(p);
+    const Geo g = gather_geo(p);
     hipStream_t st = S(stream);
     const bool k32 = p->k_pad <= 32;
 #define ARGS_ dq0, dqp, dqn
@@ -570,14 +580,14 @@ int deriv_inner_launch(lskum_plan_s *p, const double *dq0, const double *dqp, do
 #undef ARGS_
     return launched();
   }
-  LSKUM_TILED(k_deriv_inner, p, stream, geo(p), dq0, dqp, dqn);
+  LSKUM_TILED(k_deriv_inner, p, stream, gather_geo(p), dq0, dqp, dqn);
   return launched();
 }
 
 int local_dt_launch(lskum_plan_s *p, const double *U, double *dt, void *stream) {
   const TileMap &m = p->maps[tile_index(p->block)];
   const size_t lds = (size_t)(p->block + m.hmax) * 24;
-  const Geo g = geo(p);
+  const Geo g = gather_geo(p);
   const Flow f = flow(p);
   hipStream_t st = S(stream);
   if (m.blk == p->block && lds <= kTileLdsBytes) {

@@ -164,8 +164,9 @@ class Params:
 @dataclass(frozen=True)
 class Tuning:
     """Block size of the gather kernels (points per LDS tile: 128, 256, 512),
-    XCD-contiguous block mapping, and the flux kernel's block size (64, 128,
-    256); results do not depend on it."""
+    XCD-contiguous block mapping of the flux and per-point kernels (the
+    derivative passes and the local time step always use it), and the flux
+    kernel's block size (64, 128, 256); results do not depend on it."""
     block: int = 256
     xcd_contiguous: int = 0
     flux_block: int = 64
