@@ -24,8 +24,9 @@
  *     dt   [n]     local time step
  * - The caller owns every field buffer; the library never frees caller
  *   memory.  The plan owns the device copies of the geometry and the
- *   connectivity, allocated in lskum_plan_create and freed in
- *   lskum_plan_destroy.
+ *   connectivity and the tables built from them (allocated in
+ *   lskum_plan_create, on a tile-size change, or by the first VJP call) and
+ *   frees them all in lskum_plan_destroy.
  * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *   Sweep calls are asynchronous on that stream; they return LSKUM_OK once
  *   the work is enqueued, or a negative status for invalid arguments or a
