@@ -107,7 +107,7 @@ typedef struct {
  * kernel's block size (= points whose records it stages in LDS).  Results
  * do not depend on the tuning. */
 typedef struct {
-  int32_t block;          /* 128, 256 or 512 (0: 256)                         */
+  int32_t block;          /* 128, 256 or 512 (0: 512)                         */
   int32_t xcd_contiguous; /* 0 (default): round-robin over the XCDs;     */
                           /* 1: each XCD walks one contiguous range       */
   int32_t flux_block;     /* 64, 128 or 256 (0: 64)                           */

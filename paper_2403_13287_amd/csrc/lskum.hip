@@ -756,7 +756,7 @@ int lskum_batch_plan_create(lskum_plan *out, int32_t n_clouds, const lskum_cloud
   p->params.assign(params, params + n_clouds);
   p->offset = offset;
   if (tuning) {
-    p->block = tuning->block ? tuning->block : 256;
+    p->block = tuning->block ? tuning->block : 512;
     p->xcd = tuning->xcd_contiguous;
     p->flux_block = tuning->flux_block ? tuning->flux_block : 64;
   }
@@ -824,7 +824,7 @@ int lskum_plan_set_params(lskum_plan p, const lskum_params *params) {
 
 int lskum_plan_set_tuning(lskum_plan p, const lskum_tuning *tuning) {
   if (!p || !tuning || !tuning_ok(tuning)) return LSKUM_ERR_INVALID_ARG;
-  p->block = tuning->block ? tuning->block : 256;
+  p->block = tuning->block ? tuning->block : 512;
   p->xcd = tuning->xcd_contiguous;
   p->flux_block = tuning->flux_block ? tuning->flux_block : 64;
   return ensure_tile_map(p);

@@ -1120,10 +1120,11 @@ int ensure_in_tiles(lskum_plan_s *p, void *stream) {
   } catch (const std::bad_alloc &) {
     return LSKUM_ERR_NO_MEMORY;
   }
-  // tiles capped at 2 blk table slots as for the forward passes' tables,
+  // tiles capped at 2 blk table slots as for the forward passes' tables, and
+  // at what the first-order reverse's 88-byte slots fit in the LDS budget;
   // fixed tiles where capping would shrink them a lot
-  rc = tile_slots(n, ki, p->block, 2 * p->block, ids.data(), cnt.data(), slots, tlo, hoff, hids,
-                  hmax);
+  const int cap = std::min(2 * p->block, (int)(kTileLdsBytes / 88) / 4 * 4);
+  rc = tile_slots(n, ki, p->block, cap, ids.data(), cnt.data(), slots, tlo, hoff, hids, hmax);
   const int64_t fixed_tiles = ((int64_t)n + p->block - 1) / p->block;
   if (!rc && (int64_t)tlo.size() - 1 > fixed_tiles + fixed_tiles / 8 + 8)
     rc = tile_slots(n, ki, p->block, 0, ids.data(), cnt.data(), slots, tlo, hoff, hids, hmax);

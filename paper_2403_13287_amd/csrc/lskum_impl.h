@@ -425,7 +425,7 @@ struct Tiles {
 struct lskum_plan_s {
   int device = 0;
   int32_t n = 0, k_pad = 0, n_clouds = 0, n_wall = 0, n_chunks = 0;
-  int block = 256, xcd = 0;
+  int block = 512, xcd = 0;
   int flux_block = 64;  // points per block of the flux kernel
   lskum_impl::TileMap maps[3];       // tile sizes 128, 256, 512 (built on demand)
   std::vector<lskum_params> params;  // one per cloud

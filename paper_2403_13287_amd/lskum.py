@@ -167,7 +167,7 @@ class Tuning:
     XCD-contiguous block mapping of the flux and per-point kernels (the
     derivative passes and the local time step always use it), and the flux
     kernel's block size (64, 128, 256); results do not depend on it."""
-    block: int = 256
+    block: int = 512
     xcd_contiguous: int = 0
     flux_block: int = 64
 
