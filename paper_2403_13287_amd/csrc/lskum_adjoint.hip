@@ -1098,6 +1098,10 @@ void adjoint_reset(lskum_plan_s *p) {
 
 // Tile tables of the in-edge rows for the plan's tile size (synchronous;
 // rebuilt when the tile size changes).
+// Points per tile of the in-edge tables: the plan's tile size, at most 256
+// (the transposed gathers measured slower on 512-point tiles).
+inline int in_tile_size(const lskum_plan_s *p) { return std::min(p->block, 256); }
+
 int ensure_in_tiles(lskum_plan_s *p, void *stream) {
   InTileMap &m = p->in_map;
   if (m.blk == p->block) return LSKUM_OK;
@@ -1120,14 +1124,15 @@ int ensure_in_tiles(lskum_plan_s *p, void *stream) {
   } catch (const std::bad_alloc &) {
     return LSKUM_ERR_NO_MEMORY;
   }
-  // tiles capped at 2 blk table slots as for the forward passes' tables, and
-  // at what the first-order reverse's 88-byte slots fit in the LDS budget;
-  // fixed tiles where capping would shrink them a lot
-  const int cap = std::min(2 * p->block, (int)(kTileLdsBytes / 88) / 4 * 4);
-  rc = tile_slots(n, ki, p->block, cap, ids.data(), cnt.data(), slots, tlo, hoff, hids, hmax);
-  const int64_t fixed_tiles = ((int64_t)n + p->block - 1) / p->block;
+  // Tiles capped at 2 tile table slots as for the forward passes' tables
+  // and at what the first-order reverse's 88-byte slots fit in the LDS
+  // budget; fixed tiles where capping would shrink them a lot.
+  const int tile = in_tile_size(p);
+  const int cap = std::min(2 * tile, (int)(kTileLdsBytes / 88) / 4 * 4);
+  rc = tile_slots(n, ki, tile, cap, ids.data(), cnt.data(), slots, tlo, hoff, hids, hmax);
+  const int64_t fixed_tiles = ((int64_t)n + tile - 1) / tile;
   if (!rc && (int64_t)tlo.size() - 1 > fixed_tiles + fixed_tiles / 8 + 8)
-    rc = tile_slots(n, ki, p->block, 0, ids.data(), cnt.data(), slots, tlo, hoff, hids, hmax);
+    rc = tile_slots(n, ki, tile, 0, ids.data(), cnt.data(), slots, tlo, hoff, hids, hmax);
   if (rc) return rc;
   try {
     lent.resize(slots.size());
@@ -1216,21 +1221,18 @@ int reverse_passes(lskum_plan_s *p, const VjpWs &w, const double *U, const doubl
   // table fits the LDS budget
   const InTileMap &m = p->in_map;
   const Tiles t{nullptr, m.hoff, m.hids, m.hmax, 0, m.tlo, m.ntiles};
-  const size_t cap = (size_t)p->block + m.hmax;
+  const int tile = in_tile_size(p);
+  const size_t cap = (size_t)tile + m.hmax;
   const bool tiled = m.blk == p->block && cap * 88 <= kTileLdsBytes;
   const bool k48 = p->k_in <= 48;
   const int gr = grid_tiles(m.ntiles);
   hipStream_t st = S(stream);
 #define LSKUM_REV_T(kern, lds, ...)                                                      \
   do {                                                                                   \
-    switch (p->block) {                                                                  \
+    switch (tile) {  /* 128 or 256 */                                                    \
       case 128:                                                                          \
         if (k48) kern<128, 48><<<gr, 128, lds, st>>>(__VA_ARGS__);                       \
         else kern<128, 0><<<gr, 128, lds, st>>>(__VA_ARGS__);                            \
-        break;                                                                           \
-      case 512:                                                                          \
-        if (k48) kern<512, 48><<<gr, 512, lds, st>>>(__VA_ARGS__);                       \
-        else kern<512, 0><<<gr, 512, lds, st>>>(__VA_ARGS__);                            \
         break;                                                                           \
       default:                                                                           \
         if (k48) kern<256, 48><<<gr, 256, lds, st>>>(__VA_ARGS__);                       \
