@@ -558,8 +558,8 @@ def run_sweep(cloud, wl, steps: int, warm: int, options: int, n_inner: int,
         # the next stage's q into the other buffer (four stages bring q back
         # to qs[0]); q_vars runs only before the very first stage.  RK4 keeps
         # separate q_vars and stage launches.
+        # the first stage's launch stores U, the step's U^n, in Un
         L.lskum_local_dt(plan, U, dt)
-        Un.copy_(U)
         for s in range(4):
             qc = q if rk4 else qs[s % 2]
             if rk4 or (k == 0 and s == 0):

@@ -190,19 +190,19 @@ int lskum_flux_residual(lskum_plan plan, const double *q, const double *dq, cons
  * and the q-variables of eq. (13) of the updated state into q_next (as
  * lskum_q_vars): the stage update and eq. (13) need only the point's own
  * values, so they run as the flux kernel's epilogue instead of two more
- * passes over memory.  R, U and q_next equal those of the three separate
- * calls bit for bit.  Un, U, R and q_next are [n][4] (32-byte aligned), dt
- * is [n]; all device memory owned by the caller.  U holds the previous
- * stage on entry and the new one on return; q_next receives the q of the
- * next stage.  The three written buffers R, U and q_next must not share a
- * byte with each other or with q, dq, qlim (which other points still read
- * as neighbours), Un or dt (a point stores R before it reads its own U, Un
- * and dt).  Non-physical new states set the status word as lskum_q_vars
+ * passes over memory.  R, U, q_next and Un equal those of the three
+ * separate calls bit for bit.  Un, U, R and q_next are [n][4] (32-byte
+ * aligned), dt is [n]; all device memory owned by the caller.  U holds the
+ * previous stage on entry and the new one on return; q_next receives the q
+ * of the next stage; Un as in lskum_rk_stage (stage 0 writes it).  The
+ * written buffers R, U, q_next and Un must not share a byte with each
+ * other or with q, dq, qlim (which other points still read as neighbours)
+ * or dt (a point stores R before it reads its own U, Un and dt).  Non-physical new states set the status word as lskum_q_vars
  * does.  The stage is always SSP: the plan's LSKUM_RK4 bit is not read
  * here.  Returns LSKUM_ERR_INVALID_ARG for a null or misaligned pointer,
  * stage outside 0..3 or overlapping buffers as above. */
 int lskum_flux_residual_stage(lskum_plan plan, int stage, const double *q, const double *dq,
-                              const double *qlim, const double *Un, const double *dt, double *R,
+                              const double *qlim, double *Un, const double *dt, double *R,
                               double *U, double *q_next, void *stream);
 
 /* Local time step: dt_i = CFL * min_j |d_ij| / (|u_j| + 3 sqrt(p_j/rho_j)). */
@@ -211,8 +211,11 @@ int lskum_local_dt(lskum_plan plan, const double *U, double *dt, void *stream);
 /* Stage `stage` (0..3) of the SSP Runge-Kutta (4,3) scheme with L = -R:
  * U <- a Un + b (U - dt/2 R), (a, b) = (0, 1) except stage 2: (2/3, 1/3);
  * then wall points drop normal momentum and outer points are reset to the
- * free stream.  U holds the previous stage on entry. */
-int lskum_rk_stage(lskum_plan plan, int stage, const double *Un, const double *R,
+ * free stream.  U holds the previous stage on entry.  Un is the step's
+ * starting state: stage 0, whose incoming U is that state, stores it in Un
+ * for the later stages (so no copy is needed between steps).  U and Un
+ * must not share a byte with each other, R or dt (LSKUM_ERR_INVALID_ARG). */
+int lskum_rk_stage(lskum_plan plan, int stage, double *Un, const double *R,
                    const double *dt, double *U, void *stream);
 
 /* Stage `stage` (0..3) of the classical fourth-order Runge-Kutta scheme
@@ -222,8 +225,10 @@ int lskum_rk_stage(lskum_plan plan, int stage, const double *Un, const double *R
  * s's input.  acc ([n][4], caller-owned, 32-byte aligned) carries
  * R0 + 2 R1 + 2 R2 between the calls of one step: stage 0 overwrites it,
  * stages 1 and 2 update it, stage 3 only reads it.  Boundary conditions as
- * in lskum_rk_stage. */
-int lskum_rk4_stage(lskum_plan plan, int stage, const double *Un, const double *R,
+ * in lskum_rk_stage; Un as there (stage 0 stores its incoming U in it).  U,
+ * Un and acc must not share a byte with each other, R or dt
+ * (LSKUM_ERR_INVALID_ARG). */
+int lskum_rk4_stage(lskum_plan plan, int stage, double *Un, const double *R,
                     const double *dt, double *acc, double *U, void *stream);
 
 /* Deterministic L2 norm of the density residual over interior and wall

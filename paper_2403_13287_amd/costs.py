@@ -55,24 +55,26 @@ def flux_bytes(n_points: int, k_pad: int, stage: bool = False) -> float:
     """Flux pass: x, y, nx, ny, kind (33), q (32), dq (64), qlim (64),
     half-plane weights (64), connectivity; writes R (32).  With the SSP
     stage in its epilogue also U and dt in, U and the next q out, and U^n
-    at one stage in four (32 + 8 + 32 + 32 + 32/4 = 112)."""
+    read at one stage in four and written at another (32 + 8 + 32 + 32 +
+    32/4 + 32/4 = 120)."""
     return float(n_points) * (33 + 32 + 64 + 64 + 64 + 32 + conn_bytes(k_pad)
-                              + (112 if stage else 0))
+                              + (120 if stage else 0))
 
 
 def stage_bytes(n_points: int, k_pad: int, n_inner: int, fused: bool = True) -> float:
     """One RK stage: first-order pass (16 + 32 + 64 + 64 + C), each inner
     sweep (16 + previous derivatives 64 + first-order derivatives 64 + new
     derivatives 64 + C), the flux pass with the SSP stage in its epilogue,
-    plus the per-iteration time step and U^n copy amortised over 4 stages
-    ((16 + 32 + 8 + C + 64)/4).  Unfused (classical RK4): the plain flux
-    pass, a q-variables pass (64) and a stage update (Un, U, R, dt, kind
-    in; U out: 137) instead."""
+    plus the per-iteration time step amortised over 4 stages
+    ((16 + 32 + 8 + C)/4; U^n is stored by the first stage, not copied).
+    Unfused (classical RK4): the plain flux pass, a q-variables pass (64)
+    and a stage update (Un, U, R, dt, kind in; U out; U^n out at one stage
+    in four: 137 + 8) instead."""
     c = conn_bytes(k_pad)
     flux = flux_bytes(1, k_pad, stage=fused)
-    per = (176 + c) + n_inner * (208 + c) + flux + (120 + c) / 4.0
+    per = (176 + c) + n_inner * (208 + c) + flux + (56 + c) / 4.0
     if not fused:
-        per += 64 + 137
+        per += 64 + 145
     return float(n_points) * per
 
 

@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(kBlock) k_split_weights(Geo G, double *__restr
 // local time step, Runge-Kutta stage, initial state
 
 __global__ void __launch_bounds__(kBlock) k_rk_stage(Geo G, Flow P, int stage,
-                                                     const double *__restrict__ Un,
+                                                     double *__restrict__ Un,
                                                      const double *__restrict__ R,
                                                      const double *__restrict__ dt,
                                                      double *__restrict__ U) {
@@ -111,8 +111,10 @@ __global__ void __launch_bounds__(kBlock) k_rk_stage(Geo G, Flow P, int stage,
   const int i = point_index<kBlock>(G.xcd);
   if (i >= n) return;
   const int kind = G.kind[i];
+  const F4 Uc = ld4(U, i);
+  if (stage == 0) st4(Un, i, Uc);  // the step's U^n, for the third stage
   const F4 Ui = kind == 2 ? ld4(G.uinf, G.cloud[i])
-                          : ssp_stage(G, i, kind, stage, Un, ld4(U, i), ld4(R, i), dt[i]);
+                          : ssp_stage(G, i, kind, stage, Un, Uc, ld4(R, i), dt[i]);
   st4(U, i, Ui);
 }
 
@@ -120,7 +122,7 @@ __global__ void __launch_bounds__(kBlock) k_rk_stage(Geo G, Flow P, int stage,
 // Un - dt/2 R1, Un - dt R2 and the step ends at Un - dt/6 (R0 + 2 R1 + 2 R2 + R3).
 // acc carries the partial weighted sum of the stage residuals.
 __global__ void __launch_bounds__(kBlock) k_rk4_stage(Geo G, Flow P, int stage,
-                                                      const double *__restrict__ Un,
+                                                      double *__restrict__ Un,
                                                       const double *__restrict__ R,
                                                       const double *__restrict__ dt,
                                                       double *__restrict__ acc,
@@ -129,11 +131,14 @@ __global__ void __launch_bounds__(kBlock) k_rk4_stage(Geo G, Flow P, int stage,
   const int i = point_index<kBlock>(G.xcd);
   if (i >= n) return;
   const int kind = G.kind[i];
+  // stage 0: the incoming U is the step's U^n, which the later stages read
+  const F4 U0 = stage == 0 ? ld4(U, i) : ld4(Un, i);
+  if (stage == 0) st4(Un, i, U0);
   F4 Ui;
   if (kind == 2) {
     Ui = ld4(G.uinf, G.cloud[i]);
   } else {
-    const F4 U0 = ld4(Un, i), Ri = ld4(R, i);
+    const F4 Ri = ld4(R, i);
     F4 A;
     if (stage == 0) {
       A = Ri;
@@ -174,12 +179,6 @@ __global__ void __launch_bounds__(kBlock) k_far_field(Geo G, double *__restrict_
   const int i = point_index<kBlock>(G.xcd);
   if (i >= G.n || G.kind[i] != 2) return;
   st4(U, i, ld4(G.uinf, G.cloud[i]));
-}
-
-__global__ void k_copy(size_t count, const double *__restrict__ src, double *__restrict__ dst) {
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += stride)
-    dst[k] = src[k];
 }
 
 // Residual norms per cloud.  Each cloud's points are cut into fixed chunks
@@ -578,11 +577,10 @@ int run_iterations(lskum_plan_s *p, int32_t iters, double *U, double *hist, int3
   const Geo g = geo(p);
   const Flow f = flow(p);
   const int grid = grid_for(p->n);
-  const int copy_grid = grid_for((int)std::min<size_t>(4 * n, (size_t)1 << 24));
   int rc;
   for (int32_t it = 0; it < iters; ++it) {
+    // (the first stage's launch stores U, the step's U^n, in Un)
     if ((rc = local_dt_launch(p, U, dt, stream))) return rc;
-    k_copy<<<copy_grid, kBlock, 0, S(stream)>>>(4 * n, U, Un);
     for (int s = 0; s < 4; ++s) {
       // SSP stages run fused into the flux launch, which also writes the
       // next stage's q (ping-pong buffers); q_vars only starts the sequence
@@ -896,17 +894,17 @@ int lskum_flux_residual(lskum_plan p, const double *q, const double *dq, const d
 }
 
 int lskum_flux_residual_stage(lskum_plan p, int stage, const double *q, const double *dq,
-                              const double *qlim, const double *Un, const double *dt, double *R,
+                              const double *qlim, double *Un, const double *dt, double *R,
                               double *U, double *q_next, void *stream) {
   if (!p || !a32(q) || !a64(dq) || !a64(qlim) || !a32(R) || !a32(Un) || !dt || !a32(U) ||
       !a32(q_next) || stage < 0 || stage > 3)
     return LSKUM_ERR_INVALID_ARG;
-  // other points read q, dq and qlim as neighbours while R, U and q_next are
-  // written; a point stores R before it reads its own U, Un and dt
+  // other points read q, dq and qlim as neighbours while R, U, q_next (and
+  // at stage 0 Un) are written; a point stores R before it reads its own U,
+  // Un and dt
   const size_t n = (size_t)p->n;
-  if (!writes_disjoint({Span{R, 32 * n}, Span{U, 32 * n}, Span{q_next, 32 * n}},
-                       {Span{q, 32 * n}, Span{dq, 64 * n}, Span{qlim, 64 * n}, Span{Un, 32 * n},
-                        Span{dt, 8 * n}}))
+  if (!writes_disjoint({Span{R, 32 * n}, Span{U, 32 * n}, Span{q_next, 32 * n}, Span{Un, 32 * n}},
+                       {Span{q, 32 * n}, Span{dq, 64 * n}, Span{qlim, 64 * n}, Span{dt, 8 * n}}))
     return LSKUM_ERR_INVALID_ARG;
   const StageArgs sa{stage, Un, dt, U, q_next};
   return flux_launch(p, q, dq, qlim, R, stream, &sa);
@@ -917,17 +915,24 @@ int lskum_local_dt(lskum_plan p, const double *U, double *dt, void *stream) {
   return local_dt_launch(p, U, dt, stream);
 }
 
-int lskum_rk_stage(lskum_plan p, int stage, const double *Un, const double *R, const double *dt,
+int lskum_rk_stage(lskum_plan p, int stage, double *Un, const double *R, const double *dt,
                    double *U, void *stream) {
   if (!p || !a32(Un) || !a32(R) || !dt || !a32(U) || stage < 0 || stage > 3)
+    return LSKUM_ERR_INVALID_ARG;
+  const size_t n = (size_t)p->n;
+  if (!writes_disjoint({Span{U, 32 * n}, Span{Un, 32 * n}}, {Span{R, 32 * n}, Span{dt, 8 * n}}))
     return LSKUM_ERR_INVALID_ARG;
   k_rk_stage<<<grid_for(p->n), kBlock, 0, S(stream)>>>(geo(p), flow(p), stage, Un, R, dt, U);
   return launched();
 }
 
-int lskum_rk4_stage(lskum_plan p, int stage, const double *Un, const double *R, const double *dt,
+int lskum_rk4_stage(lskum_plan p, int stage, double *Un, const double *R, const double *dt,
                     double *acc, double *U, void *stream) {
   if (!p || !a32(Un) || !a32(R) || !dt || !a32(acc) || !a32(U) || stage < 0 || stage > 3)
+    return LSKUM_ERR_INVALID_ARG;
+  const size_t n = (size_t)p->n;
+  if (!writes_disjoint({Span{U, 32 * n}, Span{Un, 32 * n}, Span{acc, 32 * n}},
+                       {Span{R, 32 * n}, Span{dt, 8 * n}}))
     return LSKUM_ERR_INVALID_ARG;
   k_rk4_stage<<<grid_for(p->n), kBlock, 0, S(stream)>>>(geo(p), flow(p), stage, Un, R, dt, acc,
                                                         U);

@@ -80,7 +80,9 @@ __global__ void __launch_bounds__(BLK) k_flux(Geo G, Flow P, const double *__res
   auto finish = [&](const F4 &r, unsigned f) {
     st4(R, i, r);
     if (FUSE) {
-      const F4 Ui = ssp_stage(G, i, kind, S.stage, S.Un, ld4(S.U, i), r, S.dt[i]);
+      const F4 Uc = ld4(S.U, i);
+      if (S.stage == 0) st4(S.Un, i, Uc);
+      const F4 Ui = ssp_stage(G, i, kind, S.stage, S.Un, Uc, r, S.dt[i]);
       st4(S.U, i, Ui);
       F4 qn;
       f |= q_of_state(P, Ui, qn);

@@ -190,10 +190,11 @@ __device__ __forceinline__ F4 ssp_stage(const Geo &G, int i, int kind, int stage
 
 // The stage update a flux launch may apply right after a point's residual
 // (stage >= 0): U <- ssp_stage(U), and q_next <- the q-variables of the new
-// state (a buffer other than the q the flux reads).
+// state (a buffer other than the q the flux reads).  Stage 0 also stores the
+// incoming U, the step's U^n, in Un for the third stage.
 struct StageArgs {
   int stage;
-  const double *Un;
+  double *Un;
   const double *dt;
   double *U;
   double *q_next;

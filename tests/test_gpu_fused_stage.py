@@ -23,9 +23,13 @@ def say(*a):
 
 
 def _run_both(plan, U0):
-    """Both paths through the four stages of one iteration from U0."""
+    """Both paths through the four stages of one iteration from U0.  Each
+    path has its own U^n buffer, NaN on entry: its stage 0 must store U0
+    there for the third stage."""
     dq, qlim, work = plan.field(8), plan.field(8), plan.field(16)
-    Un, dt = U0.clone(), plan.field(1)
+    Una = torch.full_like(U0, float("nan"))
+    Unb = torch.full_like(U0, float("nan"))
+    dt = plan.field(1)
     L.lskum_local_dt(plan, U0, dt)
     Ua, Ub = U0.clone(), U0.clone()
     Ra, Rb = plan.field(4), plan.field(4)
@@ -37,13 +41,15 @@ def _run_both(plan, U0):
         # separate launches
         L.lskum_q_derivs(plan, qa, dq, qlim, work)
         L.lskum_flux_residual(plan, qa, dq, qlim, Ra)
-        L.lskum_rk_stage(plan, s, Un, Ra, dt, Ua)
+        L.lskum_rk_stage(plan, s, Una, Ra, dt, Ua)
         L.lskum_q_vars(plan, Ua, qa)
         # fused
         L.lskum_q_derivs(plan, qb, dq, qlim, work)
         qnext.fill_(float("nan"))
-        L.lskum_flux_residual_stage(plan, s, qb, dq, qlim, Un, dt, Rb, Ub, qnext)
+        L.lskum_flux_residual_stage(plan, s, qb, dq, qlim, Unb, dt, Rb, Ub, qnext)
         torch.cuda.synchronize()
+        if s == 0:
+            assert torch.equal(Una, U0) and torch.equal(Unb, U0), "U^n stored by stage 0"
         assert torch.equal(Ra, Rb), f"R at stage {s}"
         assert torch.equal(Ua, Ub), f"U at stage {s}"
         assert torch.equal(qa, qnext), f"q_next at stage {s}"
@@ -118,6 +124,22 @@ def test_fused_stage_rejects_aliased_buffers():
         L.ERR_INVALID_ARG
     assert lib.lskum_flux_residual_stage(plan.handle, 0, *args, R.data_ptr(), None) == \
         L.ERR_INVALID_ARG
+    # Un (written at stage 0) on a buffer other points read, or on U
+    for Un_bad in (q, dq, qlim, U):
+        bad = list(args)
+        bad[3] = Un_bad.data_ptr()
+        assert lib.lskum_flux_residual_stage(plan.handle, 0, *bad, qn_ok, None) == \
+            L.ERR_INVALID_ARG
+    # the stage updates alone: U, Un (and acc) distinct and off R and dt
+    acc = plan.field(4)
+    assert lib.lskum_rk_stage(plan.handle, 0, U.data_ptr(), R.data_ptr(), dt.data_ptr(),
+                              U.data_ptr(), None) == L.ERR_INVALID_ARG
+    assert lib.lskum_rk_stage(plan.handle, 0, Un.data_ptr(), R.data_ptr(), dt.data_ptr(),
+                              R.data_ptr(), None) == L.ERR_INVALID_ARG
+    assert lib.lskum_rk4_stage(plan.handle, 0, Un.data_ptr(), R.data_ptr(), dt.data_ptr(),
+                               Un.data_ptr(), U.data_ptr(), None) == L.ERR_INVALID_ARG
+    assert lib.lskum_rk4_stage(plan.handle, 0, Un.data_ptr(), R.data_ptr(), dt.data_ptr(),
+                               acc.data_ptr(), R.data_ptr(), None) == L.ERR_INVALID_ARG
     # the plain flux residual and the derivative passes check their outputs too
     assert lib.lskum_flux_residual(plan.handle, q.data_ptr(), dq.data_ptr(), qlim.data_ptr(),
                                    dq.data_ptr(), None) == L.ERR_INVALID_ARG
